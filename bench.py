@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Benchmark: one step = one pass of the whole hot path (scan -> pair -> Tm ->
+extract) over the genome-scale synthetic workload (2,000 sequences of 3-6 Mb,
+~9 Gbases, one degenerate primer pair, k=3, clamp 5, all four orientations,
+FP64 Tm filter at 45 C), genome resident in HBM.
+
+Prints one JSON line.  value = whole-job Gbases scanned per second (one pair:
+Gbases/s = pair-Gbases/s).  The dominant kernel (the primer scan) is timed
+with HIP events on its own stream inside the timed region and reported
+against the HBM roofline; the CPU oracle is timed on a bounded sample of the
+same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+BYTES_PER_BASE = 0.25   # 2-bit store
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, help="workload (2 = genome scale)")
+    ap.add_argument("--n-seqs", type=int, default=None, help="shrink the workload (testing)")
+    ap.add_argument("--len-scale", type=float, default=1.0, help="shrink the workload (testing)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-bases", type=float, default=1.0e9)
+    ap.add_argument("--stages", default="scan,pair,tm,extract")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def traffic_from_profiles(kernel_src_hash):
+    """HBM bytes per scan launch from committed rocprofv3 counter runs, if they
+    were taken on the current scan kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "scan_genome_counters.json")
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("scan_src_sha256") != kernel_src_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus %d is not supported (use --gpus 1)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import hashlib
+
+    import numpy as np
+    import torch
+
+    from paper_2511_00170_amd import ah, synth
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    wl = synth.gen_config(args.config, n_seqs=args.n_seqs, len_scale=args.len_scale)
+    total = wl.total_bases
+    log("workload %s: %d sequences, %.3f Gbases" % (wl.name, wl.n_seqs, total / 1e9))
+    sample = None
+    sample_goal = args.cpu_sample_bases
+
+    def chunks():
+        nonlocal sample
+        for first, buf, off in wl.chunks(1 << 30):
+            if sample is None and not args.no_cpu_baseline:
+                # bounded oracle sample: the leading sequences of the first chunk
+                m = int(np.searchsorted(off, sample_goal, side="right"))
+                m = max(1, min(m, len(off) - 1))
+                sample = (buf[:int(off[m])].copy(), off[:m + 1].copy(), m)
+            yield first, buf, off
+
+    store = ah.Store(wl.lengths)
+    store.pack_chunks(chunks())
+    log("generated + packed in %.1f s (store %.2f GB)" % (time.time() - t0, store.hbm_bytes / 1e9))
+
+    ps = ah.PrimerSet(wl.pairs)
+    ex = synth.ExtractSpec(trim=wl.extract.trim, fb_len=wl.extract.fb_len, rb_len=wl.extract.rb_len)
+    stream = torch.cuda.Stream()
+    stages = tuple(args.stages.split(","))
+    with torch.cuda.stream(stream):
+        pipe = ah.Pipeline(store, ps, wl.orient_mask, wl.tm, ex)
+        pipe.run(stream)                        # sizes the capacities (exact re-run on overflow)
+        n_hits, n_amps, n_bytes = pipe.counts()
+        log("hits %d amplicons %d pass %d bytes %d" % (n_hits, n_amps, int(pipe.passed[:n_amps].sum().item()),
+                                                      n_bytes))
+        for _ in range(args.warmup):
+            pipe.launch(stream, stages)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        t_start = time.perf_counter()
+        for i in range(args.steps):
+            ev[i][0].record(stream)
+            pipe.launch(stream, ("scan",))
+            ev[i][1].record(stream)
+            pipe.launch(stream, tuple(s for s in stages if s != "scan"))
+        torch.cuda.synchronize()
+        t_end = time.perf_counter()
+    ms_step = (t_end - t_start) * 1e3 / args.steps
+    scan_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    gbases_s = total / (ms_step / 1e3) / 1e9
+    alg_bytes = BYTES_PER_BASE * total + 12.0 * n_hits
+    achieved = alg_bytes / (scan_ms / 1e3) / 1e9
+    src = open(os.path.join(ROOT, "paper_2511_00170_amd", "csrc", "scan.hip"), "rb").read()
+    traffic = traffic_from_profiles(hashlib.sha256(src).hexdigest())
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "ah_scan_kernel", "kernel_ms": round(scan_ms, 4),
+            "algorithmic_bytes_per_launch": int(alg_bytes)}
+
+    cpu = None
+    if sample is not None:
+        import oracle
+        buf, off, m = sample
+        nt = os.cpu_count() or 1
+        tc = time.perf_counter()
+        o = oracle.run(buf, off, wl.pairs, wl.orient_mask, wl.tm, ex, n_threads=nt)
+        dt = time.perf_counter() - tc
+        sb = int(off[-1])
+        cpu = {"value": round(sb / dt / 1e9, 4), "unit": "Gbases/s", "cores": nt, "kind": "oracle",
+               "sample": "first %d sequences (%.3f Gbases) of the workload, scan+pair+Tm+extract, %.1f s"
+                         % (m, sb / 1e9, dt)}
+        log("oracle sample: %d amplicons in %.1f s" % (len(o.amps), dt))
+
+    out = {
+        "metric": "Gbases scanned/s per primer pair (k mm) + % HBM peak; batched vs plain; p50/p99 latency",
+        "value": round(gbases_s, 2),
+        "unit": "Gbases/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/f64",
+        "data": "synthetic",
+        "config": {"workload": "genome: %d seqs x 3-6 Mb, %.2f Gbases, 1 pair (19/21 nt, D=16/32), k=%d, clamp %d, "
+                               "FR/RF/FF/RR, window 200-2000, FP64 Tm filter >= 45 C"
+                               % (wl.n_seqs, total / 1e9, wl.pairs[0].k, wl.pairs[0].clamp),
+                   "pairs": len(wl.pairs), "k": wl.pairs[0].k, "bases": total, "stages": list(stages),
+                   "hits": n_hits, "amplicons": n_amps},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,246 @@
+/*
+ * ah.h -- C ABI of libah.so, an MI355X (gfx950) implementation of the
+ * in-silico PCR hot path of AmpliconHunter2 (Howard-Stone & Mandoiu,
+ * arXiv 2511.00170): scan 2-bit genomes for IUPAC-degenerate primers with at
+ * most k substitutions and an exact 3' clamp, pair the hits into FR/RF/FF/RR
+ * amplicons inside a length window, compute the nearest-neighbour melting
+ * temperature, trim primers and cut flanking barcodes.
+ *
+ * Conventions (every entry point):
+ *  - Plain C.  `d_` pointers are device memory owned by the caller; `h_`
+ *    pointers are host memory.  No entry point allocates device memory except
+ *    ah_primers_compile (a one-time set-up call) and none synchronises the
+ *    host, so the calls can be captured into a HIP graph.
+ *  - `stream` is a hipStream_t (NULL = the null stream); work is enqueued
+ *    asynchronously on it.
+ *  - Argument errors are returned synchronously and leave outputs untouched.
+ *  - Capacity overflow is not an error at call time: a kernel writes at most
+ *    `cap` records and always stores the true count in its device counter;
+ *    the caller compares after synchronising and re-runs with a larger cap.
+ *    Every output is deterministic, so a re-run is exact.
+ *  - Coordinates are 0-based, half-open, on the plus strand of the sequence.
+ */
+#ifndef AH_H
+#define AH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ah_status;
+#define AH_OK 0
+#define AH_E_ARG 1       /* null pointer, zero size where one is needed, bad enum */
+#define AH_E_ALPHABET 2  /* a primer letter outside the 15 IUPAC codes (U reads as T) */
+#define AH_E_LIMIT 3     /* primer length outside 1..32, clamp > length, too many pairs, key too wide */
+#define AH_E_HIP 4       /* a HIP runtime call failed */
+#define AH_E_WORKSPACE 5 /* workspace smaller than the matching *_ws_size() */
+
+/* Human-readable name of a status code (static string). */
+const char *ah_status_str(ah_status s);
+int ah_version(void);
+
+/* ------------------------------------------------------------------------
+ * 2-bit genome store (the paper's 2-bit batches: Implementations, AHv2.alpha
+ * paragraph; 2-bit files read ~3.93x fewer bytes than FASTA, Results).
+ *
+ * Every sequence starts on a 64-base block.  Block b holds four 32-bit words
+ * {hi[0:32], lo[0:32], hi[32:64], lo[32:64]}: bit i of hi/lo is the high/low
+ * bit of base i of the block with A=00, C=01, G=10, T=11 (the complement of a
+ * code is code XOR 3).  Bases past a sequence end are stored as A and never
+ * read as sequence.  A byte that is not A/C/G/T (either case) is an N: it is
+ * stored as A and flagged in a side table -- d_nbits has one bit per block
+ * ("this block holds an N"), d_nrank the number of flagged blocks before each
+ * 32-block word, d_nmask one 64-bit mask of N positions per flagged block, in
+ * block order.  16 bytes per 64 bases = 0.25 B/base in HBM.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    uint32_t n_seqs;
+    uint32_t max_len;        /* longest sequence, bases */
+    uint64_t n_blocks;       /* total 64-base blocks */
+    uint32_t *d_blocks;      /* [n_blocks][4] */
+    uint64_t *d_seq_block0;  /* [n_seqs] first block of each sequence */
+    uint32_t *d_seq_len;     /* [n_seqs] length in bases */
+    uint32_t *d_nbits;       /* [ceil(n_blocks/32)] */
+    uint32_t *d_nrank;       /* [ceil(n_blocks/32)] */
+    uint64_t *d_nmask;       /* [nmask_cap] */
+    uint64_t nmask_cap;
+    uint64_t *d_counters;    /* [AH_STORE_SCRATCH] library scratch; [0] = number of flagged blocks */
+} ah_store;
+
+#define AH_STORE_SCRATCH 2048
+
+/* Host: block layout of sequences with the given lengths.  Writes
+ * h_seq_block0[n_seqs] and *h_n_blocks.  Lengths must be < 2^32. */
+ah_status ah_pack_layout(const uint64_t *h_lens, uint32_t n_seqs, uint64_t *h_seq_block0, uint64_t *h_n_blocks);
+
+/* Clear the N side table and counters of a store before packing into it. */
+ah_status ah_pack_begin(const ah_store *st, void *stream);
+
+/* Pack sequences [first_seq, first_seq + n) whose ASCII bytes are at
+ * d_ascii + d_ascii_off[i - first_seq] (d_ascii_off has n + 1 entries,
+ * relative to d_ascii; the lengths must equal d_seq_len).  Blocks holding an
+ * N are also appended as (block, mask) pairs to d_nlist ([2 * nlist_cap]
+ * u64; count in st->d_counters[0]).  May be called for several chunks. */
+ah_status ah_pack(const ah_store *st, const uint8_t *d_ascii, const uint64_t *d_ascii_off, uint32_t first_seq,
+                  uint32_t n, uint64_t *d_nlist, uint64_t nlist_cap, void *stream);
+
+/* After the last ah_pack: build d_nrank and place the N masks in block order.
+ * If more blocks were flagged than nlist_cap / nmask_cap allow, the count in
+ * st->d_counters[0] says so and the pack must be redone with larger caps. */
+ah_status ah_pack_finish(const ah_store *st, const uint64_t *d_nlist, uint64_t nlist_cap, void *stream);
+
+/* Decode bases [start, start + n) of sequence `seq` to ASCII (A/C/G/T/N). */
+ah_status ah_unpack(const ah_store *st, uint32_t seq, uint64_t start, uint64_t n, uint8_t *d_out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Primer sets (Supplementary, "Primer matching and clamp logic": primers are
+ * compiled into per-base IUPAC masks, reverse-complement masks precomputed).
+ * Each pair has its own k (substitutions allowed, inclusive), clamp (number
+ * of 3'-terminal primer positions that must match exactly; 0 disables it)
+ * and amplicon length window [min_len, max_len] (primers included).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const char *fwd;  /* 5'->3', IUPAC, 1..32 letters */
+    const char *rev;  /* 5'->3', IUPAC, 1..32 letters */
+    uint32_t k;
+    uint32_t clamp;
+    uint32_t min_len;
+    uint32_t max_len;
+} ah_pair_spec;
+
+typedef struct ah_primer_set_ *ah_primer_set;
+
+/* Validate and compile pairs (at most AH_MAX_PAIRS).  Allocates a small
+ * device table (owned by the handle).  Errors: AH_E_ALPHABET, AH_E_LIMIT. */
+#define AH_MAX_PAIRS 4096
+ah_status ah_primers_compile(const ah_pair_spec *h_pairs, uint32_t n_pairs, ah_primer_set *out);
+void ah_primers_free(ah_primer_set ps);
+uint32_t ah_primers_count(ah_primer_set ps);
+
+/* ------------------------------------------------------------------------
+ * Scan (Supplementary, "Primer matching and clamp logic"; mismatches are
+ * substitutions, Results "Primer degeneracy and mismatch tolerance").
+ * For each sequence s, pair q, primer P in {F, R}, strand: the pattern is
+ * X = P (plus) or X = rc(P) (minus); position p in [0, len - |X|] is a hit
+ * iff every clamp position matches -- the last `clamp` positions of X on the
+ * plus strand, the first `clamp` positions of X on the minus strand (the
+ * primer's 3' end) -- and mm = #{j : s[p+j] not in X[j]} <= k.  An N matches
+ * nothing.  Hits are written in arbitrary order.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    uint32_t seq;   /* store index */
+    uint32_t pos;   /* window start on the plus strand */
+    uint16_t pair;  /* pair index in the primer set */
+    uint8_t kind;   /* bit0: reverse primer; bit1: minus strand (site of rc(primer)) */
+    uint8_t mm;     /* substitutions */
+} ah_hit;           /* 12 bytes */
+
+/* Workspace bytes for ah_scan_primers over n_list sequences (all: n_seqs). */
+ah_status ah_scan_ws_size(const ah_store *st, uint32_t n_list, uint64_t *bytes);
+
+/* d_seq_subset: NULL for every sequence, else n_subset store indices.
+ * Writes min(total, hit_cap) hits; *d_n_hits = total (the call resets it). */
+ah_status ah_scan_primers(const ah_store *st, ah_primer_set ps, const uint32_t *d_seq_subset, uint32_t n_subset,
+                          ah_hit *d_hits, uint64_t hit_cap, uint64_t *d_n_hits, void *d_ws, uint64_t ws_bytes,
+                          void *stream);
+
+/* ------------------------------------------------------------------------
+ * Pair (Supplementary, "Amplicon calling and orientation").  Per (sequence,
+ * pair) the sites are sorted by (start, end, plus before minus, forward
+ * before reverse).  A plus site a pairs with every later minus site t before
+ * the next plus site when min_len <= t.end - a.start <= max_len and the
+ * orientation is requested: FR (a forward, t reverse) = 1, RF = 2, FF = 4,
+ * RR = 8 in orient_mask.  Output order: (seq, pair, then the downstream
+ * site's sort key), which is deterministic.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    uint32_t seq;
+    uint32_t start;  /* start of the upstream (plus) site */
+    uint32_t end;    /* end of the downstream (minus) site */
+    uint16_t pair;
+    uint8_t orient;  /* 0 FR, 1 RF, 2 FF, 3 RR */
+    uint8_t flags;   /* reserved, 0 */
+} ah_amp;            /* 16 bytes */
+
+#define AH_ORIENT_FR 1u
+#define AH_ORIENT_RF 2u
+#define AH_ORIENT_FF 4u
+#define AH_ORIENT_RR 8u
+
+ah_status ah_pair_ws_size(const ah_store *st, ah_primer_set ps, uint64_t hit_cap, uint64_t *bytes);
+
+/* Reads min(*d_n_hits, hit_cap) hits (d_hits is left unchanged).  Writes
+ * min(total, amp_cap) amplicons, *d_n_amps = total. */
+ah_status ah_pair_amplicons(const ah_store *st, ah_primer_set ps, const ah_hit *d_hits, const uint64_t *d_n_hits,
+                            uint64_t hit_cap, uint32_t orient_mask, ah_amp *d_amps, uint64_t amp_cap,
+                            uint64_t *d_n_amps, void *d_ws, uint64_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Nearest-neighbour melting temperature (Implementations, "AHv2": the model
+ * of Biopython's Tm_NN).  Per amplicon, each of its two sites gets the
+ * maximum over the concrete variants of its primer of the duplex Tm of
+ * (variant 5'->3', genome strand it anneals to); the amplicon Tm is the
+ * smaller site Tm; pass = Tm >= threshold_C (or 1 when filter == 0).  FP64.
+ * Stacks: Watson-Crick (SantaLucia 1998), internal single mismatches
+ * (Allawi & SantaLucia 1997/1998, Peyret et al. 1999), terminal mismatches
+ * (Bommarito et al. 2000).  A variant with a stack none of them covers is
+ * skipped; a site with no usable variant has Tm = -inf.
+ * saltcorr: 0 none, 5 = SantaLucia 1998 entropy correction
+ * dS += 0.368 (N-1) ln[Na+eq] with [Na+eq] = Na + K + Tris/2 + 120 sqrt(Mg -
+ * dNTPs) mM (the last term only when Mg > dNTPs).  Strand concentration
+ * C = C_high - C_low / 2.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double na_mM, k_mM, tris_mM, mg_mM, dntps_mM;
+    double dnac1_nM, dnac2_nM;
+    double threshold_C;
+    int32_t saltcorr;
+    int32_t filter;
+} ah_tm_params;
+
+/* d_tm[n], d_tm_site[n][2] (upstream, downstream), d_pass[n]; n = min(*d_n_amps, amp_cap). */
+ah_status ah_tm_nn(const ah_store *st, ah_primer_set ps, const ah_amp *d_amps, const uint64_t *d_n_amps,
+                   uint64_t amp_cap, const ah_tm_params *p, double *d_tm, double *d_tm_site, uint8_t *d_pass,
+                   void *stream);
+
+/* Tm of n explicit duplexes: d_seq and d_cseq hold n rows of `stride` bytes
+ * (seq 5'->3'; cseq its partner written 3'->5'), d_len[i] <= 32 letters.
+ * Writes d_tm[i] (NaN when a stack is not tabulated or a letter is not ACGT). */
+ah_status ah_tm_duplex(const char *d_seq, const char *d_cseq, const uint32_t *d_len, uint32_t n, uint32_t stride,
+                       const ah_tm_params *p, double *d_tm, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Extract (Supplementary, "Primer trimming and barcode extraction" and
+ * "Headers and outputs").  FR/FF/RR amplicons are s[start:end]; RF ones are
+ * reverse-complemented (Supplementary, "Amplicon calling and orientation").
+ * trim removes both primer sites.  fb = the fb_len bases upstream of the
+ * forward site and rb = the rb_len bases downstream of the reverse site (FR,
+ * FF, RR); for RF the opposite sides, both reverse-complemented.  Barcodes
+ * are clipped at sequence ends (real lengths in d_bc_len[n][2]).
+ * fprimer/rprimer: the genome bases under the forward/reverse site in that
+ * primer's orientation (FF/RR: upstream / downstream site), NUL-padded to 32.
+ * Amplicons with d_pass[i] == 0 (d_pass may be NULL) produce nothing.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    uint32_t trim;
+    uint32_t fb_len;  /* <= 255 */
+    uint32_t rb_len;  /* <= 255 */
+} ah_extract_opts;
+
+ah_status ah_extract_ws_size(uint64_t amp_cap, uint64_t *bytes);
+
+/* d_seq_off has amp_cap + 1 entries; d_fb [n][fb_len], d_rb [n][rb_len],
+ * d_fprimer/d_rprimer [n][32]; *d_n_bytes = total sequence bytes (bytes past
+ * seq_cap are not written). */
+ah_status ah_extract(const ah_store *st, ah_primer_set ps, const ah_amp *d_amps, const uint64_t *d_n_amps,
+                     uint64_t amp_cap, const uint8_t *d_pass, const ah_extract_opts *o, char *d_seq, uint64_t seq_cap,
+                     uint64_t *d_seq_off, char *d_fb, char *d_rb, uint8_t *d_bc_len, char *d_fprimer,
+                     char *d_rprimer, uint64_t *d_n_bytes, void *d_ws, uint64_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AH_H */

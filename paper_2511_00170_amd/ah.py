@@ -1,0 +1,430 @@
+"""Thin Python binding of libah.so (ctypes).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+libah.so.  PyTorch provides device memory and streams.  If the library has
+not been built this module raises at import time -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libah.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libah.so is not built (run `python -m paper_2511_00170_amd.build`): %s" % LIB_PATH)
+
+_lib = C.CDLL(LIB_PATH)
+
+AH_OK, AH_E_ARG, AH_E_ALPHABET, AH_E_LIMIT, AH_E_HIP, AH_E_WORKSPACE = 0, 1, 2, 3, 4, 5
+AH_STORE_SCRATCH = 2048
+ORIENT_ALL = 0xF
+
+VP = C.c_void_p
+U32, U64, I32 = C.c_uint32, C.c_uint64, C.c_int32
+
+
+class AhError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.ah_status_str(status).decode()
+        super().__init__("%s: %s (status %d)" % (where, msg, status))
+        self.status = status
+
+
+class ah_store(C.Structure):
+    _fields_ = [("n_seqs", U32), ("max_len", U32), ("n_blocks", U64),
+                ("d_blocks", VP), ("d_seq_block0", VP), ("d_seq_len", VP),
+                ("d_nbits", VP), ("d_nrank", VP), ("d_nmask", VP), ("nmask_cap", U64),
+                ("d_counters", VP)]
+
+
+class ah_pair_spec(C.Structure):
+    _fields_ = [("fwd", C.c_char_p), ("rev", C.c_char_p), ("k", U32), ("clamp", U32),
+                ("min_len", U32), ("max_len", U32)]
+
+
+class ah_tm_params(C.Structure):
+    _fields_ = [("na_mM", C.c_double), ("k_mM", C.c_double), ("tris_mM", C.c_double), ("mg_mM", C.c_double),
+                ("dntps_mM", C.c_double), ("dnac1_nM", C.c_double), ("dnac2_nM", C.c_double),
+                ("threshold_C", C.c_double), ("saltcorr", I32), ("filter", I32)]
+
+
+class ah_extract_opts(C.Structure):
+    _fields_ = [("trim", U32), ("fb_len", U32), ("rb_len", U32)]
+
+
+def _sig(name, restype, *args):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = list(args)
+    return f
+
+
+_lib.ah_status_str.restype = C.c_char_p
+_lib.ah_status_str.argtypes = [I32]
+_sig("ah_version", C.c_int)
+_sig("ah_pack_layout", I32, VP, U32, VP, C.POINTER(U64))
+_sig("ah_pack_begin", I32, C.POINTER(ah_store), VP)
+_sig("ah_pack", I32, C.POINTER(ah_store), VP, VP, U32, U32, VP, U64, VP)
+_sig("ah_pack_finish", I32, C.POINTER(ah_store), VP, U64, VP)
+_sig("ah_unpack", I32, C.POINTER(ah_store), U32, U64, U64, VP, VP)
+_sig("ah_primers_compile", I32, C.POINTER(ah_pair_spec), U32, C.POINTER(VP))
+_sig("ah_primers_free", None, VP)
+_sig("ah_primers_count", U32, VP)
+_sig("ah_scan_ws_size", I32, C.POINTER(ah_store), U32, C.POINTER(U64))
+_sig("ah_scan_primers", I32, C.POINTER(ah_store), VP, VP, U32, VP, U64, VP, VP, U64, VP)
+_sig("ah_pair_ws_size", I32, C.POINTER(ah_store), VP, U64, C.POINTER(U64))
+_sig("ah_pair_amplicons", I32, C.POINTER(ah_store), VP, VP, VP, U64, U32, VP, U64, VP, VP, U64, VP)
+_sig("ah_tm_nn", I32, C.POINTER(ah_store), VP, VP, VP, U64, C.POINTER(ah_tm_params), VP, VP, VP, VP)
+_sig("ah_tm_duplex", I32, VP, VP, VP, U32, U32, C.POINTER(ah_tm_params), VP, VP)
+_sig("ah_extract_ws_size", I32, U64, C.POINTER(U64))
+_sig("ah_extract", I32, C.POINTER(ah_store), VP, VP, VP, U64, VP, C.POINTER(ah_extract_opts), VP, U64, VP, VP, VP,
+     VP, VP, VP, VP, VP, U64, VP)
+
+EXPORTED = ["ah_status_str", "ah_version", "ah_pack_layout", "ah_pack_begin", "ah_pack", "ah_pack_finish",
+            "ah_unpack", "ah_primers_compile", "ah_primers_free", "ah_primers_count", "ah_scan_ws_size",
+            "ah_scan_primers", "ah_pair_ws_size", "ah_pair_amplicons", "ah_tm_nn", "ah_tm_duplex",
+            "ah_extract_ws_size", "ah_extract"]
+
+HIT_DTYPE = np.dtype([("seq", "<u4"), ("pos", "<u4"), ("pair", "<u2"), ("kind", "u1"), ("mm", "u1")])
+AMP_DTYPE = np.dtype([("seq", "<u4"), ("start", "<u4"), ("end", "<u4"), ("pair", "<u2"), ("orient", "u1"),
+                      ("flags", "u1")])
+assert HIT_DTYPE.itemsize == 12 and AMP_DTYPE.itemsize == 16
+
+
+def check(st: int, where: str) -> None:
+    if st != AH_OK:
+        raise AhError(st, where)
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev():
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+# ---------------------------------------------------------------------------
+# Store
+# ---------------------------------------------------------------------------
+class Store:
+    """Device-resident 2-bit genome store (all arrays are torch tensors)."""
+
+    def __init__(self, lengths: Sequence[int], nmask_cap: int = 1 << 16, device=None):
+        dev = device or _dev()
+        lens = np.ascontiguousarray(np.asarray(lengths, dtype=np.uint64))
+        n = len(lens)
+        b0 = np.zeros(max(n, 1), np.uint64)
+        nb = U64(0)
+        check(_lib.ah_pack_layout(lens.ctypes.data_as(VP), n, b0.ctypes.data_as(VP), C.byref(nb)), "ah_pack_layout")
+        self.n_seqs = n
+        self.n_blocks = int(nb.value)
+        self.lengths = lens
+        self.seq_block0_host = b0[:n].copy()
+        nw = (self.n_blocks + 31) // 32
+        self.blocks = torch.empty((max(self.n_blocks, 1), 4), dtype=torch.int32, device=dev)
+        self.seq_block0 = torch.from_numpy(b0[:n].astype(np.int64)).to(dev) if n else torch.zeros(1, dtype=torch.int64,
+                                                                                                    device=dev)
+        self.seq_len = torch.from_numpy(lens.astype(np.uint32).view(np.int32)).to(dev) if n else torch.zeros(
+            1, dtype=torch.int32, device=dev)
+        self.nbits = torch.zeros(max(nw, 1), dtype=torch.int32, device=dev)
+        self.nrank = torch.zeros(max(nw, 1), dtype=torch.int32, device=dev)
+        self.nmask = torch.zeros(max(nmask_cap, 1), dtype=torch.int64, device=dev)
+        self.nmask_cap = nmask_cap
+        self.counters = torch.zeros(AH_STORE_SCRATCH, dtype=torch.int64, device=dev)
+        self.c = ah_store(n, int(lens.max()) if n else 0, self.n_blocks, self.blocks.data_ptr(),
+                          self.seq_block0.data_ptr(), self.seq_len.data_ptr(), self.nbits.data_ptr(),
+                          self.nrank.data_ptr(), self.nmask.data_ptr(), nmask_cap, self.counters.data_ptr())
+
+    @property
+    def total_bases(self) -> int:
+        return int(self.lengths.sum())
+
+    @property
+    def hbm_bytes(self) -> int:
+        return 16 * self.n_blocks
+
+    # -- ingest -------------------------------------------------------------
+    def pack_chunks(self, chunks, stream=None, nlist_cap: Optional[int] = None):
+        """chunks: iterable of (first_seq, ascii uint8 array, offsets uint64[n+1])."""
+        s = _stream(stream)
+        cap = nlist_cap or self.nmask_cap
+        nlist = torch.zeros((max(cap, 1), 2), dtype=torch.int64, device=self.blocks.device)
+        check(_lib.ah_pack_begin(C.byref(self.c), s), "ah_pack_begin")
+        for first, buf, off in chunks:
+            n = len(off) - 1
+            d_buf = torch.from_numpy(np.ascontiguousarray(buf)).to(self.blocks.device, non_blocking=False)
+            d_off = torch.from_numpy(np.ascontiguousarray(off, dtype=np.uint64).view(np.int64)).to(
+                self.blocks.device)
+            check(_lib.ah_pack(C.byref(self.c), _p(d_buf), _p(d_off), first, n, _p(nlist), cap, s), "ah_pack")
+            torch.cuda.current_stream().synchronize()
+            del d_buf, d_off
+        check(_lib.ah_pack_finish(C.byref(self.c), _p(nlist), cap, s), "ah_pack_finish")
+        torch.cuda.synchronize()
+        n_flag = int(self.counters[0].item())
+        if n_flag > cap or n_flag > self.nmask_cap:
+            raise AhError(AH_E_LIMIT, "store: %d blocks hold N, capacity %d" % (n_flag, min(cap, self.nmask_cap)))
+        self.n_nblocks = n_flag
+        return self
+
+    @classmethod
+    def from_workload(cls, wl, chunk_bases: int = 1 << 30, nmask_cap: int = 1 << 16):
+        st = cls(wl.lengths, nmask_cap=nmask_cap)
+        return st.pack_chunks(wl.chunks(chunk_bases))
+
+    @classmethod
+    def from_ascii(cls, seqs: Sequence[bytes], nmask_cap: int = 1 << 16):
+        arrs = [np.frombuffer(s if isinstance(s, (bytes, bytearray)) else s.encode(), np.uint8) if not isinstance(
+            s, np.ndarray) else s for s in seqs]
+        lens = [len(a) for a in arrs]
+        st = cls(lens, nmask_cap=nmask_cap)
+        off = np.zeros(len(arrs) + 1, np.uint64)
+        off[1:] = np.cumsum(lens)
+        buf = np.concatenate(arrs) if arrs else np.zeros(0, np.uint8)
+        if len(buf) == 0:
+            buf = np.zeros(1, np.uint8)
+        return st.pack_chunks([(0, buf, off)])
+
+    def unpack(self, seq: int, start: int = 0, n: Optional[int] = None) -> bytes:
+        n = int(self.lengths[seq]) - start if n is None else n
+        out = torch.zeros(max(n, 1), dtype=torch.uint8, device=self.blocks.device)
+        check(_lib.ah_unpack(C.byref(self.c), seq, start, n, _p(out), _stream()), "ah_unpack")
+        torch.cuda.synchronize()
+        return out[:n].cpu().numpy().tobytes()
+
+
+# ---------------------------------------------------------------------------
+# Primer sets
+# ---------------------------------------------------------------------------
+class PrimerSet:
+    def __init__(self, pairs):
+        self.pairs = list(pairs)
+        arr = (ah_pair_spec * len(self.pairs))()
+        self._keep = []
+        for i, p in enumerate(self.pairs):
+            f, r = p.fwd.encode(), p.rev.encode()
+            self._keep += [f, r]
+            arr[i] = ah_pair_spec(f, r, int(p.k), int(p.clamp), int(p.min_len), int(p.max_len))
+        h = VP()
+        check(_lib.ah_primers_compile(arr, len(self.pairs), C.byref(h)), "ah_primers_compile")
+        self.h = h
+
+    def __len__(self):
+        return len(self.pairs)
+
+    def close(self):
+        if self.h:
+            _lib.ah_primers_free(self.h)
+            self.h = VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tm_params(tm) -> ah_tm_params:
+    return ah_tm_params(tm.na_mM, tm.k_mM, tm.tris_mM, tm.mg_mM, tm.dntps_mM, tm.dnac1_nM, tm.dnac2_nM,
+                        tm.threshold_C, int(tm.saltcorr), int(bool(tm.filter)))
+
+
+def extract_opts(ex) -> ah_extract_opts:
+    return ah_extract_opts(int(bool(ex.trim)), int(ex.fb_len), int(ex.rb_len))
+
+
+# ---------------------------------------------------------------------------
+# Stage wrappers (device buffers in, device buffers out)
+# ---------------------------------------------------------------------------
+def ws_scan(store: Store, n_list: int) -> int:
+    b = U64(0)
+    check(_lib.ah_scan_ws_size(C.byref(store.c), n_list, C.byref(b)), "ah_scan_ws_size")
+    return int(b.value)
+
+
+def ws_pair(store: Store, ps: PrimerSet, hit_cap: int) -> int:
+    b = U64(0)
+    check(_lib.ah_pair_ws_size(C.byref(store.c), ps.h, hit_cap, C.byref(b)), "ah_pair_ws_size")
+    return int(b.value)
+
+
+def ws_extract(amp_cap: int) -> int:
+    b = U64(0)
+    check(_lib.ah_extract_ws_size(amp_cap, C.byref(b)), "ah_extract_ws_size")
+    return int(b.value)
+
+
+def scan_primers(store, ps, hits, hit_cap, n_hits, ws, subset=None, stream=None):
+    n_sub = 0 if subset is None else int(subset.numel())
+    check(_lib.ah_scan_primers(C.byref(store.c), ps.h, _p(subset), n_sub, _p(hits), hit_cap, _p(n_hits), _p(ws),
+                               ws.numel() * ws.element_size(), _stream(stream)), "ah_scan_primers")
+
+
+def pair_amplicons(store, ps, hits, n_hits, hit_cap, orient_mask, amps, amp_cap, n_amps, ws, stream=None):
+    check(_lib.ah_pair_amplicons(C.byref(store.c), ps.h, _p(hits), _p(n_hits), hit_cap, orient_mask, _p(amps),
+                                 amp_cap, _p(n_amps), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
+          "ah_pair_amplicons")
+
+
+def tm_nn(store, ps, amps, n_amps, amp_cap, params: ah_tm_params, tm, tm_site, passed, stream=None):
+    check(_lib.ah_tm_nn(C.byref(store.c), ps.h, _p(amps), _p(n_amps), amp_cap, C.byref(params), _p(tm),
+                        _p(tm_site), _p(passed), _stream(stream)), "ah_tm_nn")
+
+
+def extract(store, ps, amps, n_amps, amp_cap, passed, opts: ah_extract_opts, seq, seq_cap, seq_off, fb, rb, bc_len,
+            fpr, rpr, n_bytes, ws, stream=None):
+    check(_lib.ah_extract(C.byref(store.c), ps.h, _p(amps), _p(n_amps), amp_cap, _p(passed), C.byref(opts), _p(seq),
+                          seq_cap, _p(seq_off), _p(fb), _p(rb), _p(bc_len), _p(fpr), _p(rpr), _p(n_bytes), _p(ws),
+                          ws.numel() * ws.element_size(), _stream(stream)), "ah_extract")
+
+
+def tm_duplex(seqs: Sequence[str], cseqs: Sequence[str], tm) -> np.ndarray:
+    """Tm of explicit duplexes on the GPU (seq 5'->3', cseq its partner 3'->5')."""
+    n = len(seqs)
+    stride = 32
+    a = np.zeros((max(n, 1), stride), np.uint8)
+    b = np.zeros((max(n, 1), stride), np.uint8)
+    ln = np.zeros(max(n, 1), np.uint32)
+    for i, (s, c) in enumerate(zip(seqs, cseqs)):
+        a[i, :len(s)] = np.frombuffer(s.encode(), np.uint8)
+        b[i, :len(c)] = np.frombuffer(c.encode(), np.uint8)
+        ln[i] = len(s)
+    dev = _dev()
+    da, db = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    dl = torch.from_numpy(ln.view(np.int32)).to(dev)
+    out = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    prm = tm_params(tm)
+    check(_lib.ah_tm_duplex(_p(da), _p(db), _p(dl), n, stride, C.byref(prm), _p(out), _stream()), "ah_tm_duplex")
+    torch.cuda.synchronize()
+    return out[:n].cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# The whole path with preallocated buffers
+# ---------------------------------------------------------------------------
+@dataclass
+class Caps:
+    hits: int
+    amps: int
+    seq_bytes: int
+
+
+class Pipeline:
+    """scan -> pair -> Tm -> extract over a store with fixed capacities.
+
+    All buffers are allocated once; ``launch()`` only enqueues kernels (so it
+    can be captured into a HIP graph); ``counts()`` synchronises and reads the
+    device counters; ``run()`` re-launches with larger capacities on overflow.
+    """
+
+    def __init__(self, store: Store, ps: PrimerSet, orient_mask: int, tm, ex=None, caps: Optional[Caps] = None,
+                 subset: Optional[torch.Tensor] = None):
+        self.store, self.ps = store, ps
+        self.orient_mask = orient_mask
+        self.tm_spec = tm
+        self.params = tm_params(tm)
+        self.ex = ex
+        self.opts = extract_opts(ex) if ex is not None else None
+        self.subset = subset
+        self.dev = store.blocks.device
+        self._alloc(caps or Caps(1 << 16, 1 << 15, 1 << 22))
+
+    def _alloc(self, caps: Caps):
+        d = self.dev
+        self.caps = caps
+        n_list = self.store.n_seqs if self.subset is None else int(self.subset.numel())
+        self.counters = torch.zeros(4, dtype=torch.int64, device=d)  # hits, amps, bytes
+        self.hits = torch.empty((caps.hits, 3), dtype=torch.int32, device=d)
+        self.amps = torch.empty((caps.amps, 4), dtype=torch.int32, device=d)
+        self.tm = torch.empty(caps.amps, dtype=torch.float64, device=d)
+        self.tm_site = torch.empty((caps.amps, 2), dtype=torch.float64, device=d)
+        self.passed = torch.empty(caps.amps, dtype=torch.uint8, device=d)
+        ws = max(ws_scan(self.store, n_list), ws_pair(self.store, self.ps, caps.hits), ws_extract(caps.amps))
+        self.ws = torch.empty(ws // 8 + 1, dtype=torch.int64, device=d)
+        if self.opts is not None:
+            fb, rb = max(self.opts.fb_len, 1), max(self.opts.rb_len, 1)
+            self.seq = torch.empty(max(caps.seq_bytes, 1), dtype=torch.uint8, device=d)
+            self.seq_off = torch.empty(caps.amps + 1, dtype=torch.int64, device=d)
+            self.fb = torch.empty((caps.amps, fb), dtype=torch.uint8, device=d)
+            self.rb = torch.empty((caps.amps, rb), dtype=torch.uint8, device=d)
+            self.bc_len = torch.empty((caps.amps, 2), dtype=torch.uint8, device=d)
+            self.fpr = torch.empty((caps.amps, 32), dtype=torch.uint8, device=d)
+            self.rpr = torch.empty((caps.amps, 32), dtype=torch.uint8, device=d)
+
+    def launch(self, stream=None, stages=("scan", "pair", "tm", "extract")):
+        c = self.counters
+        n_hits, n_amps, n_bytes = c[0:1], c[1:2], c[2:3]
+        if "scan" in stages:
+            scan_primers(self.store, self.ps, self.hits, self.caps.hits, n_hits, self.ws, self.subset, stream)
+        if "pair" in stages:
+            pair_amplicons(self.store, self.ps, self.hits, n_hits, self.caps.hits, self.orient_mask, self.amps,
+                           self.caps.amps, n_amps, self.ws, stream)
+        if "tm" in stages:
+            tm_nn(self.store, self.ps, self.amps, n_amps, self.caps.amps, self.params, self.tm, self.tm_site,
+                  self.passed, stream)
+        if "extract" in stages and self.opts is not None:
+            extract(self.store, self.ps, self.amps, n_amps, self.caps.amps,
+                    self.passed if self.tm_spec.filter else None, self.opts, self.seq, self.caps.seq_bytes,
+                    self.seq_off, self.fb, self.rb, self.bc_len, self.fpr, self.rpr, n_bytes, self.ws, stream)
+
+    def counts(self):
+        torch.cuda.synchronize()
+        v = self.counters.cpu().numpy()
+        return int(v[0]), int(v[1]), int(v[2])
+
+    def overflowed(self):
+        h, a, b = self.counts()
+        return h > self.caps.hits or a > self.caps.amps or (self.opts is not None and b > self.caps.seq_bytes)
+
+    def run(self, stream=None):
+        """Launch; on overflow grow the capacities and launch again (exact)."""
+        while True:
+            self.launch(stream)
+            h, a, b = self.counts()
+            if h <= self.caps.hits and a <= self.caps.amps and (self.opts is None or b <= self.caps.seq_bytes):
+                return self
+            self._alloc(Caps(max(self.caps.hits, int(h * 1.25) + 1024), max(self.caps.amps, int(a * 1.25) + 1024),
+                             max(self.caps.seq_bytes, int(b * 1.25) + 4096)))
+
+    # -- results to host ------------------------------------------------------
+    def results(self):
+        h, a, b = self.counts()
+        out = {}
+        out["hits"] = self.hits[:h].cpu().numpy().view(np.uint8).reshape(-1).view(HIT_DTYPE)
+        out["amps"] = self.amps[:a].cpu().numpy().view(np.uint8).reshape(-1).view(AMP_DTYPE)
+        out["tm"] = self.tm[:a].cpu().numpy()
+        out["tm_site"] = self.tm_site[:a].cpu().numpy()
+        out["pass"] = self.passed[:a].cpu().numpy()
+        if self.opts is not None:
+            out["seq"] = self.seq[:b].cpu().numpy().tobytes()
+            out["seq_off"] = self.seq_off[:a + 1].cpu().numpy().astype(np.uint64)
+            out["fb"] = self.fb[:a, :self.opts.fb_len].cpu().numpy()
+            out["rb"] = self.rb[:a, :self.opts.rb_len].cpu().numpy()
+            out["bc_len"] = self.bc_len[:a].cpu().numpy()
+            out["fprimer"] = self.fpr[:a].cpu().numpy()
+            out["rprimer"] = self.rpr[:a].cpu().numpy()
+        return out
+
+
+def hits_canonical(h: np.ndarray) -> np.ndarray:
+    """Hits as an (n, 5) array [seq, pos, pair, kind, mm] in the oracle's order (seq, pair, pos, kind)."""
+    a = np.stack([h["seq"].astype(np.int64), h["pos"], h["pair"], h["kind"], h["mm"]], axis=1).astype(np.int64)
+    order = np.lexsort((a[:, 3], a[:, 1], a[:, 2], a[:, 0]))
+    return a[order]
+
+
+def amps_array(a: np.ndarray) -> np.ndarray:
+    """Amplicons as (n, 5) [seq, start, end, pair, orient] (library order kept)."""
+    return np.stack([a["seq"], a["start"], a["end"], a["pair"], a["orient"]], axis=1).astype(np.int64)

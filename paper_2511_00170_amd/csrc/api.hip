@@ -1,0 +1,185 @@
+// Host-side entry points of libah.so: status strings, store layout and the
+// primer-set compiler (per-base IUPAC masks and reverse-complement masks,
+// Supplementary "Primer matching and clamp logic").
+#include <string.h>
+
+#include <vector>
+
+#include "ah_internal.h"
+
+extern "C" const char *ah_status_str(ah_status s) {
+    switch (s) {
+    case AH_OK: return "ok";
+    case AH_E_ARG: return "invalid argument";
+    case AH_E_ALPHABET: return "primer letter is not an IUPAC nucleotide code";
+    case AH_E_LIMIT: return "size limit exceeded (primer length 1..32, clamp <= length, pairs, key width)";
+    case AH_E_HIP: return "HIP runtime error";
+    case AH_E_WORKSPACE: return "workspace too small";
+    default: return "unknown status";
+    }
+}
+
+extern "C" int ah_version(void) { return 1; }
+
+extern "C" ah_status ah_pack_layout(const uint64_t *h_lens, uint32_t n_seqs, uint64_t *h_seq_block0,
+                                    uint64_t *h_n_blocks) {
+    if ((!h_lens || !h_seq_block0) && n_seqs) return AH_E_ARG;
+    if (!h_n_blocks) return AH_E_ARG;
+    uint64_t b = 0;
+    for (uint32_t i = 0; i < n_seqs; i++) {
+        if (h_lens[i] >= (1ull << 32)) return AH_E_LIMIT;
+        h_seq_block0[i] = b;
+        b += (h_lens[i] + 63) / 64;
+    }
+    *h_n_blocks = b;
+    return AH_OK;
+}
+
+// IUPAC nucleotide code -> set of bases, bit b for base b (A=0, C=1, G=2, T=3).
+static int iupac_bits(char ch) {
+    static const char *names = "ACGTURYSWKMBDHVN";
+    static const int sets[16] = {
+        1, 2, 4, 8, 8,            // A C G T U
+        1 | 4, 2 | 8,             // R (A/G)  Y (C/T)
+        2 | 4, 1 | 8,             // S (C/G)  W (A/T)
+        4 | 8, 1 | 2,             // K (G/T)  M (A/C)
+        14, 13, 11, 7,            // B (not A) D (not C) H (not G) V (not T)
+        15};                      // N
+    char u = (ch >= 'a' && ch <= 'z') ? (char)(ch - 32) : ch;
+    const char *p = u ? strchr(names, u) : nullptr;
+    return p ? sets[p - names] : 0;
+}
+
+// Complement of a base set: base b <-> 3 - b.
+static int comp_bits(int m) {
+    int r = 0;
+    for (int b = 0; b < 4; b++)
+        if (m & (1 << b)) r |= 1 << (3 - b);
+    return r;
+}
+
+static ah_status parse_primer(const char *s, int *masks, int *L) {
+    if (!s) return AH_E_ARG;
+    size_t n = strlen(s);
+    if (n < 1 || n > AH_MAXL) return AH_E_LIMIT;
+    for (size_t j = 0; j < n; j++) {
+        masks[j] = iupac_bits(s[j]);
+        if (!masks[j]) return AH_E_ALPHABET;
+    }
+    *L = (int)n;
+    return AH_OK;
+}
+
+static void make_pattern(const int *X, int L, int k, int clamp, int minus, uint32_t pair, uint32_t kind, DPat *d) {
+    memset(d, 0, sizeof(*d));
+    for (int j = 0; j < L; j++)
+        for (int b = 0; b < 4; b++)
+            if (X[j] & (1 << b)) d->P[b] |= 1u << j;
+    d->lmask = L == 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
+    for (int j = 0; j < clamp; j++) d->clampmask |= 1u << (minus ? j : L - 1 - j);
+    int W = clamp < AH_WMAX ? clamp : AH_WMAX;
+    int shift = minus ? 0 : L - W;
+    for (int i = 0; i < W; i++) d->fcode[i] = (uint8_t)(minus ? X[i] : X[L - W + i]);
+    int kk = k > 255 ? 255 : k;
+    d->meta = (uint32_t)L | ((uint32_t)kk << 8) | ((uint32_t)W << 16) | ((uint32_t)shift << 24);
+    d->pk = pair | (kind << 16);
+}
+
+static void make_primer(const int *m, int L, DPrimer *p) {
+    memset(p, 0, sizeof(*p));
+    p->L = (uint8_t)L;
+    uint64_t D = 1;
+    for (int j = 0; j < L; j++) {
+        int n = 0, first = -1;
+        for (int b = 0; b < 4; b++)
+            if (m[j] & (1 << b)) {
+                if (first < 0) first = b;
+                n++;
+            }
+        p->code[j] = (uint8_t)first;
+        if (n > 1) {
+            int d = p->n_deg++;
+            p->deg_pos[d] = (uint8_t)j;
+            p->deg_n[d] = (uint8_t)n;
+            int c = 0;
+            for (int b = 0; b < 4; b++)
+                if (m[j] & (1 << b)) p->deg_base[d][c++] = (uint8_t)b;
+        }
+        D *= (uint64_t)n;
+        if (D > AH_MAX_VARIANTS) D = (uint64_t)AH_MAX_VARIANTS + 1;
+    }
+    p->D = D > AH_MAX_VARIANTS ? 0u : (uint32_t)D;  // 0: too many variants for Tm
+}
+
+extern "C" ah_status ah_primers_compile(const ah_pair_spec *h_pairs, uint32_t n_pairs, ah_primer_set *out) {
+    if (!out || (!h_pairs && n_pairs)) return AH_E_ARG;
+    if (n_pairs == 0) return AH_E_ARG;
+    if (n_pairs > AH_MAX_PAIRS) return AH_E_LIMIT;
+    std::vector<DPat> pats(4 * (size_t)n_pairs);
+    std::vector<DPair> prs(n_pairs);
+    uint32_t maxL = 0, maxW = 0, minW = AH_WMAX;
+    for (uint32_t q = 0; q < n_pairs; q++) {
+        const ah_pair_spec &sp = h_pairs[q];
+        int mf[AH_MAXL], mr[AH_MAXL], Lf = 0, Lr = 0;
+        ah_status e = parse_primer(sp.fwd, mf, &Lf);
+        if (e) return e;
+        e = parse_primer(sp.rev, mr, &Lr);
+        if (e) return e;
+        if ((int)sp.clamp > (Lf < Lr ? Lf : Lr)) return AH_E_LIMIT;
+        if (sp.min_len > sp.max_len) return AH_E_ARG;
+        int rf[AH_MAXL], rr[AH_MAXL];  // reverse complements
+        for (int j = 0; j < Lf; j++) rf[j] = comp_bits(mf[Lf - 1 - j]);
+        for (int j = 0; j < Lr; j++) rr[j] = comp_bits(mr[Lr - 1 - j]);
+        int k = (int)(sp.k > 255 ? 255 : sp.k), c = (int)sp.clamp;
+        make_pattern(mf, Lf, k, c, 0, q, 0, &pats[4 * q + 0]);  // F+
+        make_pattern(mr, Lr, k, c, 0, q, 1, &pats[4 * q + 1]);  // R+
+        make_pattern(rf, Lf, k, c, 1, q, 2, &pats[4 * q + 2]);  // F-
+        make_pattern(rr, Lr, k, c, 1, q, 3, &pats[4 * q + 3]);  // R-
+        DPair &P = prs[q];
+        memset(&P, 0, sizeof(P));
+        P.min_len = sp.min_len;
+        P.max_len = sp.max_len;
+        P.Lf = (uint8_t)Lf;
+        P.Lr = (uint8_t)Lr;
+        P.k = (uint8_t)k;
+        P.clamp = (uint8_t)c;
+        make_primer(mf, Lf, &P.prim[0]);
+        make_primer(mr, Lr, &P.prim[1]);
+        maxL = (uint32_t)(Lf > (int)maxL ? Lf : maxL);
+        maxL = (uint32_t)(Lr > (int)maxL ? Lr : maxL);
+        uint32_t W = c < AH_WMAX ? (uint32_t)c : AH_WMAX;
+        if (W > maxW) maxW = W;
+        if (W < minW) minW = W;
+    }
+    ah_primer_set ps = new ah_primer_set_();
+    ps->n_pairs = n_pairs;
+    ps->n_pats = 4 * n_pairs;
+    ps->max_L = maxL;
+    ps->max_W = maxW;
+    ps->min_W = minW;
+    ps->h_pats = new DPat[pats.size()];
+    memcpy(ps->h_pats, pats.data(), pats.size() * sizeof(DPat));
+    ps->h_pairs = new DPair[n_pairs];
+    memcpy(ps->h_pairs, prs.data(), prs.size() * sizeof(DPair));
+    if (hipGetDevice(&ps->device) != hipSuccess ||
+        hipMalloc((void **)&ps->d_pats, pats.size() * sizeof(DPat)) != hipSuccess ||
+        hipMalloc((void **)&ps->d_pairs, prs.size() * sizeof(DPair)) != hipSuccess ||
+        hipMemcpy(ps->d_pats, pats.data(), pats.size() * sizeof(DPat), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ps->d_pairs, prs.data(), prs.size() * sizeof(DPair), hipMemcpyHostToDevice) != hipSuccess) {
+        ah_primers_free(ps);
+        return AH_E_HIP;
+    }
+    *out = ps;
+    return AH_OK;
+}
+
+extern "C" void ah_primers_free(ah_primer_set ps) {
+    if (!ps) return;
+    if (ps->d_pats) (void)hipFree(ps->d_pats);
+    if (ps->d_pairs) (void)hipFree(ps->d_pairs);
+    delete[] ps->h_pats;
+    delete[] ps->h_pairs;
+    delete ps;
+}
+
+extern "C" uint32_t ah_primers_count(ah_primer_set ps) { return ps ? ps->n_pairs : 0; }

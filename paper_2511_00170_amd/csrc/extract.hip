@@ -1,0 +1,192 @@
+// Amplicon sequences, primer trimming and flanking barcodes (Supplementary,
+// "Primer trimming and barcode extraction", "Amplicon calling and
+// orientation": RF amplicons are reverse-complemented; "Headers and
+// outputs": matched primer snippets and fb/rb in the header).
+//
+// Two passes: per-amplicon output sizes -> exclusive scan -> one wavefront
+// per amplicon decodes its bases from the 2-bit store and writes them with
+// consecutive lanes on consecutive bytes.
+#include "ah_internal.h"
+#include "ah_scan_impl.h"
+
+struct AmpGeom {
+    uint32_t seq, start, end, pair, orient;
+    uint32_t Ll, Lr;  // lengths of the upstream and downstream primers
+    int lp, rp;       // upstream / downstream primer: 0 forward, 1 reverse
+};
+
+__device__ __forceinline__ AmpGeom amp_geom(const uint32_t *amps, uint64_t i, const DPair *pairs) {
+    AmpGeom g;
+    g.seq = amps[4 * i];
+    g.start = amps[4 * i + 1];
+    g.end = amps[4 * i + 2];
+    g.pair = amps[4 * i + 3] & 0xFFFFu;
+    g.orient = (amps[4 * i + 3] >> 16) & 0xFFu;
+    g.lp = (g.orient == 0 || g.orient == 2) ? 0 : 1;
+    g.rp = (g.orient == 0 || g.orient == 3) ? 1 : 0;
+    g.Ll = g.lp ? pairs[g.pair].Lr : pairs[g.pair].Lf;
+    g.Lr = g.rp ? pairs[g.pair].Lr : pairs[g.pair].Lf;
+    return g;
+}
+
+__device__ __forceinline__ void amp_span(const AmpGeom &g, uint32_t trim, uint64_t *a0, uint64_t *a1) {
+    if (trim) {
+        *a0 = (uint64_t)g.start + g.Ll;
+        const uint64_t e = (uint64_t)g.end - g.Lr;
+        *a1 = e > *a0 ? e : *a0;
+    } else {
+        *a0 = g.start;
+        *a1 = g.end;
+    }
+}
+
+// base at position p of sequence with first block b0: 'A','C','G','T' or 'N'
+__device__ __forceinline__ char base_at(const ah_store &st, uint64_t b0, uint64_t p, bool rc) {
+    const uint64_t b = b0 + (p >> 6);
+    const uint32_t bit = (uint32_t)(p & 63);
+    const uint32_t *w = st.d_blocks + 4 * b;
+    const uint32_t h = bit < 32 ? w[0] : w[2], l = bit < 32 ? w[1] : w[3];
+    uint32_t c = (((h >> (bit & 31)) & 1u) << 1) | ((l >> (bit & 31)) & 1u);
+    if ((ah_block_nmask(st, b) >> bit) & 1ull) return 'N';
+    if (rc) c ^= 3u;
+    return "ACGT"[c];
+}
+
+__global__ void ah_extract_size_kernel(const uint32_t *amps, const uint64_t *d_n, uint64_t cap, const DPair *pairs,
+                                       const uint8_t *pass, uint32_t trim, uint64_t *size) {
+    const uint64_t n = *d_n < cap ? *d_n : cap;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t s = 0;
+        if (!pass || pass[i]) {
+            const AmpGeom g = amp_geom(amps, i, pairs);
+            uint64_t a0, a1;
+            amp_span(g, trim, &a0, &a1);
+            s = a1 - a0;
+        }
+        size[i] = s;
+    }
+}
+
+__global__ void ah_extract_tail_kernel(const uint64_t *d_n, uint64_t cap, const uint64_t *total, uint64_t *seq_off,
+                                       uint64_t *n_bytes) {
+    const uint64_t n = *d_n < cap ? *d_n : cap;
+    seq_off[n] = *total;
+    *n_bytes = *total;
+}
+
+__global__ void __launch_bounds__(256) ah_extract_write_kernel(ah_store st, const uint32_t *amps, const uint64_t *d_n,
+                                                               uint64_t cap, const DPair *pairs, const uint8_t *pass,
+                                                               ah_extract_opts o, const uint64_t *seq_off, char *out,
+                                                               uint64_t seq_cap, char *fb, char *rb, uint8_t *bc_len,
+                                                               char *fpr, char *rpr) {
+    const uint64_t n = *d_n < cap ? *d_n : cap;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t i = blockIdx.x * (uint64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); i < n; i += nw) {
+        const bool on = !pass || pass[i];
+        const AmpGeom g = amp_geom(amps, i, pairs);
+        const uint64_t b0 = st.d_seq_block0[g.seq];
+        const uint64_t len = st.d_seq_len[g.seq];
+        const bool rc = g.orient == 1;
+        // barcode spans on the plus strand
+        uint64_t f0, f1, r0, r1;
+        if (!rc) {
+            f0 = g.start >= o.fb_len ? g.start - o.fb_len : 0;
+            f1 = g.start;
+            r0 = g.end;
+            r1 = (uint64_t)g.end + o.rb_len <= len ? (uint64_t)g.end + o.rb_len : len;
+        } else {
+            f0 = g.end;
+            f1 = (uint64_t)g.end + o.fb_len <= len ? (uint64_t)g.end + o.fb_len : len;
+            r0 = g.start >= o.rb_len ? g.start - o.rb_len : 0;
+            r1 = g.start;
+        }
+        if (!on) f1 = f0, r1 = r0;
+        const uint32_t nf = (uint32_t)(f1 - f0), nr = (uint32_t)(r1 - r0);
+        for (uint32_t j = lane; j < o.fb_len; j += 64)
+            fb[i * o.fb_len + j] = j < nf ? base_at(st, b0, rc ? f1 - 1 - j : f0 + j, rc) : 0;
+        for (uint32_t j = lane; j < o.rb_len; j += 64)
+            rb[i * o.rb_len + j] = j < nr ? base_at(st, b0, rc ? r1 - 1 - j : r0 + j, rc) : 0;
+        if (lane == 0) {
+            bc_len[2 * i] = (uint8_t)nf;
+            bc_len[2 * i + 1] = (uint8_t)nr;
+        }
+        // primer snippets: upstream site as read, downstream site reverse-complemented
+        char *left_dst = (g.lp == 0) ? fpr + 32 * i : rpr + 32 * i;
+        char *right_dst = (g.rp == 1) ? rpr + 32 * i : fpr + 32 * i;
+        if (g.lp == g.rp) {
+            left_dst = fpr + 32 * i;
+            right_dst = rpr + 32 * i;
+        }
+        if (lane < 32) {
+            left_dst[lane] = (on && lane < g.Ll) ? base_at(st, b0, (uint64_t)g.start + lane, false) : 0;
+        } else {
+            const uint32_t j = lane - 32;
+            right_dst[j] = (on && j < g.Lr) ? base_at(st, b0, (uint64_t)g.end - 1 - j, true) : 0;
+        }
+        if (!on) continue;
+        uint64_t a0, a1;
+        amp_span(g, o.trim, &a0, &a1);
+        const uint64_t dst0 = seq_off[i];
+        const uint64_t m = a1 - a0;
+        for (uint64_t j = lane; j < m; j += 64) {
+            if (dst0 + j < seq_cap) out[dst0 + j] = base_at(st, b0, rc ? a1 - 1 - j : a0 + j, rc);
+        }
+    }
+}
+
+struct ExtractWs {
+    uint64_t *size, *partials, *total;
+    uint64_t bytes;
+};
+
+static ExtractWs extract_ws(void *base, uint64_t cap) {
+    ExtractWs w;
+    char *p = (char *)base;
+    uint64_t o = 0;
+    auto take = [&](uint64_t n) {
+        char *r = p ? p + o : nullptr;
+        o += ah_align_up(n, 256);
+        return r;
+    };
+    w.size = (uint64_t *)take(8 * cap);
+    w.partials = (uint64_t *)take(8 * AH_SCAN_BLOCKS);
+    w.total = (uint64_t *)take(16);
+    w.bytes = o;
+    return w;
+}
+
+extern "C" ah_status ah_extract_ws_size(uint64_t amp_cap, uint64_t *bytes) {
+    if (!bytes) return AH_E_ARG;
+    *bytes = extract_ws(nullptr, amp_cap ? amp_cap : 1).bytes;
+    return AH_OK;
+}
+
+extern "C" ah_status ah_extract(const ah_store *st, ah_primer_set ps, const ah_amp *d_amps, const uint64_t *d_n_amps,
+                                uint64_t amp_cap, const uint8_t *d_pass, const ah_extract_opts *o, char *d_seq,
+                                uint64_t seq_cap, uint64_t *d_seq_off, char *d_fb, char *d_rb, uint8_t *d_bc_len,
+                                char *d_fprimer, char *d_rprimer, uint64_t *d_n_bytes, void *d_ws, uint64_t ws_bytes,
+                                void *stream) {
+    if (!st || !ps || !o || !d_n_amps || !d_n_bytes || !d_seq_off) return AH_E_ARG;
+    if (o->fb_len > 255 || o->rb_len > 255) return AH_E_LIMIT;
+    if (amp_cap && (!d_amps || !d_bc_len || !d_fprimer || !d_rprimer)) return AH_E_ARG;
+    if (amp_cap && ((o->fb_len && !d_fb) || (o->rb_len && !d_rb))) return AH_E_ARG;
+    if (seq_cap && !d_seq) return AH_E_ARG;
+    ExtractWs w = extract_ws(d_ws, amp_cap ? amp_cap : 1);
+    if (!d_ws || ws_bytes < w.bytes) return AH_E_WORKSPACE;
+    hipStream_t s = ah_stream(stream);
+    hipLaunchKernelGGL(ah_extract_size_kernel, dim3(1024), dim3(256), 0, s, (const uint32_t *)d_amps, d_n_amps, amp_cap,
+                       (const DPair *)ps->d_pairs, d_pass, o->trim, w.size);
+    ah_status e = ah_exclusive_scan<uint64_t, uint64_t>(w.size, d_seq_off, d_n_amps, amp_cap, w.total, w.partials, s);
+    if (e) return e;
+    hipLaunchKernelGGL(ah_extract_tail_kernel, dim3(1), dim3(1), 0, s, d_n_amps, amp_cap, (const uint64_t *)w.total,
+                       d_seq_off, d_n_bytes);
+    if (amp_cap) {
+        uint64_t wgs = (amp_cap + 3) / 4;
+        if (wgs > 16384) wgs = 16384;
+        hipLaunchKernelGGL(ah_extract_write_kernel, dim3((unsigned)wgs), dim3(256), 0, s, *st,
+                           (const uint32_t *)d_amps, d_n_amps, amp_cap, (const DPair *)ps->d_pairs, d_pass, *o,
+                           (const uint64_t *)d_seq_off, d_seq, seq_cap, d_fb, d_rb, d_bc_len, d_fprimer, d_rprimer);
+    }
+    return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
+}

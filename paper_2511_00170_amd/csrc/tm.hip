@@ -1,0 +1,400 @@
+// Nearest-neighbour melting temperature in FP64 (Implementations, "AHv2": a
+// C re-implementation of Biopython's Tm_NN; Results, "Primer degeneracy and
+// mismatch tolerance": Tm is computed for every primer variant).
+//
+// A wavefront owns one primer site; its lanes stride over the concrete
+// variants of the degenerate primer, each lane evaluating the duplex of one
+// variant with the genome strand the primer anneals to, and the wave reduces
+// the maximum.  Stack parameters live in LDS as 256-entry tables indexed by
+// (top dinucleotide, bottom dinucleotide).
+#include <math.h>
+
+#include "ah_internal.h"
+
+// ---------------------------------------------------------------- tables
+// Stack "XY/WZ": top strand 5'-XY-3' over bottom strand 3'-WZ-5'.
+// dH kcal/mol, dS cal/(K mol).
+struct NNRow {
+    char x, y, w, z;
+    double dh, ds;
+};
+
+// Watson-Crick nearest neighbours, SantaLucia (1998) PNAS 95:1460, Table 2.
+static constexpr NNRow kWatsonCrick[] = {
+    {'A', 'A', 'T', 'T', -7.9, -22.2}, {'A', 'T', 'T', 'A', -7.2, -20.4}, {'T', 'A', 'A', 'T', -7.2, -21.3},
+    {'C', 'A', 'G', 'T', -8.5, -22.7}, {'G', 'T', 'C', 'A', -8.4, -22.4}, {'C', 'T', 'G', 'A', -7.8, -21.0},
+    {'G', 'A', 'C', 'T', -8.2, -22.2}, {'C', 'G', 'G', 'C', -10.6, -27.2}, {'G', 'C', 'C', 'G', -9.8, -24.4},
+    {'G', 'G', 'C', 'C', -8.0, -19.9},
+};
+
+// Single internal mismatches (and tandem G.T), one mismatch type per row:
+// G.T Allawi & SantaLucia 1997; G.A Allawi & SantaLucia 1998 (Biochemistry
+// 37:2170); C.T Allawi & SantaLucia 1998 (NAR 26:2694); A.C Allawi &
+// SantaLucia 1998 (Biochemistry 37:9435); A.A C.C G.G T.T Peyret et al. 1999.
+static constexpr NNRow kInternalMismatch[] = {
+    // G.T
+    {'A', 'G', 'T', 'T', 1.0, 0.9}, {'A', 'T', 'T', 'G', -2.5, -8.3}, {'C', 'G', 'G', 'T', -4.1, -11.7},
+    {'C', 'T', 'G', 'G', -2.8, -8.0}, {'G', 'G', 'C', 'T', 3.3, 10.4}, {'G', 'G', 'T', 'T', 5.8, 16.3},
+    {'G', 'T', 'C', 'G', -4.4, -12.3}, {'G', 'T', 'T', 'G', 4.1, 9.5}, {'T', 'G', 'A', 'T', -0.1, -1.7},
+    {'T', 'G', 'G', 'T', -1.4, -6.2}, {'T', 'T', 'A', 'G', -1.3, -5.3},
+    // G.A
+    {'A', 'A', 'T', 'G', -0.6, -2.3}, {'A', 'G', 'T', 'A', -0.7, -2.3}, {'C', 'A', 'G', 'G', -0.7, -2.3},
+    {'C', 'G', 'G', 'A', -4.0, -13.2}, {'G', 'A', 'C', 'G', -0.6, -1.0}, {'G', 'G', 'C', 'A', 0.5, 3.2},
+    {'T', 'A', 'A', 'G', 0.7, 0.7}, {'T', 'G', 'A', 'A', 3.0, 7.4},
+    // C.T
+    {'A', 'C', 'T', 'T', 0.7, 0.2}, {'A', 'T', 'T', 'C', -1.2, -6.2}, {'C', 'C', 'G', 'T', -0.8, -4.5},
+    {'C', 'T', 'G', 'C', -1.5, -6.1}, {'G', 'C', 'C', 'T', 2.3, 5.4}, {'G', 'T', 'C', 'C', 5.2, 13.5},
+    {'T', 'C', 'A', 'T', 1.2, 0.7}, {'T', 'T', 'A', 'C', 1.0, 0.7},
+    // A.C
+    {'A', 'A', 'T', 'C', 2.3, 4.6}, {'A', 'C', 'T', 'A', 5.3, 14.6}, {'C', 'A', 'G', 'C', 1.9, 3.7},
+    {'C', 'C', 'G', 'A', 0.6, -0.6}, {'G', 'A', 'C', 'C', 5.2, 14.2}, {'G', 'C', 'C', 'A', -0.7, -3.8},
+    {'T', 'A', 'A', 'C', 3.4, 8.0}, {'T', 'C', 'A', 'A', 7.6, 20.2},
+    // A.A, C.C, G.G, T.T
+    {'A', 'A', 'T', 'A', 1.2, 1.7}, {'C', 'A', 'G', 'A', -0.9, -4.2}, {'G', 'A', 'C', 'A', -2.9, -9.8},
+    {'T', 'A', 'A', 'A', 4.7, 12.9}, {'A', 'C', 'T', 'C', 0.0, -4.4}, {'C', 'C', 'G', 'C', -1.5, -7.2},
+    {'G', 'C', 'C', 'C', 3.6, 8.9}, {'T', 'C', 'A', 'C', 6.1, 16.4}, {'A', 'G', 'T', 'G', -3.1, -9.5},
+    {'C', 'G', 'G', 'G', -4.9, -15.3}, {'G', 'G', 'C', 'G', -6.0, -15.8}, {'T', 'G', 'A', 'G', 1.6, 3.6},
+    {'A', 'T', 'T', 'T', -2.7, -10.8}, {'C', 'T', 'G', 'T', -5.0, -15.8}, {'G', 'T', 'C', 'T', -2.2, -8.4},
+    {'T', 'T', 'A', 'T', 0.2, -1.5},
+};
+
+// Terminal mismatches, Bommarito, Peyret & SantaLucia (2000) NAR 28:1929.
+// The second pair of each stack is the mismatched duplex end.
+static constexpr NNRow kTerminalMismatch[] = {
+    {'A', 'A', 'T', 'A', -3.1, -7.8}, {'T', 'A', 'A', 'A', -2.5, -6.3}, {'C', 'A', 'G', 'A', -4.3, -10.7},
+    {'G', 'A', 'C', 'A', -8.0, -22.5}, {'A', 'C', 'T', 'C', -0.1, 0.5}, {'T', 'C', 'A', 'C', -0.7, -1.3},
+    {'C', 'C', 'G', 'C', -2.1, -5.1}, {'G', 'C', 'C', 'C', -3.9, -10.6}, {'A', 'G', 'T', 'G', -1.1, -2.1},
+    {'T', 'G', 'A', 'G', -1.1, -2.7}, {'C', 'G', 'G', 'G', -3.8, -9.5}, {'G', 'G', 'C', 'G', -0.7, -19.2},
+    {'A', 'T', 'T', 'T', -2.4, -6.5}, {'T', 'T', 'A', 'T', -3.2, -8.9}, {'C', 'T', 'G', 'T', -6.1, -16.9},
+    {'G', 'T', 'C', 'T', -7.4, -21.2}, {'A', 'A', 'T', 'C', -1.6, -4.0}, {'A', 'C', 'T', 'A', -1.8, -3.8},
+    {'C', 'A', 'G', 'C', -2.6, -5.9}, {'C', 'C', 'G', 'A', -2.7, -6.0}, {'G', 'A', 'C', 'C', -5.0, -13.8},
+    {'G', 'C', 'C', 'A', -3.2, -7.1}, {'T', 'A', 'A', 'C', -2.3, -5.9}, {'T', 'C', 'A', 'A', -2.7, -7.0},
+    {'A', 'C', 'T', 'T', -0.9, -1.7}, {'A', 'T', 'T', 'C', -2.3, -6.3}, {'C', 'C', 'G', 'T', -3.2, -8.0},
+    {'C', 'T', 'G', 'C', -3.9, -10.6}, {'G', 'C', 'C', 'T', -4.9, -13.5}, {'G', 'T', 'C', 'C', -3.0, -7.8},
+    {'T', 'C', 'A', 'T', -2.5, -6.3}, {'T', 'T', 'A', 'C', -0.7, -1.2}, {'A', 'A', 'T', 'G', -1.9, -4.4},
+    {'A', 'G', 'T', 'A', -2.5, -5.9}, {'C', 'A', 'G', 'G', -3.9, -9.6}, {'C', 'G', 'G', 'A', -6.0, -15.5},
+    {'G', 'A', 'C', 'G', -4.3, -11.1}, {'G', 'G', 'C', 'A', -4.6, -11.4}, {'T', 'A', 'A', 'G', -2.0, -4.7},
+    {'T', 'G', 'A', 'A', -2.4, -5.8}, {'A', 'G', 'T', 'T', -3.2, -8.7}, {'A', 'T', 'T', 'G', -3.5, -9.4},
+    {'C', 'G', 'G', 'T', -3.8, -9.0}, {'C', 'T', 'G', 'G', -6.6, -18.7}, {'G', 'G', 'C', 'T', -5.7, -15.9},
+    {'G', 'T', 'C', 'G', -5.9, -16.1}, {'T', 'G', 'A', 'T', -3.9, -10.5}, {'T', 'T', 'A', 'G', -3.6, -9.8},
+};
+
+// Initiation per duplex end (SantaLucia 1998): terminal A.T or G.C pair.
+#define AH_INIT_AT_DH 2.3
+#define AH_INIT_AT_DS 4.1
+#define AH_INIT_GC_DH 0.1
+#define AH_INIT_GC_DS (-2.8)
+
+struct NNTable {
+    double dh[256];
+    double ds[256];
+    uint32_t ok[8];  // bit i: entry i tabulated
+};
+
+constexpr int base_of(char c) { return c == 'A' ? 0 : c == 'C' ? 1 : c == 'G' ? 2 : 3; }
+// index: top pair of bases (x, y) in the low nibble, bottom (w, z) in the high nibble
+constexpr int nn_index(int x, int y, int w, int z) { return (x | (y << 2)) | ((w | (z << 2)) << 4); }
+
+template <size_t N>
+constexpr void put_rows(NNTable &t, const NNRow (&rows)[N], bool reversed) {
+    for (size_t r = 0; r < N; r++) {
+        const NNRow &e = rows[r];
+        int i = reversed ? nn_index(base_of(e.z), base_of(e.w), base_of(e.y), base_of(e.x))
+                         : nn_index(base_of(e.x), base_of(e.y), base_of(e.w), base_of(e.z));
+        if (t.ok[i >> 5] & (1u << (i & 31))) continue;  // a stack as written wins over a reversed reading
+        t.dh[i] = e.dh;
+        t.ds[i] = e.ds;
+        t.ok[i >> 5] |= 1u << (i & 31);
+    }
+}
+
+constexpr NNTable make_stack_table() {
+    NNTable t{};
+    put_rows(t, kWatsonCrick, false);
+    put_rows(t, kInternalMismatch, false);
+    put_rows(t, kWatsonCrick, true);
+    put_rows(t, kInternalMismatch, true);
+    return t;
+}
+
+constexpr NNTable make_terminal_table() {
+    NNTable t{};
+    put_rows(t, kTerminalMismatch, false);
+    return t;
+}
+
+__constant__ NNTable g_stack = make_stack_table();
+__constant__ NNTable g_term = make_terminal_table();
+
+struct TmConst {
+    int saltcorr;     // 0 none, 5 SantaLucia 1998 entropy term
+    double ln_mon;    // ln of the monovalent-equivalent concentration (M)
+    double rlnc;      // R ln C, C = C_high - C_low / 2 (M)
+    double threshold;
+    int filter;
+};
+
+__device__ TmConst tm_const(const ah_tm_params &p) {
+    TmConst k;
+    double mon = p.na_mM + p.k_mM + p.tris_mM / 2.0;
+    if (p.dntps_mM < p.mg_mM) mon += 120.0 * sqrt(p.mg_mM - p.dntps_mM);  // von Ahsen et al. 2001
+    mon = mon * 1e-3;
+    const double hiC = p.dnac1_nM > p.dnac2_nM ? p.dnac1_nM : p.dnac2_nM;
+    const double loC = p.dnac1_nM > p.dnac2_nM ? p.dnac2_nM : p.dnac1_nM;
+    const double C = (hiC - loC / 2.0) * 1e-9;
+    k.saltcorr = p.saltcorr;
+    k.ln_mon = log(mon);
+    k.rlnc = 1.987 * log(C);
+    k.threshold = p.threshold_C;
+    k.filter = p.filter;
+    return k;
+}
+
+__device__ __forceinline__ bool tab_ok(const uint32_t *ok, int i) { return (ok[i >> 5] >> (i & 31)) & 1u; }
+
+// Duplex Tm of variant V with partner C (2-bit codes, base j at bits 2j; C is
+// the partner strand read 3'->5' against V).  Steps: a mismatched end pair
+// is charged with the terminal-mismatch stack and leaves the helix; one
+// initiation term per end by the end bases of V; the remaining stacks from
+// 5' to 3'; the salt term; Tm = 1000 dH / (dS + R ln C) - 273.15.  The order
+// of the floating-point additions is fixed.  Returns false if a stack is not
+// tabulated.
+__device__ bool duplex_tm(uint64_t V, uint64_t C, int L, const double *sdh, const double *sds, const uint32_t *sok,
+                          const double *tdh, const double *tds, const uint32_t *tok, const TmConst &k, double *out) {
+    if (L < 2) return false;
+    auto bb = [](uint64_t X, int j) { return (int)((X >> (2 * j)) & 3u); };
+    double dh = 0.0, ds = 0.0;
+    int lo = 0, hi = L - 1;
+    {
+        // left end read from the partner strand, so the end pair comes second
+        const int i = nn_index(bb(C, 1), bb(C, 0), bb(V, 1), bb(V, 0));
+        if (tab_ok(tok, i)) {
+            dh += tdh[i];
+            ds += tds[i];
+            lo = 1;
+        }
+    }
+    if (hi - 1 >= lo) {
+        const int i = nn_index(bb(V, hi - 1), bb(V, hi), bb(C, hi - 1), bb(C, hi));
+        if (tab_ok(tok, i)) {
+            dh += tdh[i];
+            ds += tds[i];
+            hi -= 1;
+        }
+    }
+    {
+        const int e0 = bb(V, 0), e1 = bb(V, L - 1);
+        if (e0 == 0 || e0 == 3) { dh += AH_INIT_AT_DH; ds += AH_INIT_AT_DS; }
+        else { dh += AH_INIT_GC_DH; ds += AH_INIT_GC_DS; }
+        if (e1 == 0 || e1 == 3) { dh += AH_INIT_AT_DH; ds += AH_INIT_AT_DS; }
+        else { dh += AH_INIT_GC_DH; ds += AH_INIT_GC_DS; }
+    }
+    for (int j = lo; j < hi; j++) {
+        const int i = nn_index(bb(V, j), bb(V, j + 1), bb(C, j), bb(C, j + 1));
+        if (!tab_ok(sok, i)) return false;
+        dh += sdh[i];
+        ds += sds[i];
+    }
+    if (k.saltcorr == 5) ds += 0.368 * (double)(L - 1) * k.ln_mon;
+    *out = (1000.0 * dh) / (ds + k.rlnc) - 273.15;
+    return true;
+}
+
+// ---------------------------------------------------------------- sites
+__device__ __forceinline__ uint64_t spread_bits(uint32_t v) {
+    uint64_t x = v;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+// 2-bit codes of bases [p, p + L) of the store (global base index p, L <= 32),
+// base j at bits 2j; *has_n reports an N inside the window.
+__device__ uint64_t load_site(const ah_store &st, uint64_t p, int L, bool *has_n) {
+    const uint4 *blocks = (const uint4 *)st.d_blocks;
+    const uint64_t gb = p >> 6;
+    const uint32_t o = (uint32_t)(p & 63);
+    const uint4 A = blocks[gb];
+    uint32_t hW, lW;
+    if (o < 32) {
+        hW = __builtin_amdgcn_alignbit(A.z, A.x, o);
+        lW = __builtin_amdgcn_alignbit(A.w, A.y, o);
+    } else {
+        uint32_t bh = 0, bl = 0;
+        if (o - 32 + (uint32_t)L > 32 && gb + 1 < st.n_blocks) {
+            const uint4 B = blocks[gb + 1];
+            bh = B.x;
+            bl = B.y;
+        }
+        hW = __builtin_amdgcn_alignbit(bh, A.z, o - 32);
+        lW = __builtin_amdgcn_alignbit(bl, A.w, o - 32);
+    }
+    const uint64_t lmask = L == 32 ? ~0ull : ((1ull << (2 * L)) - 1);
+    uint64_t nm = ah_block_nmask(st, gb) >> o;
+    if (o + (uint32_t)L > 64 && o) nm |= ah_block_nmask(st, gb + 1) << (64 - o);
+    *has_n = (nm & ((1ull << L) - 1)) != 0;
+    return (spread_bits(lW) | (spread_bits(hW) << 1)) & lmask;
+}
+
+// reverse the order of the L 2-bit groups
+__device__ __forceinline__ uint64_t reverse_codes(uint64_t G, int L) {
+    uint64_t r = __builtin_bitreverse64(G);
+    r = ((r >> 1) & 0x5555555555555555ull) | ((r & 0x5555555555555555ull) << 1);
+    return r >> (64 - 2 * L);
+}
+
+// Variant v of a degenerate primer as 2-bit codes.
+__device__ __forceinline__ uint64_t primer_variant(const DPrimer &P, uint64_t base, uint32_t v) {
+    uint64_t V = base;
+    for (int d = P.n_deg - 1; d >= 0; d--) {
+        const uint32_t n = P.deg_n[d];
+        uint32_t q, digit;
+        if (n == 2) { q = v >> 1; digit = v & 1u; }
+        else if (n == 4) { q = v >> 2; digit = v & 3u; }
+        else { q = v / 3u; digit = v - 3u * q; }
+        v = q;
+        const int pos = P.deg_pos[d];
+        V = (V & ~(3ull << (2 * pos))) | ((uint64_t)P.deg_base[d][digit] << (2 * pos));
+    }
+    return V;
+}
+
+__device__ __forceinline__ uint64_t primer_base_codes(const DPrimer &P) {
+    uint64_t V = 0;
+    for (int j = 0; j < P.L; j++) V |= (uint64_t)P.code[j] << (2 * j);
+    return V;
+}
+
+__global__ void __launch_bounds__(256) ah_tm_site_kernel(ah_store st, const DPair *pairs, const uint32_t *amps,
+                                                         const uint64_t *d_n, uint64_t cap, ah_tm_params prm,
+                                                         double *tm_site) {
+    __shared__ double sdh[256], sds[256], tdh[256], tds[256];
+    __shared__ uint32_t sok[8], tok[8];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+        sdh[i] = g_stack.dh[i];
+        sds[i] = g_stack.ds[i];
+        tdh[i] = g_term.dh[i];
+        tds[i] = g_term.ds[i];
+    }
+    if (threadIdx.x < 8) {
+        sok[threadIdx.x] = g_stack.ok[threadIdx.x];
+        tok[threadIdx.x] = g_term.ok[threadIdx.x];
+    }
+    __syncthreads();
+    const TmConst k = tm_const(prm);
+    const uint64_t n = *d_n < cap ? *d_n : cap;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t w = blockIdx.x * (uint64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); w < 2 * n; w += nw) {
+        const uint64_t a = w >> 1;
+        const int side = (int)(w & 1);
+        const uint32_t seq = amps[4 * a], start = amps[4 * a + 1], end = amps[4 * a + 2], meta = amps[4 * a + 3];
+        const uint32_t pair = meta & 0xFFFFu, orient = (meta >> 16) & 0xFFu;
+        // upstream site: forward primer for FR/FF; downstream: reverse primer for FR/RR
+        const int pr = side == 0 ? ((orient == 0 || orient == 2) ? 0 : 1) : ((orient == 0 || orient == 3) ? 1 : 0);
+        const DPrimer &P = pairs[pair].prim[pr];
+        const int L = P.L;
+        const uint64_t s0 = st.d_seq_block0[seq] * 64;
+        const uint64_t ws = side == 0 ? (uint64_t)start : (uint64_t)end - (uint64_t)L;
+        bool has_n = false;
+        const uint64_t G = load_site(st, s0 + ws, L, &has_n);
+        // partner strand 3'->5' against the primer: complement of the plus
+        // strand for an upstream (plus) site, the plus strand reversed for a
+        // downstream (minus) site
+        const uint64_t lm = L == 32 ? ~0ull : ((1ull << (2 * L)) - 1);
+        const uint64_t Cc = side == 0 ? (G ^ (0xFFFFFFFFFFFFFFFFull & lm)) : reverse_codes(G, L);
+        double best = -INFINITY;
+        if (!has_n && P.D) {
+            const uint64_t base = primer_base_codes(P);
+            for (uint32_t v = lane; v < P.D; v += 64) {
+                double t;
+                if (duplex_tm(primer_variant(P, base, v), Cc, L, sdh, sds, sok, tdh, tds, tok, k, &t))
+                    best = t > best ? t : best;
+            }
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const double o = __shfl_xor(best, d, 64);
+            best = o > best ? o : best;
+        }
+        if (lane == 0) tm_site[2 * a + side] = best;
+    }
+}
+
+__global__ void ah_tm_finish_kernel(const double *tm_site, const uint64_t *d_n, uint64_t cap, ah_tm_params prm,
+                                    double *tm, uint8_t *pass) {
+    const uint64_t n = *d_n < cap ? *d_n : cap;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const double t1 = tm_site[2 * i], t2 = tm_site[2 * i + 1];
+        const double t = t1 < t2 ? t1 : t2;  // the weaker primer limits the amplicon
+        tm[i] = t;
+        pass[i] = prm.filter ? (uint8_t)(t >= prm.threshold_C) : (uint8_t)1;
+    }
+}
+
+extern "C" ah_status ah_tm_nn(const ah_store *st, ah_primer_set ps, const ah_amp *d_amps, const uint64_t *d_n_amps,
+                              uint64_t amp_cap, const ah_tm_params *p, double *d_tm, double *d_tm_site,
+                              uint8_t *d_pass, void *stream) {
+    if (!st || !ps || !p || !d_n_amps || (amp_cap && (!d_amps || !d_tm || !d_tm_site || !d_pass))) return AH_E_ARG;
+    if (p->saltcorr != 0 && p->saltcorr != 5) return AH_E_ARG;
+    for (uint32_t q = 0; q < ps->n_pairs; q++)
+        if (!ps->h_pairs[q].prim[0].D || !ps->h_pairs[q].prim[1].D) return AH_E_LIMIT;
+    if (!amp_cap) return AH_OK;
+    hipStream_t s = ah_stream(stream);
+    uint64_t wgs = (2 * amp_cap + 3) / 4;
+    if (wgs > 16384) wgs = 16384;
+    hipLaunchKernelGGL(ah_tm_site_kernel, dim3((unsigned)wgs), dim3(256), 0, s, *st, (const DPair *)ps->d_pairs,
+                       (const uint32_t *)d_amps, d_n_amps, amp_cap, *p, d_tm_site);
+    hipLaunchKernelGGL(ah_tm_finish_kernel, dim3(256), dim3(256), 0, s, (const double *)d_tm_site, d_n_amps, amp_cap,
+                       *p, d_tm, d_pass);
+    return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
+}
+
+// ---------------------------------------------------------------- explicit duplexes
+__device__ __forceinline__ int letter_code(char c) {
+    switch (c) {
+    case 'A': case 'a': return 0;
+    case 'C': case 'c': return 1;
+    case 'G': case 'g': return 2;
+    case 'T': case 't': return 3;
+    default: return -1;
+    }
+}
+
+__global__ void ah_tm_duplex_kernel(const char *seq, const char *cseq, const uint32_t *len, uint32_t n,
+                                    uint32_t stride, ah_tm_params prm, double *out) {
+    const TmConst k = tm_const(prm);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int L = (int)len[i];
+        uint64_t V = 0, C = 0;
+        bool okc = L >= 2 && L <= 32 && (uint32_t)L <= stride;
+        for (int j = 0; okc && j < L; j++) {
+            const int a = letter_code(seq[(uint64_t)i * stride + j]);
+            const int b = letter_code(cseq[(uint64_t)i * stride + j]);
+            if (a < 0 || b < 0) okc = false;
+            else {
+                V |= (uint64_t)a << (2 * j);
+                C |= (uint64_t)b << (2 * j);
+            }
+        }
+        double t = NAN;
+        if (okc && !duplex_tm(V, C, L, g_stack.dh, g_stack.ds, g_stack.ok, g_term.dh, g_term.ds, g_term.ok, k, &t))
+            t = NAN;
+        out[i] = t;
+    }
+}
+
+extern "C" ah_status ah_tm_duplex(const char *d_seq, const char *d_cseq, const uint32_t *d_len, uint32_t n,
+                                  uint32_t stride, const ah_tm_params *p, double *d_tm, void *stream) {
+    if (!p || (n && (!d_seq || !d_cseq || !d_len || !d_tm))) return AH_E_ARG;
+    if (p->saltcorr != 0 && p->saltcorr != 5) return AH_E_ARG;
+    if (!n) return AH_OK;
+    unsigned blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(ah_tm_duplex_kernel, dim3(blocks), dim3(256), 0, ah_stream(stream), d_seq, d_cseq, d_len, n,
+                       stride, *p, d_tm);
+    return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
+}

@@ -1,0 +1,193 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs -- element by element, bit-exact for hits, amplicons,
+sequences and barcodes, |dTm| <= 1e-9 C with identical pass/fail."""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_00170_amd import synth
+from paper_2511_00170_amd.synth import ExtractSpec, PairSpec, TmSpec
+from tests import _parity as P
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def ah():
+    _need_gpu()
+    from paper_2511_00170_amd import ah as mod
+    return mod
+
+
+def _concat(seqs):
+    arrs = [np.frombuffer(s.encode() if isinstance(s, str) else s, np.uint8) for s in seqs]
+    off = np.zeros(len(arrs) + 1, np.uint64)
+    off[1:] = np.cumsum([len(a) for a in arrs])
+    buf = np.concatenate(arrs) if arrs else np.zeros(0, np.uint8)
+    return buf, off
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ pack
+def test_pack_roundtrip_with_n_and_case(ah):
+    rng = np.random.default_rng(1)
+    seqs = []
+    for L in [0, 1, 31, 32, 33, 63, 64, 65, 127, 4095, 4096, 4097, 10000, 70000]:
+        s = rng.choice(list("ACGTacgtNnRY-"), size=L, p=[.2, .2, .2, .2, .03, .03, .03, .03, .02, .02, .01, .01,
+                                                       .02]).tolist()
+        seqs.append("".join(s))
+    _say("pack roundtrip", len(seqs))
+    st = ah.Store.from_ascii(seqs)
+    for i, s in enumerate(seqs):
+        want = "".join(c.upper() if c.upper() in "ACGT" else "N" for c in s).encode()
+        assert st.unpack(i) == want, i
+
+
+# ------------------------------------------------------------------ scan
+ADVERSARIAL_PAIRS = [
+    PairSpec("ACGTRYACGTNNACG", "TTGCAKCCAGTMA", k=2, clamp=3, min_len=20, max_len=600),
+    PairSpec("AAAAAAAAAA", "TTTTTTTTTT", k=1, clamp=2, min_len=10, max_len=300),   # homopolymer storms
+    PairSpec("NNNNNNNN", "ACGTACGTACGTACGTACGTACGTACGTACGT", k=0, clamp=0, min_len=1, max_len=100),
+    PairSpec("GATTACAGATTACAGATTACAGATTACAGATT", "CC", k=3, clamp=2, min_len=5, max_len=5000),
+]
+
+
+@pytest.mark.parametrize("pi", range(len(ADVERSARIAL_PAIRS)))
+def test_scan_pair_tm_adversarial(ah, pi):
+    rng = np.random.default_rng(100 + pi)
+    pair = ADVERSARIAL_PAIRS[pi]
+    seqs = []
+    # lengths around tile (4096) and block (64) boundaries, sequences shorter than the primers
+    for L in [0, 5, 31, 64, 65, 100, 4095, 4096, 4097, 4160, 8191, 8192, 12000, 20000]:
+        s = synth.random_ascii(rng, L, gc=0.5).tobytes().decode()
+        seqs.append(s)
+    seqs.append("A" * 9000)                      # poly-A
+    seqs.append("T" * 5000 + "A" * 5000)         # poly-T then poly-A
+    s = list(synth.random_ascii(rng, 6000).tobytes().decode())
+    for j in rng.choice(6000, 60, replace=False):
+        s[j] = "N"                                # scattered N
+    seqs.append("".join(s))
+    # planted sites across a tile boundary
+    s = list(synth.random_ascii(rng, 9000).tobytes().decode())
+    F = "".join(synth._IUPAC_SETS[c][0] for c in pair.fwd)
+    R = synth.revcomp_str("".join(synth._IUPAC_SETS[c][-1] for c in pair.rev))
+    for at in [0, 4096 - len(F) // 2, 4096 - 3, 8191 - len(F) + 1]:
+        s[at:at + len(F)] = F
+    for at in [300, 4096 - 2, 8000]:
+        s[at:at + len(R)] = R
+    seqs.append("".join(s)[:9000])
+    buf, off = _concat(seqs)
+    _say("adversarial pair", pi)
+    st = ah.Store.from_ascii(seqs)
+    tm = TmSpec(threshold_C=40.0)
+    r, o = P.full_parity(st, buf, off, [pair], 0xF, tm, ExtractSpec(trim=True, fb_len=7, rb_len=9))
+    assert len(o.hits) > 0
+
+
+def test_tiny_config_full_path(ah):
+    wl = synth.gen_config(1)
+    buf, off = wl.concat()
+    _say("config tiny")
+    st = ah.Store.from_ascii([buf[int(off[i]):int(off[i + 1])] for i in range(wl.n_seqs)])
+    r, o = P.full_parity(st, buf, off, wl.pairs, wl.orient_mask, wl.tm, ExtractSpec(trim=False, fb_len=16, rb_len=16))
+    assert len(o.amps) >= len(wl.truth["amplicons"])
+
+
+def test_genome_config_reduced_full_path(ah):
+    wl = synth.gen_config(2, n_seqs=60, len_scale=0.02)   # 60 x 60-120 kb
+    buf, off = wl.concat()
+    _say("config genome reduced", wl.total_bases)
+    st = ah.Store.from_workload(wl)
+    r, o = P.full_parity(st, buf, off, wl.pairs, wl.orient_mask, wl.tm, ExtractSpec(trim=True, fb_len=16, rb_len=16))
+    assert len(o.amps) > 20
+
+
+def test_dense_config_reduced_full_path(ah):
+    wl = synth.gen_config(4, n_seqs=8, len_scale=0.05)
+    buf, off = wl.concat()
+    _say("config dense reduced", wl.total_bases)
+    st = ah.Store.from_workload(wl)
+    r, o = P.full_parity(st, buf, off, wl.pairs, wl.orient_mask, wl.tm, wl.extract)
+    n_units = sum(len(t["units"]) for t in wl.truth["operons"])
+    assert len(o.amps) == n_units
+
+
+def test_many_pairs_batch_reduced(ah):
+    wl = synth.gen_config(3, len_scale=1e-4)   # ~0.9 Mb, 64 pairs
+    buf, off = wl.concat()
+    _say("config batch reduced", wl.total_bases, wl.n_seqs)
+    st = ah.Store.from_workload(wl)
+    P.full_parity(st, buf, off, wl.pairs, wl.orient_mask, wl.tm, ExtractSpec())
+
+
+def test_overflow_rerun_is_exact(ah):
+    wl = synth.gen_config(1)
+    buf, off = wl.concat()
+    st = ah.Store.from_workload(wl)
+    _say("overflow rerun")
+    small = ah.Caps(hits=3, amps=2, seq_bytes=10)
+    r = P.gpu_run(st, wl.pairs, wl.orient_mask, wl.tm, ExtractSpec(fb_len=4, rb_len=4), caps=small)
+    o = oracle.run(buf, off, wl.pairs, wl.orient_mask, wl.tm, ExtractSpec(fb_len=4, rb_len=4))
+    P.compare_hits(r["hits"], o.hits, o.mm)
+    P.compare_amps(r["amps"], o.amps)
+    P.compare_extract(r, o.ext)
+
+
+def test_subset_scan_matches_full(ah):
+    wl = synth.gen_config(1)
+    buf, off = wl.concat()
+    st = ah.Store.from_workload(wl)
+    sub = np.array(sorted(np.random.default_rng(3).choice(wl.n_seqs, 37, replace=False)), np.uint32)
+    _say("subset scan")
+    r_sub = P.gpu_run(st, wl.pairs, wl.orient_mask, wl.tm, subset=sub)
+    r_all = P.gpu_run(st, wl.pairs, wl.orient_mask, wl.tm)
+    g_all = ah.hits_canonical(r_all["hits"])
+    g_all = g_all[np.isin(g_all[:, 0], sub)]
+    assert (ah.hits_canonical(r_sub["hits"]) == g_all).all()
+    a_all = ah.amps_array(r_all["amps"])
+    assert (ah.amps_array(r_sub["amps"]) == a_all[np.isin(a_all[:, 0], sub)]).all()
+
+
+# ------------------------------------------------------------------ Tm
+def test_tm_duplex_documented_value(ah):
+    comp = {"A": "T", "C": "G", "G": "C", "T": "A"}
+    seq = "CGTTCCAAAGATGTGGGCATGAGCTTAC"
+    t = ah.tm_duplex([seq], ["".join(comp[c] for c in seq)], TmSpec(dnac1_nM=25, dnac2_nM=25))
+    assert "%.2f" % t[0] == "60.32"
+
+
+def test_tm_duplex_random_mismatches_match_oracle(ah):
+    """Every tabulated stack (Watson-Crick, internal and terminal mismatch)
+    is exercised; the GPU's own copy of the tables must agree with the oracle's."""
+    rng = np.random.default_rng(7)
+    seqs, cseqs = [], []
+    comp = {"A": "T", "C": "G", "G": "C", "T": "A"}
+    for _ in range(20000):
+        L = int(rng.integers(2, 33))
+        s = "".join(rng.choice(list("ACGT"), size=L))
+        c = [comp[x] for x in s]
+        for j in rng.choice(L, size=int(rng.integers(0, min(L, 4) + 1)), replace=False):
+            c[j] = rng.choice([b for b in "ACGT" if b != c[j]])
+        seqs.append(s)
+        cseqs.append("".join(c))
+    for cond in [TmSpec(), TmSpec(na_mM=10, k_mM=40, tris_mM=10, mg_mM=1.5, dntps_mM=0.2, dnac1_nM=500, dnac2_nM=50),
+                 TmSpec(saltcorr=0)]:
+        g = ah.tm_duplex(seqs, cseqs, cond)
+        o = np.array([oracle.tm_duplex(s, c, cond) for s, c in zip(seqs, cseqs)])
+        assert (np.isnan(g) == np.isnan(o)).all()
+        fin = ~np.isnan(o)
+        assert fin.sum() > 5000
+        assert np.abs(g[fin] - o[fin]).max() <= P.TM_TOL
