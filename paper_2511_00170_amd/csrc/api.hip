@@ -78,7 +78,9 @@ static void make_pattern(const int *X, int L, int k, int clamp, int minus, uint3
     d->lmask = L == 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
     for (int j = 0; j < clamp; j++) d->clampmask |= 1u << (minus ? j : L - 1 - j);
     int W = clamp < AH_WMAX ? clamp : AH_WMAX;
-    int shift = minus ? 0 : L - W;
+    // clamp site q = window start + shift; for the plus strand the filter's
+    // first position, for W = 0 the last base (q must lie inside the window)
+    int shift = minus ? 0 : L - (W > 0 ? W : 1);
     for (int i = 0; i < W; i++) d->fcode[i] = (uint8_t)(minus ? X[i] : X[L - W + i]);
     int kk = k > 255 ? 255 : k;
     d->meta = (uint32_t)L | ((uint32_t)kk << 8) | ((uint32_t)W << 16) | ((uint32_t)shift << 24);

@@ -60,7 +60,8 @@ def test_pack_roundtrip_with_n_and_case(ah):
 ADVERSARIAL_PAIRS = [
     PairSpec("ACGTRYACGTNNACG", "TTGCAKCCAGTMA", k=2, clamp=3, min_len=20, max_len=600),
     PairSpec("AAAAAAAAAA", "TTTTTTTTTT", k=1, clamp=2, min_len=10, max_len=300),   # homopolymer storms
-    PairSpec("NNNNNNNN", "ACGTACGTACGTACGTACGTACGTACGTACGT", k=0, clamp=0, min_len=1, max_len=100),
+    # no clamp: every window is a candidate; F matches half of all positions
+    PairSpec("NNRNN", "ACGTACGTACGTACGTACGTACGTACGTACGT", k=0, clamp=0, min_len=20, max_len=100),
     PairSpec("GATTACAGATTACAGATTACAGATTACAGATT", "CC", k=3, clamp=2, min_len=5, max_len=5000),
 ]
 
