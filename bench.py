@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-bases", type=float, default=1.0e9)
     ap.add_argument("--stages", default="scan,pair,tm,extract")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 1 GiB device copy (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -68,6 +70,13 @@ def main():
     from paper_2511_00170_amd import ah, synth
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src_t = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        torch.cuda.synchronize()
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
     t0 = time.time()
     wl = synth.gen_config(args.config, n_seqs=args.n_seqs, len_scale=args.len_scale)
     total = wl.total_bases
