@@ -23,7 +23,9 @@
 #ifndef AH_H
 #define AH_H
 
+#ifndef __HIPCC_RTC__
 #include <stdint.h>
+#endif
 
 #ifdef __cplusplus
 extern "C" {
@@ -118,6 +120,18 @@ typedef struct ah_primer_set_ *ah_primer_set;
 ah_status ah_primers_compile(const ah_pair_spec *h_pairs, uint32_t n_pairs, ah_primer_set *out);
 void ah_primers_free(ah_primer_set ps);
 uint32_t ah_primers_count(ah_primer_set ps);
+
+/* Optional set-up step: compile, with hipRTC, a scan kernel whose clamp
+ * pre-filter has this primer set's IUPAC codes as compile-time constants
+ * (each set test folds into one bit operation) and use it for later
+ * ah_scan_primers calls with this set on the current device.  Results are
+ * identical to the generic kernel.  Blocks for the compile (about a second);
+ * AH_E_HIP if hipRTC or module loading fails (the generic kernel stays). */
+ah_status ah_primers_jit(ah_primer_set ps);
+
+/* Switch between the specialised (on != 0, needs ah_primers_jit first) and
+ * the generic scan kernel for this set. */
+ah_status ah_primers_use_jit(ah_primer_set ps, int32_t on);
 
 /* ------------------------------------------------------------------------
  * Scan (Supplementary, "Primer matching and clamp logic"; mismatches are

@@ -77,6 +77,8 @@ _sig("ah_unpack", I32, C.POINTER(ah_store), U32, U64, U64, VP, VP)
 _sig("ah_primers_compile", I32, C.POINTER(ah_pair_spec), U32, C.POINTER(VP))
 _sig("ah_primers_free", None, VP)
 _sig("ah_primers_count", U32, VP)
+_sig("ah_primers_jit", I32, VP)
+_sig("ah_primers_use_jit", I32, VP, I32)
 _sig("ah_scan_ws_size", I32, C.POINTER(ah_store), U32, C.POINTER(U64))
 _sig("ah_scan_primers", I32, C.POINTER(ah_store), VP, VP, U32, VP, U64, VP, VP, U64, VP)
 _sig("ah_pair_ws_size", I32, C.POINTER(ah_store), VP, U64, C.POINTER(U64))
@@ -88,7 +90,7 @@ _sig("ah_extract", I32, C.POINTER(ah_store), VP, VP, VP, U64, VP, C.POINTER(ah_e
      VP, VP, VP, VP, VP, U64, VP)
 
 EXPORTED = ["ah_status_str", "ah_version", "ah_pack_layout", "ah_pack_begin", "ah_pack", "ah_pack_finish",
-            "ah_unpack", "ah_primers_compile", "ah_primers_free", "ah_primers_count", "ah_scan_ws_size",
+            "ah_unpack", "ah_primers_compile", "ah_primers_free", "ah_primers_count", "ah_primers_jit", "ah_primers_use_jit", "ah_scan_ws_size",
             "ah_scan_primers", "ah_pair_ws_size", "ah_pair_amplicons", "ah_tm_nn", "ah_tm_duplex",
             "ah_extract_ws_size", "ah_extract"]
 
@@ -209,7 +211,10 @@ class Store:
 # Primer sets
 # ---------------------------------------------------------------------------
 class PrimerSet:
-    def __init__(self, pairs):
+    """Compiled primer pairs.  jit=True also compiles (hipRTC) a scan kernel
+    specialised to these pairs; results are identical to the generic kernel."""
+
+    def __init__(self, pairs, jit: bool = False):
         self.pairs = list(pairs)
         arr = (ah_pair_spec * len(self.pairs))()
         self._keep = []
@@ -220,6 +225,17 @@ class PrimerSet:
         h = VP()
         check(_lib.ah_primers_compile(arr, len(self.pairs), C.byref(h)), "ah_primers_compile")
         self.h = h
+        self.jit = False
+        if jit:
+            self.enable_jit()
+
+    def enable_jit(self):
+        check(_lib.ah_primers_jit(self.h), "ah_primers_jit")
+        self.jit = True
+
+    def use_jit(self, on: bool):
+        check(_lib.ah_primers_use_jit(self.h, int(bool(on))), "ah_primers_use_jit")
+        self.jit = bool(on)
 
     def __len__(self):
         return len(self.pairs)

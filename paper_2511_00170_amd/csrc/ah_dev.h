@@ -1,0 +1,93 @@
+// Device-visible types and helpers of libah.so.  Self-contained so that the
+// same text can be compiled by hipcc and, for primer-set specialised scan
+// kernels, by hipRTC at run time.
+#pragma once
+
+#ifndef __HIPCC_RTC__
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#else
+typedef __hip_internal::uint8_t uint8_t;
+typedef __hip_internal::uint16_t uint16_t;
+typedef __hip_internal::uint32_t uint32_t;
+typedef __hip_internal::uint64_t uint64_t;
+typedef __hip_internal::int32_t int32_t;
+typedef __hip_internal::int64_t int64_t;
+#endif
+
+#include "ah.h"
+
+// Pre-filter width: at most this many clamp positions are tested with
+// bit-parallel word operations before a candidate window is verified.
+#define AH_WMAX 6
+// Bases per wave tile = 64 blocks x 64 bases; one block per lane.
+#define AH_TILE_BLOCKS 64
+#define AH_TILE_BASES (AH_TILE_BLOCKS * 64)
+// Candidate queue entries per wave (verification batch).
+#define AH_QCAP 1024
+#define AH_MAXL 32
+// Variants per primer the Tm kernel will enumerate.
+#define AH_MAX_VARIANTS (1u << 24)
+
+// One oriented pattern: pair q, kind (bit0 reverse primer, bit1 minus strand).
+struct alignas(16) DPat {
+    uint32_t P[4];       // bit j: base A/C/G/T allowed at pattern position j
+    uint32_t clampmask;  // positions that must match
+    uint32_t lmask;      // bits [0, L)
+    uint32_t meta;       // L | k << 8 | W << 16 | shift << 24
+    uint32_t pk;         // pair | kind << 16
+    uint8_t fcode[8];    // IUPAC sets of the W filter positions, from the clamp site on
+    uint32_t pad[2];
+};
+static_assert(sizeof(DPat) == 48, "DPat layout");
+
+// One primer for Tm variant enumeration.
+struct DPrimer {
+    uint8_t L;
+    uint8_t n_deg;           // degenerate positions
+    uint8_t pad[2];
+    uint32_t D;              // number of concrete variants (<= AH_MAX_VARIANTS)
+    uint8_t code[AH_MAXL];   // 2-bit base of each concrete position
+    uint8_t deg_pos[AH_MAXL];
+    uint8_t deg_n[AH_MAXL];
+    uint8_t deg_base[AH_MAXL][4];
+};
+
+struct DPair {
+    uint32_t min_len, max_len;
+    uint8_t Lf, Lr, k, clamp;
+    DPrimer prim[2];  // 0 forward, 1 reverse
+};
+
+__device__ __forceinline__ uint32_t ah_lane() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t ah_mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T ah_wave_incl_sum(T v) {
+    const uint32_t lane = ah_lane();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T u = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d) v += u;
+    }
+    return v;
+}
+
+// A wave-local ordering point for LDS written by one lane and read by another.
+__device__ __forceinline__ void ah_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// N-side-table lookup: 64-bit mask of N positions of block b (0 if none).
+__device__ __forceinline__ uint64_t ah_block_nmask(const ah_store &st, uint64_t b) {
+    uint32_t w = st.d_nbits[b >> 5];
+    uint32_t bit = 1u << (b & 31);
+    if (!(w & bit)) return 0;
+    uint64_t r = (uint64_t)st.d_nrank[b >> 5] + __popc(w & (bit - 1));
+    return r < st.nmask_cap ? st.d_nmask[r] : ~0ull;
+}

@@ -4,49 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "ah.h"
-
-// Pre-filter width: at most this many clamp positions are tested with
-// bit-parallel word operations before a candidate window is verified.
-#define AH_WMAX 6
-// Bases per wave tile = 64 blocks x 64 bases; one block per lane.
-#define AH_TILE_BLOCKS 64
-#define AH_TILE_BASES (AH_TILE_BLOCKS * 64)
-// Candidate queue entries per wave (verification batch).
-#define AH_QCAP 1024
-#define AH_MAXL 32
-// Variants per primer the Tm kernel will enumerate.
-#define AH_MAX_VARIANTS (1u << 24)
-
-// One oriented pattern: pair q, kind (bit0 reverse primer, bit1 minus strand).
-struct alignas(16) DPat {
-    uint32_t P[4];       // bit j: base A/C/G/T allowed at pattern position j
-    uint32_t clampmask;  // positions that must match
-    uint32_t lmask;      // bits [0, L)
-    uint32_t meta;       // L | k << 8 | W << 16 | shift << 24
-    uint32_t pk;         // pair | kind << 16
-    uint8_t fcode[8];    // IUPAC sets of the W filter positions, from the clamp site on
-    uint32_t pad[2];
-};
-static_assert(sizeof(DPat) == 48, "DPat layout");
-
-// One primer for Tm variant enumeration.
-struct DPrimer {
-    uint8_t L;
-    uint8_t n_deg;           // degenerate positions
-    uint8_t pad[2];
-    uint32_t D;              // number of concrete variants (<= AH_MAX_VARIANTS)
-    uint8_t code[AH_MAXL];   // 2-bit base of each concrete position
-    uint8_t deg_pos[AH_MAXL];
-    uint8_t deg_n[AH_MAXL];
-    uint8_t deg_base[AH_MAXL][4];
-};
-
-struct DPair {
-    uint32_t min_len, max_len;
-    uint8_t Lf, Lr, k, clamp;
-    DPrimer prim[2];  // 0 forward, 1 reverse
-};
+#include "ah_dev.h"
 
 struct ah_primer_set_ {
     uint32_t n_pairs;
@@ -59,7 +17,11 @@ struct ah_primer_set_ {
     DPair *h_pairs;
     DPat *h_pats;
     int device;
+    void *jit;    // primer-set specialised scan kernel (ah_primers_jit), or null
+    int use_jit;
 };
+
+void ah_jit_free(void *jit);
 
 // ---------------------------------------------------------------- helpers
 #define AH_CHECK_HIP(x)                         \
@@ -76,30 +38,6 @@ static inline int ah_bits_for(uint64_t n) {  // bits to represent values 0..n-1
     int b = 0;
     while (b < 64 && (n > (1ull << b))) b++;
     return b;
-}
-
-__device__ __forceinline__ uint32_t ah_lane() { return __lane_id(); }
-
-__device__ __forceinline__ uint32_t ah_mbcnt(uint64_t m) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-template <typename T>
-__device__ __forceinline__ T ah_wave_incl_sum(T v) {
-    const uint32_t lane = ah_lane();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        T u = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += u;
-    }
-    return v;
-}
-
-// A wave-local ordering point for LDS written by one lane and read by another.
-__device__ __forceinline__ void ah_wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Fill kernel (graph-safe replacement for memset).
@@ -133,11 +71,3 @@ ah_status ah_exclusive_scan(const TI *d_in, TO *d_out, const uint64_t *d_n, uint
 // outputs (the last one is the total).
 void ah_scan_small_u64(const uint64_t *d_in, uint64_t *d_out, uint64_t n, hipStream_t s);
 
-// N-side-table lookup: 64-bit mask of N positions of block b (0 if none).
-__device__ __forceinline__ uint64_t ah_block_nmask(const ah_store &st, uint64_t b) {
-    uint32_t w = st.d_nbits[b >> 5];
-    uint32_t bit = 1u << (b & 31);
-    if (!(w & bit)) return 0;
-    uint64_t r = (uint64_t)st.d_nrank[b >> 5] + __popc(w & (bit - 1));
-    return r < st.nmask_cap ? st.d_nmask[r] : ~0ull;
-}

@@ -179,6 +179,7 @@ extern "C" void ah_primers_free(ah_primer_set ps) {
     if (!ps) return;
     if (ps->d_pats) (void)hipFree(ps->d_pats);
     if (ps->d_pairs) (void)hipFree(ps->d_pairs);
+    ah_jit_free(ps->jit);
     delete[] ps->h_pats;
     delete[] ps->h_pairs;
     delete ps;

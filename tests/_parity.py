@@ -9,10 +9,10 @@ import oracle
 TM_TOL = 1e-9  # degrees C, FP64 (same operation order on both sides)
 
 
-def gpu_run(store, pairs, orient_mask, tm, ex=None, subset=None, caps=None):
+def gpu_run(store, pairs, orient_mask, tm, ex=None, subset=None, caps=None, jit=False):
     from paper_2511_00170_amd import ah
     import torch
-    ps = ah.PrimerSet(pairs)
+    ps = ah.PrimerSet(pairs, jit=jit)
     sub = None
     if subset is not None:
         sub = torch.from_numpy(np.asarray(subset, np.uint32).view(np.int32)).cuda()
@@ -67,9 +67,9 @@ def compare_extract(r, e):
     assert (r["rprimer"] == e.rprimer).all()
 
 
-def full_parity(store, ascii_buf, off, pairs, orient_mask, tm, ex=None, n_threads=None):
+def full_parity(store, ascii_buf, off, pairs, orient_mask, tm, ex=None, n_threads=None, jit=False):
     """Run both sides on the same input; assert every output agrees."""
-    r = gpu_run(store, pairs, orient_mask, tm, ex)
+    r = gpu_run(store, pairs, orient_mask, tm, ex, jit=jit)
     o = oracle.run(ascii_buf, off, pairs, orient_mask, tm, ex, n_threads=n_threads)
     compare_hits(r["hits"], o.hits, o.mm)
     compare_amps(r["amps"], o.amps)

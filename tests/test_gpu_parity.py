@@ -66,8 +66,12 @@ ADVERSARIAL_PAIRS = [
 ]
 
 
+KERNELS = ["generic", "jit"]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("pi", range(len(ADVERSARIAL_PAIRS)))
-def test_scan_pair_tm_adversarial(ah, pi):
+def test_scan_pair_tm_adversarial(ah, pi, kernel):
     rng = np.random.default_rng(100 + pi)
     pair = ADVERSARIAL_PAIRS[pi]
     seqs = []
@@ -91,10 +95,11 @@ def test_scan_pair_tm_adversarial(ah, pi):
         s[at:at + len(R)] = R
     seqs.append("".join(s)[:9000])
     buf, off = _concat(seqs)
-    _say("adversarial pair", pi)
+    _say("adversarial pair", pi, kernel)
     st = ah.Store.from_ascii(seqs)
     tm = TmSpec(threshold_C=40.0)
-    r, o = P.full_parity(st, buf, off, [pair], 0xF, tm, ExtractSpec(trim=True, fb_len=7, rb_len=9))
+    r, o = P.full_parity(st, buf, off, [pair], 0xF, tm, ExtractSpec(trim=True, fb_len=7, rb_len=9),
+                         jit=kernel == "jit")
     assert len(o.hits) > 0
 
 
@@ -107,12 +112,14 @@ def test_tiny_config_full_path(ah):
     assert len(o.amps) >= len(wl.truth["amplicons"])
 
 
-def test_genome_config_reduced_full_path(ah):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_genome_config_reduced_full_path(ah, kernel):
     wl = synth.gen_config(2, n_seqs=60, len_scale=0.02)   # 60 x 60-120 kb
     buf, off = wl.concat()
-    _say("config genome reduced", wl.total_bases)
+    _say("config genome reduced", wl.total_bases, kernel)
     st = ah.Store.from_workload(wl)
-    r, o = P.full_parity(st, buf, off, wl.pairs, wl.orient_mask, wl.tm, ExtractSpec(trim=True, fb_len=16, rb_len=16))
+    r, o = P.full_parity(st, buf, off, wl.pairs, wl.orient_mask, wl.tm, ExtractSpec(trim=True, fb_len=16, rb_len=16),
+                         jit=kernel == "jit")
     assert len(o.amps) > 20
 
 
@@ -126,12 +133,13 @@ def test_dense_config_reduced_full_path(ah):
     assert len(o.amps) == n_units
 
 
-def test_many_pairs_batch_reduced(ah):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_many_pairs_batch_reduced(ah, kernel):
     wl = synth.gen_config(3, len_scale=1e-4)   # ~0.9 Mb, 64 pairs
     buf, off = wl.concat()
-    _say("config batch reduced", wl.total_bases, wl.n_seqs)
+    _say("config batch reduced", wl.total_bases, wl.n_seqs, kernel)
     st = ah.Store.from_workload(wl)
-    P.full_parity(st, buf, off, wl.pairs, wl.orient_mask, wl.tm, ExtractSpec())
+    P.full_parity(st, buf, off, wl.pairs, wl.orient_mask, wl.tm, ExtractSpec(), jit=kernel == "jit")
 
 
 def test_overflow_rerun_is_exact(ah):
