@@ -23,8 +23,6 @@ typedef __hip_internal::int64_t int64_t;
 // Bases per wave tile = 64 blocks x 64 bases; one block per lane.
 #define AH_TILE_BLOCKS 64
 #define AH_TILE_BASES (AH_TILE_BLOCKS * 64)
-// Candidate queue entries per wave (verification batch).
-#define AH_QCAP 1024
 #define AH_MAXL 32
 // Variants per primer the Tm kernel will enumerate.
 #define AH_MAX_VARIANTS (1u << 24)

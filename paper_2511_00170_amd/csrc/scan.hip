@@ -5,8 +5,8 @@
 //    (scalar) branch;
 //  - ah_primers_jit() compiles, with hipRTC, a kernel whose clamp codes are
 //    compile-time constants, so each set test folds into the running AND.
-// Both share the candidate queue and the exact verification, so they produce
-// the same hits.
+// Both share the exact per-candidate verification, so they produce the same
+// hits.
 #include <hip/hiprtc.h>
 #include <stdio.h>
 #include <string.h>
@@ -36,6 +36,7 @@ __device__ __forceinline__ uint32_t ah_pick(uint32_t eA, uint32_t eC, uint32_t e
 struct GenericFilter {
     const DPat *sPat;
     const DPat *gPat;
+    uint32_t n_lds;
     __device__ uint32_t groups(const ScanArgs &a) const { return a.n_groups; }
     __device__ __forceinline__ void filter(uint32_t g, const uint32_t (&Sh)[AH_WMAX][2],
                                            const uint32_t (&Sl)[AH_WMAX][2], uint32_t v0, uint32_t v1,
@@ -44,7 +45,7 @@ struct GenericFilter {
 #pragma unroll
         for (int x = 0; x < 4; x++) {
             const uint32_t X = 4 * g + (uint32_t)x;
-            const DPat *P = X < AH_LDS_PATS ? &sPat[X] : &gPat[X];
+            const DPat *P = X < n_lds ? &sPat[X] : &gPat[X];
             const uint32_t meta = __builtin_amdgcn_readfirstlane(P->meta);
             // positions past a pattern's own W read as N (every base matches)
             const uint32_t wx = (meta >> 16) & 0xFFu;
@@ -77,12 +78,13 @@ struct GenericFilter {
 
 __global__ void __launch_bounds__(256) ah_scan_kernel(ScanArgs a) {
     __shared__ DPat sPat[AH_LDS_PATS];
-    __shared__ uint32_t sH[4][2 * AH_TILE_BLOCKS + 2];
-    __shared__ uint32_t sL[4][2 * AH_TILE_BLOCKS + 2];
-    __shared__ uint32_t sQ[4][AH_QCAP];
-    ah_stage_patterns(a, sPat);
-    GenericFilter f{sPat, a.pats};
-    ah_scan_body(a, f, sPat, sH, sL, sQ);
+    __shared__ TileCtx sCtx[4][AH_NCTX];
+    __shared__ uint32_t sQ[4][AH_QCAP][3];
+    __shared__ uint32_t sW[4][AH_NCTX][2][AH_TW];
+    ah_stage_patterns(a, sPat, AH_LDS_PATS);
+    const uint32_t n_lds = a.n_pats < AH_LDS_PATS ? a.n_pats : AH_LDS_PATS;
+    GenericFilter f{sPat, a.pats, n_lds};
+    ah_scan_body(a, f, sPat, n_lds, sCtx, sQ, sW);
 }
 
 // ---------------------------------------------------------------- tile table
@@ -157,14 +159,16 @@ static std::string jit_source(const ah_primer_set_ *ps) {
     }
     s += "    default: for (int w = 0; w < 8; w++) C[w] = 0u;\n";
     s += "    }\n  }\n};\n";
+    const uint32_t n_lds = ps->n_pats < AH_LDS_PATS ? ps->n_pats : AH_LDS_PATS;
+    s += "#define AH_JIT_LDS_PATS " + std::to_string(n_lds) + "u\n";
     s += "extern \"C\" __global__ void __launch_bounds__(256) ah_scan_jit(ScanArgs a) {\n"
-         "  __shared__ DPat sPat[AH_LDS_PATS];\n"
-         "  __shared__ uint32_t sH[4][2 * AH_TILE_BLOCKS + 2];\n"
-         "  __shared__ uint32_t sL[4][2 * AH_TILE_BLOCKS + 2];\n"
-         "  __shared__ uint32_t sQ[4][AH_QCAP];\n"
-         "  ah_stage_patterns(a, sPat);\n"
+         "  __shared__ DPat sPat[AH_JIT_LDS_PATS];\n"
+         "  __shared__ TileCtx sCtx[4][AH_NCTX];\n"
+         "  __shared__ uint32_t sQ[4][AH_QCAP][3];\n"
+         "  __shared__ uint32_t sW[4][AH_NCTX][2][AH_TW];\n"
+         "  ah_stage_patterns(a, sPat, AH_JIT_LDS_PATS);\n"
          "  JitFilter f;\n"
-         "  ah_scan_body(a, f, sPat, sH, sL, sQ);\n"
+         "  ah_scan_body(a, f, sPat, AH_JIT_LDS_PATS, sCtx, sQ, sW);\n"
          "}\n";
     return s;
 }

@@ -10,11 +10,14 @@
 // reads it with one 128-bit load).  For its 64 clamp sites q a lane builds
 // bit-vectors "base q+i is in IUPAC set m" from funnel shifts of the two bit
 // planes and ANDs them over the first W clamp positions of each oriented
-// pattern -- a window that fails this pre-filter can never be a hit.
-// Surviving (pattern, q) pairs are compacted into an LDS queue with a wave
-// prefix sum; each queued candidate is verified exactly (full window against
-// the pattern's per-base masks, full clamp, N bases, substitution count) and
-// hits are appended with one atomic per wave and verification round.
+// pattern -- a window that fails this pre-filter can never be a hit.  A lane
+// whose candidate mask for a pattern is non-zero appends (mask, pattern,
+// lane, tile) to a per-wave LDS queue -- one ballot per pattern gives the
+// slots, no prefix sums.  The queue spans several tiles and is verified in
+// full-wave rounds: each entry's windows are read back from the (L2-resident)
+// store and checked exactly against the pattern's per-base masks, the full
+// clamp, N bases and the substitution count.  Hits are rare and appended
+// with one atomic each.
 #pragma once
 
 #include "ah_dev.h"
@@ -48,36 +51,51 @@ __device__ __forceinline__ uint32_t ah_and_set(uint32_t acc, uint32_t h, uint32_
     return acc & ((h & high) | (~h & low));
 }
 
+// Per-tile context kept for deferred verification.
 struct TileCtx {
+    uint64_t gbase;  // store position (block index * 64) of the tile's first base
     uint32_t seq;
     uint32_t len;
-    int64_t pos0;    // sequence position of the tile's first base
-    uint64_t gblk0;  // store block of the tile's first base
-    bool has_n;
+    uint32_t pos0;   // sequence position of the tile's first base
+    uint32_t has_n;
 };
 
-// Sequence cursor over the tile list of one wave.
+#ifndef AH_QCAP
+#define AH_QCAP 128                       // queue entries per wave (>= 128)
+#endif
+#ifndef AH_NCTX
+#define AH_NCTX 4                         // tiles whose candidates may wait in the queue (<= 4)
+#endif
+#define AH_TW (2 * AH_TILE_BLOCKS + 2)    // words per plane of a tile (+ one word each side)
+
+__device__ __forceinline__ uint32_t ah_uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t ah_uni64(uint64_t x) {
+    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(x >> 32)) << 32) |
+           __builtin_amdgcn_readfirstlane((uint32_t)x);
+}
+
+// Sequence cursor over the tile list of one wave (wave-uniform values).
 struct SeqCursor {
     uint32_t i;        // list index
     uint32_t seq;
     uint32_t len;
-    uint64_t nblk;
+    uint32_t nblk;
     uint64_t blk0;
     uint64_t tp0, tp1; // tile_pref[i], tile_pref[i + 1]
 
     __device__ void load(const ScanArgs &a) {
-        seq = a.list ? a.list[i] : i;
-        len = a.st.d_seq_len[seq];
-        nblk = ((uint64_t)len + 63) / 64;
-        blk0 = a.st.d_seq_block0[seq];
-        tp0 = a.tile_pref[i];
-        tp1 = a.tile_pref[i + 1];
+        seq = ah_uni(a.list ? a.list[i] : i);
+        len = ah_uni(a.st.d_seq_len[seq]);
+        nblk = (len + 63u) / 64u;
+        blk0 = ah_uni64(a.st.d_seq_block0[seq]);
+        tp0 = ah_uni64(a.tile_pref[i]);
+        tp1 = ah_uni64(a.tile_pref[i + 1]);
     }
     __device__ void init(const ScanArgs &a, uint64_t t) {
         uint32_t lo = 0, hi = a.n_list;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (a.tile_pref[mid] <= t) lo = mid;
+            if (ah_uni64(a.tile_pref[mid]) <= t) lo = mid;
             else hi = mid;
         }
         i = lo;
@@ -91,169 +109,164 @@ struct SeqCursor {
     }
 };
 
-// Everything one tile needs from global memory, loaded one tile ahead.
+// What one tile needs from global memory, issued one tile ahead.  The loads
+// are unconditional (addresses clamped into the sequence) so they stay in
+// flight until the next iteration uses them.
 struct TileLoad {
-    uint4 blk;        // this lane's block
-    uint32_t nbw;     // N-bitmap word of this lane's block (bit already extracted)
-    uint32_t halo_h;  // lane 0: upper half of the previous block; lane 63: lower half of the next block
-    uint32_t halo_l;
-    uint32_t halo_n;  // N flag of that halo block
-    uint32_t nb;      // blocks in the tile
-    uint64_t rel0;    // first block of the tile within its sequence
+    uint4 blk;       // this lane's block (lanes past the end repeat the last one)
+    uint4 hal;       // lane 0: the block before the tile; lane 63: the block after it
+    uint32_t nbw;    // N-bitmap word holding this lane's block
+    uint32_t nbw_h;  // N-bitmap word holding the halo block
+    uint32_t nb;     // blocks in the tile (uniform)
+    uint32_t rel0;   // first block of the tile within its sequence (uniform)
+    uint64_t gb0;    // store block of the tile's first block (uniform)
+    uint32_t prev;   // a block precedes the tile in its sequence (uniform)
+    uint32_t next;   // a block follows the tile in its sequence (uniform)
 };
 
 __device__ __forceinline__ void tile_issue(const ScanArgs &a, const SeqCursor &c, uint64_t t, TileLoad &L) {
     const uint32_t lane = ah_lane();
     const uint4 *blocks = (const uint4 *)a.st.d_blocks;
-    L.rel0 = (t - c.tp0) * AH_TILE_BLOCKS;
-    const uint64_t left = c.nblk - L.rel0;
-    L.nb = (uint32_t)(left < AH_TILE_BLOCKS ? left : AH_TILE_BLOCKS);
-    const uint64_t gb0 = c.blk0 + L.rel0;
-    L.blk = make_uint4(0, 0, 0, 0);
-    L.nbw = 0;
-    L.halo_h = L.halo_l = L.halo_n = 0;
-    if (lane < L.nb) {
-        L.blk = blocks[gb0 + lane];
-        L.nbw = (a.st.d_nbits[(gb0 + lane) >> 5] >> ((gb0 + lane) & 31)) & 1u;
-    }
-    if (lane == 0 && L.rel0 > 0) {
-        const uint4 pv = blocks[gb0 - 1];
-        L.halo_h = pv.z;
-        L.halo_l = pv.w;
-        L.halo_n = (a.st.d_nbits[(gb0 - 1) >> 5] >> ((gb0 - 1) & 31)) & 1u;
-    }
-    if (lane == 63 && L.nb == AH_TILE_BLOCKS && L.rel0 + AH_TILE_BLOCKS < c.nblk) {
-        const uint4 nx = blocks[gb0 + AH_TILE_BLOCKS];
-        L.halo_h = nx.x;
-        L.halo_l = nx.y;
-        L.halo_n = (a.st.d_nbits[(gb0 + AH_TILE_BLOCKS) >> 5] >> ((gb0 + AH_TILE_BLOCKS) & 31)) & 1u;
-    }
+    L.rel0 = (uint32_t)(t - c.tp0) * AH_TILE_BLOCKS;
+    const uint32_t left = c.nblk - L.rel0;
+    L.nb = left < AH_TILE_BLOCKS ? left : AH_TILE_BLOCKS;
+    L.gb0 = c.blk0 + L.rel0;
+    L.prev = L.rel0 > 0;
+    L.next = L.rel0 + AH_TILE_BLOCKS < c.nblk;
+    const uint4 *tb = blocks + L.gb0;
+    const uint32_t own = lane < L.nb ? lane : L.nb - 1;
+    int32_t hoff = (int32_t)own;
+    if (lane == 0 && L.prev) hoff = -1;
+    if (lane == 63 && L.next) hoff = AH_TILE_BLOCKS;
+    L.blk = tb[own];
+    L.hal = tb[hoff];
+    L.nbw = a.st.d_nbits[(L.gb0 + own) >> 5];
+    L.nbw_h = a.st.d_nbits[(uint64_t)((int64_t)L.gb0 + hoff) >> 5];
 }
 
-// Verify queued candidates [0, qn) and append hits.
-__device__ void ah_verify_queue(const ScanArgs &a, const TileCtx &t, const uint32_t *sH, const uint32_t *sL,
-                                const uint32_t *sQ, uint32_t qn, const DPat *sPat) {
+// Any N in the tile's blocks or its halo blocks (wave-uniform result).
+__device__ __forceinline__ bool tile_has_n(const TileLoad &L) {
     const uint32_t lane = ah_lane();
-    for (uint32_t base = 0; base < qn; base += 64) {
-        const uint32_t e = base + lane;
-        bool ok = false;
-        uint32_t pos = 0, pk = 0, mm = 0;
-        if (e < qn) {
-            const uint32_t ent = sQ[e];
-            const uint32_t X = ent >> 13, ql = ent & 0x1FFFu;
-            const DPat *P = X < AH_LDS_PATS ? &sPat[X] : &a.pats[X];
-            const uint4 p0 = *(const uint4 *)&P->P[0];
-            const uint4 p1 = *(const uint4 *)&P->clampmask;
-            const uint32_t L = p1.z & 0xFFu, k = (p1.z >> 8) & 0xFFu, shift = p1.z >> 24;
-            const int32_t pl = (int32_t)ql - (int32_t)shift;  // window start, tile-relative
-            const int64_t gpos = t.pos0 + pl;
-            if (gpos >= 0 && gpos + (int64_t)L <= (int64_t)t.len) {
-                const uint32_t idx = (uint32_t)(pl + 32);
-                const uint32_t w = idx >> 5, off = idx & 31u;
-                const uint32_t hW = ah_funnel(sH[w + 1], sH[w], off);
-                const uint32_t lW = ah_funnel(sL[w + 1], sL[w], off);
-                uint32_t nW = 0;
-                if (t.has_n) {
-                    const uint64_t gp = t.gblk0 * 64 + (uint64_t)((int64_t)pl);
-                    const uint64_t ba = gp >> 6, bb = (gp + L - 1) >> 6;
-                    const uint32_t o = (uint32_t)(gp & 63);
-                    uint64_t m = ah_block_nmask(a.st, ba) >> o;
-                    if (bb != ba && o) m |= ah_block_nmask(a.st, bb) << (64 - o);
-                    nW = (uint32_t)m;
-                }
-                const uint32_t lo = (lW & p0.y) | (~lW & p0.x);  // C : A
-                const uint32_t hi = (lW & p0.w) | (~lW & p0.z);  // T : G
-                const uint32_t matched = ((hW & hi) | (~hW & lo)) & ~nW & p1.y;
-                mm = __popc(p1.y & ~matched);
-                ok = ((matched & p1.x) == p1.x) && mm <= k;
-                pos = (uint32_t)gpos;
-                pk = p1.w;
-            }
-        }
-        const uint64_t bal = __ballot(ok);
-        if (bal) {
-            uint64_t hbase = 0;
-            if (lane == 0) hbase = atomicAdd((unsigned long long *)a.n_hits, (unsigned long long)__popcll(bal));
-            hbase = __shfl(hbase, 0);
-            if (ok) {
-                const uint64_t h = hbase + ah_mbcnt(bal);
-                if (h < a.hit_cap) {
-                    uint32_t *r = a.hits + 3 * h;
-                    r[0] = t.seq;
-                    r[1] = pos;
-                    r[2] = pk | (mm << 24);
-                }
-            }
-        }
+    const uint32_t own = lane < L.nb ? lane : L.nb - 1;
+    const uint64_t gown = L.gb0 + own;
+    bool nf = (L.nbw >> (gown & 31)) & 1u;
+    if ((lane == 0 && L.prev) || (lane == 63 && L.next)) {
+        const uint64_t gh = lane == 0 ? L.gb0 - 1 : L.gb0 + AH_TILE_BLOCKS;
+        nf = nf || ((L.nbw_h >> (gh & 31)) & 1u);
     }
+    return __ballot(nf) != 0;
 }
 
-// Push the candidate words C[8] (pattern x of group g: words 2x, 2x+1) into
-// the wave queue, verifying whenever it would overflow.
-__device__ __forceinline__ void ah_push_group(const ScanArgs &a, const TileCtx &t, uint32_t g, uint32_t (&C)[8],
-                                              const uint32_t *sH, const uint32_t *sL, uint32_t *sQ, uint32_t &qn,
-                                              const DPat *sPat) {
-    const uint32_t lane = ah_lane();
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int w = 0; w < 8; w++) cnt += __popc(C[w]);
-    if (__ballot(cnt != 0) == 0) return;
-    const uint32_t incl = ah_wave_incl_sum<uint32_t>(cnt);
-    const uint32_t tot = __shfl(incl, 63);
-    if (qn + tot > AH_QCAP) {
-        ah_wave_sync();
-        ah_verify_queue(a, t, sH, sL, sQ, qn, sPat);
-        ah_wave_sync();
-        qn = 0;
-    }
-    if (tot <= AH_QCAP) {
-        uint32_t o = qn + incl - cnt;
-#pragma unroll
-        for (int w = 0; w < 8; w++) {
-            uint32_t c = C[w];
-            const uint32_t tag = ((4 * g + (uint32_t)(w >> 1)) << 13) | (64 * lane + 32 * (uint32_t)(w & 1));
-            while (c) {
-                const uint32_t b = __ffs(c) - 1;
-                c &= c - 1;
-                sQ[o++] = tag + b;
-            }
-        }
-        qn += tot;
+__device__ __forceinline__ void ah_pattern_record(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, uint32_t X,
+                                                  uint4 &p0, uint4 &p1) {
+    if (X < n_lds) {
+        p0 = *(const uint4 *)&sPat[X].P[0];
+        p1 = *(const uint4 *)&sPat[X].clampmask;
     } else {
-        // hit-dense tile: drain in rounds of at most AH_QCAP / 64 per lane
-        uint32_t left = cnt;
-        while (__ballot(left != 0)) {
-            const uint32_t take = left < AH_QCAP / 64 ? left : AH_QCAP / 64;
-            const uint32_t inc2 = ah_wave_incl_sum<uint32_t>(take);
-            const uint32_t tot2 = __shfl(inc2, 63);
-            uint32_t o = inc2 - take, done = 0;
-#pragma unroll
-            for (int w = 0; w < 8; w++) {
-                const uint32_t tag = ((4 * g + (uint32_t)(w >> 1)) << 13) | (64 * lane + 32 * (uint32_t)(w & 1));
-                while (C[w] && done < take) {
-                    const uint32_t b = __ffs(C[w]) - 1;
-                    C[w] &= C[w] - 1;
-                    sQ[o++] = tag + b;
-                    done++;
-                }
+        p0 = *(const uint4 *)&a.pats[X].P[0];
+        p1 = *(const uint4 *)&a.pats[X].clampmask;
+    }
+}
+
+// Verify queued entries [e0, e1) (at most 64: one per lane).  Entry =
+// {candidate mask bits 0-31, bits 32-63, X << 8 | ctx << 6 | lane}; windows
+// are read from the tile words kept in LDS (sW[ctx][plane][word]).
+__device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
+                                const uint32_t (*sQ)[3], uint32_t e0, uint32_t e1,
+                                const uint32_t (*sW)[2][AH_TW]) {
+    const uint32_t e = e0 + ah_lane();
+    if (e >= e1) return;
+    uint64_t m = ((uint64_t)sQ[e][1] << 32) | sQ[e][0];
+    const uint32_t tag = sQ[e][2];
+    const uint32_t X = tag >> 8, ci = (tag >> 6) & 3u, ln = tag & 63u;
+    const TileCtx c = sCtx[ci];
+    uint4 p0, p1;
+    ah_pattern_record(a, sPat, n_lds, X, p0, p1);
+    const uint32_t L = p1.z & 0xFFu, k = (p1.z >> 8) & 0xFFu, shift = p1.z >> 24;
+    const uint32_t *Wh = sW[ci][0], *Wl = sW[ci][1];
+    // window starts (tile-relative) allowed by the sequence bounds
+    const int32_t lo_ok = -(int32_t)(c.pos0 < 32u ? c.pos0 : 32u);
+    const int64_t room = (int64_t)c.len - (int64_t)c.pos0 - (int64_t)L;
+    const int32_t hi_ok = (int32_t)(room < (1 << 20) ? room : (1 << 20));
+    while (m) {
+        const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const int32_t pl = (int32_t)(64 * ln + b) - (int32_t)shift;  // window start, tile-relative
+        if (pl < lo_ok || pl > hi_ok) continue;
+        const uint32_t idx = (uint32_t)(pl + 32);
+        const uint32_t w = idx >> 5, off = idx & 31u;
+        const uint32_t hW = ah_funnel(Wh[w + 1], Wh[w], off);
+        const uint32_t lW = ah_funnel(Wl[w + 1], Wl[w], off);
+        uint32_t nW = 0;
+        if (c.has_n) {
+            const uint64_t gp = c.gbase + (uint64_t)(int64_t)pl;
+            const uint64_t ba = gp >> 6, bb = (gp + L - 1) >> 6;
+            const uint32_t o = (uint32_t)(gp & 63);
+            uint64_t nm = ah_block_nmask(a.st, ba) >> o;
+            if (bb != ba && o) nm |= ah_block_nmask(a.st, bb) << (64 - o);
+            nW = (uint32_t)nm;
+        }
+        const uint32_t lo = (lW & p0.y) | (~lW & p0.x);  // C : A
+        const uint32_t hi = (lW & p0.w) | (~lW & p0.z);  // T : G
+        const uint32_t matched = ((hW & hi) | (~hW & lo)) & ~nW & p1.y;
+        const uint32_t mm = __popc(p1.y & ~matched);
+        if ((matched & p1.x) == p1.x && mm <= k) {
+            const uint64_t h = atomicAdd((unsigned long long *)a.n_hits, 1ull);
+            if (h < a.hit_cap) {
+                uint32_t *r = a.hits + 3 * h;
+                r[0] = c.seq;
+                r[1] = (uint32_t)((int64_t)c.pos0 + pl);
+                r[2] = p1.w | (mm << 24);
             }
-            left -= take;
-            ah_wave_sync();
-            ah_verify_queue(a, t, sH, sL, sQ, tot2, sPat);
-            ah_wave_sync();
         }
     }
+}
+
+// Verify whole rounds of 64 queued entries; with drain, also the remainder.
+// Entries left over move to the front of the queue.
+__device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
+                                         uint32_t (*sQ)[3], uint32_t &qn, const uint32_t (*sW)[2][AH_TW],
+                                         bool drain) {
+    ah_wave_sync();
+    uint32_t e0 = 0;
+    for (; e0 + 64 <= qn; e0 += 64) ah_verify_round(a, sPat, n_lds, sCtx, sQ, e0, e0 + 64, sW);
+    if (drain) {
+        if (e0 < qn) ah_verify_round(a, sPat, n_lds, sCtx, sQ, e0, qn, sW);
+        qn = 0;
+    } else if (e0 > 0) {
+        const uint32_t rest = qn - e0;  // < 64
+        const uint32_t lane = ah_lane();
+        uint32_t v0 = 0, v1 = 0, v2 = 0;
+        if (lane < rest) {
+            v0 = sQ[e0 + lane][0];
+            v1 = sQ[e0 + lane][1];
+            v2 = sQ[e0 + lane][2];
+        }
+        ah_wave_sync();
+        if (lane < rest) {
+            sQ[lane][0] = v0;
+            sQ[lane][1] = v1;
+            sQ[lane][2] = v2;
+        }
+        qn = rest;
+    }
+    ah_wave_sync();
 }
 
 // The kernel body.  Filter F provides
-//   F::groups(a)  number of pattern groups,
-//   f.filter(g, Sh, Sl, v0, v1, C)  candidate words of group g.
+//   f.groups(a)                         number of pattern groups (primer pairs),
+//   f.filter(g, Sh, Sl, v0, v1, C)      candidate words of group g (C[2x], C[2x+1]:
+//                                       clamp sites 0-31 / 32-63 of pattern x).
+// n_lds: pattern records staged in sPat.
 template <class F>
-__device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, DPat *sPat, uint32_t (*sH_all)[2 * AH_TILE_BLOCKS + 2],
-                                             uint32_t (*sL_all)[2 * AH_TILE_BLOCKS + 2], uint32_t (*sQ_all)[AH_QCAP]) {
+__device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds,
+                                             TileCtx (*sCtx_all)[AH_NCTX], uint32_t (*sQ_all)[AH_QCAP][3],
+                                             uint32_t (*sW_all)[AH_NCTX][2][AH_TW]) {
     const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint32_t *sH = sH_all[wv], *sL = sL_all[wv], *sQ = sQ_all[wv];
-    const uint64_t total = a.tile_pref[a.n_list];
+    TileCtx *sCtx = sCtx_all[wv];
+    uint32_t(*sQ)[3] = sQ_all[wv];
+    uint32_t(*sW)[2][AH_TW] = sW_all[wv];
+    const uint64_t total = ah_uni64(a.tile_pref[a.n_list]);
     // XCD-aware numbering: workgroup i runs on XCD i % 8, so give each XCD a
     // contiguous share of the tiles.
     const uint32_t nwg = gridDim.x;
@@ -269,46 +282,54 @@ __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, DPat *sPat
     TileLoad L;
     tile_issue(a, cur, t, L);
     const uint32_t groups = f.groups(a);
+    uint32_t qn = 0, nctx = 0;
 
     for (; t < tend; t++) {
-        // issue the next tile's loads before working on this one
+        // issue the next tile's loads before working on this one (the last
+        // tile reloads itself, so the loads are unconditional)
+        const uint64_t tn = t + 1 < tend ? t + 1 : t;
         SeqCursor nc = cur;
+        nc.advance(a, tn);
         TileLoad NL;
-        const bool has_next = t + 1 < tend;
-        if (has_next) {
-            nc.advance(a, t + 1);
-            tile_issue(a, nc, t + 1, NL);
+        tile_issue(a, nc, tn, NL);
+
+        if (nctx == AH_NCTX) {  // every context slot is referenced: verify all
+            ah_flush(a, sPat, n_lds, sCtx, sQ, qn, sW, true);
+            nctx = 0;
         }
-
-        TileCtx tc;
-        tc.seq = cur.seq;
-        tc.len = cur.len;
-        tc.pos0 = (int64_t)(L.rel0 * 64);
-        tc.gblk0 = cur.blk0 + L.rel0;
-        tc.has_n = __ballot(L.nbw | L.halo_n) != 0;
-
+        const uint32_t ci = nctx++;
+        const bool has_n = tile_has_n(L);
+        if (lane == 0) {
+            TileCtx c;
+            c.gbase = L.gb0 * 64;
+            c.seq = cur.seq;
+            c.len = cur.len;
+            c.pos0 = L.rel0 * 64;
+            c.has_n = has_n;
+            sCtx[ci] = c;
+        }
         const uint32_t h0 = L.blk.x, l0 = L.blk.y, h1 = L.blk.z, l1 = L.blk.w;
         uint32_t nh0 = __shfl_down(h0, 1, 64), nl0 = __shfl_down(l0, 1, 64);
         if (lane == 63) {
-            nh0 = L.halo_h;
-            nl0 = L.halo_l;
+            nh0 = L.hal.x;
+            nl0 = L.hal.y;
         }
-        sH[1 + 2 * lane] = h0;
-        sH[2 + 2 * lane] = h1;
-        sL[1 + 2 * lane] = l0;
-        sL[2 + 2 * lane] = l1;
+        uint32_t *Wh = sW[ci][0], *Wl = sW[ci][1];
+        Wh[1 + 2 * lane] = h0;
+        Wh[2 + 2 * lane] = h1;
+        Wl[1 + 2 * lane] = l0;
+        Wl[2 + 2 * lane] = l1;
         if (lane == 0) {
-            sH[0] = L.halo_h;
-            sL[0] = L.halo_l;
+            Wh[0] = L.hal.z;
+            Wl[0] = L.hal.w;
         }
         if (lane == 63) {
-            sH[2 * AH_TILE_BLOCKS + 1] = L.halo_h;
-            sL[2 * AH_TILE_BLOCKS + 1] = L.halo_l;
+            Wh[AH_TW - 1] = nh0;
+            Wl[AH_TW - 1] = nl0;
         }
-        // clamp sites of this lane inside the sequence
-        const int64_t rem = (int64_t)tc.len - (tc.pos0 + 64 * (int64_t)lane);
-        const uint32_t v0 = rem >= 32 ? 0xFFFFFFFFu : (rem <= 0 ? 0u : ((1u << rem) - 1u));
-        const uint32_t v1 = rem >= 64 ? 0xFFFFFFFFu : (rem <= 32 ? 0u : ((1u << (rem - 32)) - 1u));
+        // lanes past the sequence end hold a repeated block: no candidates there
+        // (windows reaching past the end are rejected in verification)
+        const uint32_t v = lane < L.nb ? 0xFFFFFFFFu : 0u;
         // bit q of S*[i][w]: plane bit of base q + i (w selects bases 0-31 / 32-63)
         uint32_t Sh[AH_WMAX][2], Sl[AH_WMAX][2];
 #pragma unroll
@@ -318,26 +339,37 @@ __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, DPat *sPat
             Sl[i][0] = ah_funnel(l1, l0, i);
             Sl[i][1] = ah_funnel(nl0, l1, i);
         }
-        ah_wave_sync();
-        uint32_t qn = 0;
         for (uint32_t g = 0; g < groups; g++) {
             uint32_t C[8];
-            f.filter(g, Sh, Sl, v0, v1, C);
-            ah_push_group(a, tc, g, C, sH, sL, sQ, qn, sPat);
+            f.filter(g, Sh, Sl, v, v, C);
+            const uint32_t any = (C[0] | C[1] | C[2] | C[3]) | (C[4] | C[5] | C[6] | C[7]);
+            if (__ballot(any != 0) == 0) continue;
+#pragma unroll
+            for (int x = 0; x < 4; x++) {
+                const bool nz = (C[2 * x] | C[2 * x + 1]) != 0;
+                const uint64_t bal = __ballot(nz);
+                if (!bal) continue;
+                const uint32_t cnt = (uint32_t)__popcll(bal);
+                if (qn + cnt > AH_QCAP) ah_flush(a, sPat, n_lds, sCtx, sQ, qn, sW, false);
+                if (nz) {
+                    const uint32_t slot = qn + ah_mbcnt(bal);
+                    sQ[slot][0] = C[2 * x];
+                    sQ[slot][1] = C[2 * x + 1];
+                    sQ[slot][2] = ((4 * g + (uint32_t)x) << 8) | (ci << 6) | lane;
+                }
+                qn += cnt;
+            }
         }
-        if (qn) {
-            ah_wave_sync();
-            ah_verify_queue(a, tc, sH, sL, sQ, qn, sPat);
-        }
-        ah_wave_sync();
+        if (qn >= 64) ah_flush(a, sPat, n_lds, sCtx, sQ, qn, sW, false);
         cur = nc;
         L = NL;
     }
+    if (qn) ah_flush(a, sPat, n_lds, sCtx, sQ, qn, sW, true);
 }
 
-// Stage the first AH_LDS_PATS pattern records in LDS (all threads of the block).
-__device__ __forceinline__ void ah_stage_patterns(const ScanArgs &a, DPat *sPat) {
-    const uint32_t n = a.n_pats < AH_LDS_PATS ? a.n_pats : AH_LDS_PATS;
+// Stage the first n pattern records in LDS (all threads of the block).
+__device__ __forceinline__ void ah_stage_patterns(const ScanArgs &a, DPat *sPat, uint32_t cap) {
+    const uint32_t n = a.n_pats < cap ? a.n_pats : cap;
     const uint4 *src = (const uint4 *)a.pats;
     uint4 *dst = (uint4 *)sPat;
     for (uint32_t i = threadIdx.x; i < n * 3; i += blockDim.x) dst[i] = src[i];
