@@ -32,9 +32,12 @@ def parse():
     ap.add_argument("--n-seqs", type=int, default=None, help="shrink the workload (testing)")
     ap.add_argument("--len-scale", type=float, default=1.0, help="shrink the workload (testing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-bases", type=float, default=1.0e9)
+    ap.add_argument("--cpu-sample-bases", type=float, default=None,
+                    help="oracle sample size (default 1e9 bases for one pair, 3e7 for many)")
     ap.add_argument("--stages", default="scan,pair,tm,extract")
     ap.add_argument("--generic", action="store_true", help="use the generic scan kernel (no primer-set JIT)")
+    ap.add_argument("--plain-reps", type=int, default=1, help="timed repetitions of the plain per-pair loop (batch)")
+    ap.add_argument("--no-tune", action="store_true", help="batch: skip the autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM counters)")
     return ap.parse_args()
@@ -55,6 +58,122 @@ def traffic_from_profiles(kernel_src_hash):
     if d.get("scan_src_sha256") != kernel_src_hash:
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, sample, ex, what):
+    if sample is None:
+        return None
+    import oracle
+    buf, off, m = sample
+    nt = os.cpu_count() or 1
+    tc = time.perf_counter()
+    o = oracle.run(buf, off, wl.pairs, wl.orient_mask, wl.tm, ex, n_threads=nt)
+    dt = time.perf_counter() - tc
+    sb = int(off[-1])
+    log("oracle sample: %d amplicons in %.1f s" % (len(o.amps), dt))
+    return {"value": round(len(wl.pairs) * sb / dt / 1e9, 4), "unit": what, "cores": nt, "kind": "oracle",
+            "sample": "first %d sequences (%.4f Gbases) of the workload, %d pairs, scan+pair+Tm+extract, %.1f s"
+                      % (m, sb / 1e9, len(wl.pairs), dt)}
+
+
+def bench_batch(args, wl, store, sample):
+    """Many pairs: one autotuned, graph-captured pass over the store against
+    the plain per-pair loop (64 single-pair pipelines).  value = pair-Gbases/s
+    of the graph (pairs x bases / time)."""
+    import numpy as np
+    import torch
+
+    from paper_2511_00170_amd import ah, batch
+
+    total = wl.total_bases
+    ex = synth_extract(wl)
+    tj = time.time()
+    br = batch.BatchRunner(store, wl.pairs, wl.orient_mask, wl.tm, ex, jit=not args.generic)
+    log("primer set (%d pairs) compiled in %.2f s" % (len(wl.pairs), time.time() - tj))
+    tuned = None
+    if not args.no_tune:
+        tuned = br.tune(sample_bases=min(1e9, total / 4))
+        log("autotune: %s" % json.dumps(tuned.table))
+    res = br.run()                                 # eager sizing + capture + one replay
+    n_hits, n_amps, n_bytes = br.pipe.counts()
+    log("batch: hits %d amplicons %d pass %d bytes %d" % (n_hits, n_amps, int(res["pass"].sum()), n_bytes))
+    for _ in range(args.warmup):
+        br.replay()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        br.replay()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t_start) * 1e3 / args.steps
+    # scan alone, eagerly, for the roofline (same kernel and launch shape)
+    with torch.cuda.stream(br.stream):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+        for a, b in ev:
+            a.record(br.stream)
+            br.pipe.launch(br.stream, ("scan",))
+            b.record(br.stream)
+        torch.cuda.synchronize()
+    scan_ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    # the graph again, so the buffers hold the whole path's output
+    br.replay()
+    res = br.pipe.results()
+    log("graph %.3f ms/step, scan %.3f ms" % (ms_step, scan_ms))
+    plain, plain_ms = batch.plain_loop(store, wl.pairs, wl.orient_mask, wl.tm, ex, jit=not args.generic,
+                                       reps=args.plain_reps)
+    same = batch_outputs_equal(res, plain)
+    log("plain loop %.3f ms; identical output: %s" % (plain_ms, same))
+    npairs = len(wl.pairs)
+    alg_bytes = BYTES_PER_BASE * total + 12.0 * n_hits
+    achieved = alg_bytes / (scan_ms / 1e3) / 1e9
+    kern = "ah_scan_jit" if br.ps.jit else "ah_scan_kernel"
+    out = {
+        "metric": "Gbases scanned/s per primer pair (k mm) + % HBM peak; batched vs plain; p50/p99 latency",
+        "value": round(npairs * total / (ms_step / 1e3) / 1e9, 2),
+        "unit": "pair-Gbases/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32/f64", "data": "synthetic",
+        "config": {"workload": "batch: %d seqs (log-normal chromosomes + 20%% plasmids), %.2f Gbases, %d pairs "
+                               "(L 17-26, D up to 512, k 0-3, clamp 3-5), FR/RF/FF/RR, window 200-2000, "
+                               "FP64 Tm filter >= 45 C" % (wl.n_seqs, total / 1e9, npairs),
+                   "pairs": npairs, "bases": total, "hits": n_hits, "amplicons": n_amps,
+                   "scan_kernel": "primer-set specialised (hipRTC)" if br.ps.jit else "generic",
+                   "graph": True, "autotune": tuned.table if tuned else None,
+                   "wg_per_cu": tuned.wg_per_cu if tuned else 0},
+        "batched_vs_plain": {"batched_ms": round(ms_step, 3), "plain_loop_ms": round(plain_ms, 3),
+                             "speedup": round(plain_ms / ms_step, 3), "identical_output": same,
+                             "plain_pair_gbases_s": round(npairs * total / (plain_ms / 1e3) / 1e9, 2)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kern,
+                     "kernel_ms": round(scan_ms, 4), "algorithmic_bytes_per_launch": int(alg_bytes)},
+        "cpu_baseline": cpu_baseline(wl, sample, ex, "pair-Gbases/s"),
+    }
+    print(json.dumps(out), flush=True)
+    if not same:
+        sys.exit(1)
+
+
+def synth_extract(wl):
+    from paper_2511_00170_amd import synth
+    return synth.ExtractSpec(trim=wl.extract.trim, fb_len=wl.extract.fb_len, rb_len=wl.extract.rb_len)
+
+
+def batch_outputs_equal(a, b):
+    import numpy as np
+
+    from paper_2511_00170_amd import ah
+    try:
+        ok = np.array_equal(ah.hits_canonical(a["hits"]), ah.hits_canonical(b["hits"]))
+        ok &= np.array_equal(ah.amps_array(a["amps"]), ah.amps_array(b["amps"]))
+        ok &= np.array_equal(a["amps"]["flags"], b["amps"]["flags"])
+        for k in ("tm", "tm_site", "pass", "seq_off", "fb", "rb", "bc_len", "fprimer", "rprimer"):
+            if k in a:
+                ok &= np.array_equal(a[k], b[k])
+        if "seq" in a:
+            ok &= a["seq"] == b["seq"]
+        return bool(ok)
+    except Exception as e:  # shape mismatch etc.
+        log("compare failed: %r" % (e,))
+        return False
 
 
 def main():
@@ -83,7 +202,7 @@ def main():
     total = wl.total_bases
     log("workload %s: %d sequences, %.3f Gbases" % (wl.name, wl.n_seqs, total / 1e9))
     sample = None
-    sample_goal = args.cpu_sample_bases
+    sample_goal = args.cpu_sample_bases or (1.0e9 if len(wl.pairs) == 1 else 3.0e7)
 
     def chunks():
         nonlocal sample
@@ -98,6 +217,8 @@ def main():
     store = ah.Store(wl.lengths)
     store.pack_chunks(chunks())
     log("generated + packed in %.1f s (store %.2f GB)" % (time.time() - t0, store.hbm_bytes / 1e9))
+    if len(wl.pairs) > 1:
+        return bench_batch(args, wl, store, sample)
 
     tj = time.time()
     ps = ah.PrimerSet(wl.pairs, jit=not args.generic)
@@ -135,19 +256,7 @@ def main():
             "kernel": "ah_scan_jit" if ps.jit else "ah_scan_kernel", "kernel_ms": round(scan_ms, 4),
             "algorithmic_bytes_per_launch": int(alg_bytes)}
 
-    cpu = None
-    if sample is not None:
-        import oracle
-        buf, off, m = sample
-        nt = os.cpu_count() or 1
-        tc = time.perf_counter()
-        o = oracle.run(buf, off, wl.pairs, wl.orient_mask, wl.tm, ex, n_threads=nt)
-        dt = time.perf_counter() - tc
-        sb = int(off[-1])
-        cpu = {"value": round(sb / dt / 1e9, 4), "unit": "Gbases/s", "cores": nt, "kind": "oracle",
-               "sample": "first %d sequences (%.3f Gbases) of the workload, scan+pair+Tm+extract, %.1f s"
-                         % (m, sb / 1e9, dt)}
-        log("oracle sample: %d amplicons in %.1f s" % (len(o.amps), dt))
+    cpu = cpu_baseline(wl, sample, ex, "Gbases/s")
 
     out = {
         "metric": "Gbases scanned/s per primer pair (k mm) + % HBM peak; batched vs plain; p50/p99 latency",

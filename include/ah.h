@@ -133,6 +133,16 @@ ah_status ah_primers_jit(ah_primer_set ps);
  * the generic scan kernel for this set. */
 ah_status ah_primers_use_jit(ah_primer_set ps, int32_t on);
 
+/* Launch shape of the persistent scan for this set: wg_per_cu workgroups of
+ * 256 lanes per compute unit (0 = as many as can be resident, the default;
+ * larger values are clamped to that maximum).  Applies to whichever kernel
+ * (specialised or generic) is selected at the next ah_scan_primers call.
+ * If max_wg_per_cu is non-null it receives the resident maximum of the
+ * currently selected kernel on the current device.  Results do not depend on
+ * the shape (every tile is scanned exactly once); only the speed does.
+ * Errors: AH_E_ARG (null set, negative value), AH_E_HIP. */
+ah_status ah_primers_launch_shape(ah_primer_set ps, int32_t wg_per_cu, int32_t *max_wg_per_cu);
+
 /* ------------------------------------------------------------------------
  * Scan (Supplementary, "Primer matching and clamp logic"; mismatches are
  * substitutions, Results "Primer degeneracy and mismatch tolerance").

@@ -79,6 +79,7 @@ _sig("ah_primers_free", None, VP)
 _sig("ah_primers_count", U32, VP)
 _sig("ah_primers_jit", I32, VP)
 _sig("ah_primers_use_jit", I32, VP, I32)
+_sig("ah_primers_launch_shape", I32, VP, I32, C.POINTER(I32))
 _sig("ah_scan_ws_size", I32, C.POINTER(ah_store), U32, C.POINTER(U64))
 _sig("ah_scan_primers", I32, C.POINTER(ah_store), VP, VP, U32, VP, U64, VP, VP, U64, VP)
 _sig("ah_pair_ws_size", I32, C.POINTER(ah_store), VP, U64, C.POINTER(U64))
@@ -90,7 +91,8 @@ _sig("ah_extract", I32, C.POINTER(ah_store), VP, VP, VP, U64, VP, C.POINTER(ah_e
      VP, VP, VP, VP, VP, U64, VP)
 
 EXPORTED = ["ah_status_str", "ah_version", "ah_pack_layout", "ah_pack_begin", "ah_pack", "ah_pack_finish",
-            "ah_unpack", "ah_primers_compile", "ah_primers_free", "ah_primers_count", "ah_primers_jit", "ah_primers_use_jit", "ah_scan_ws_size",
+            "ah_unpack", "ah_primers_compile", "ah_primers_free", "ah_primers_count", "ah_primers_jit", "ah_primers_use_jit",
+            "ah_primers_launch_shape", "ah_scan_ws_size",
             "ah_scan_primers", "ah_pair_ws_size", "ah_pair_amplicons", "ah_tm_nn", "ah_tm_duplex",
             "ah_extract_ws_size", "ah_extract"]
 
@@ -225,17 +227,25 @@ class PrimerSet:
         h = VP()
         check(_lib.ah_primers_compile(arr, len(self.pairs), C.byref(h)), "ah_primers_compile")
         self.h = h
-        self.jit = False
+        self.jit = False       # specialised kernel selected
+        self.has_jit = False   # specialised kernel compiled
         if jit:
             self.enable_jit()
 
     def enable_jit(self):
         check(_lib.ah_primers_jit(self.h), "ah_primers_jit")
-        self.jit = True
+        self.jit = self.has_jit = True
 
     def use_jit(self, on: bool):
         check(_lib.ah_primers_use_jit(self.h, int(bool(on))), "ah_primers_use_jit")
         self.jit = bool(on)
+
+    def launch_shape(self, wg_per_cu: int = 0) -> int:
+        """Set the persistent scan's workgroups per CU (0 = resident maximum);
+        returns the resident maximum of the selected kernel."""
+        m = I32(0)
+        check(_lib.ah_primers_launch_shape(self.h, int(wg_per_cu), C.byref(m)), "ah_primers_launch_shape")
+        return int(m.value)
 
     def __len__(self):
         return len(self.pairs)

@@ -19,6 +19,7 @@ struct ah_primer_set_ {
     int device;
     void *jit;    // primer-set specialised scan kernel (ah_primers_jit), or null
     int use_jit;
+    int wg_per_cu;  // persistent scan workgroups per CU (0 = resident maximum)
 };
 
 void ah_jit_free(void *jit);

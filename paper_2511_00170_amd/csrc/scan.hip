@@ -125,7 +125,7 @@ extern "C" ah_status ah_scan_ws_size(const ah_store *st, uint32_t n_list, uint64
 struct AhJit {
     hipModule_t mod = nullptr;
     hipFunction_t fn = nullptr;
-    int grid = 0;
+    int per_cu = 0;  // resident workgroups per CU
     int device = -1;
 };
 
@@ -221,8 +221,8 @@ extern "C" ah_status ah_primers_jit(ah_primer_set ps) {
     }
     int per_cu = 0;
     if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, j->fn, 256, 0) != hipSuccess || per_cu <= 0)
-        per_cu = 2;
-    j->grid = device_cus(dev) * per_cu;
+        per_cu = 1;
+    j->per_cu = per_cu;
     j->device = dev;
     ps->jit = j;
     ps->use_jit = 1;
@@ -243,8 +243,32 @@ void ah_jit_free(void *jit) {
     delete j;
 }
 
+// Resident workgroups per CU of the generic kernel (same on every gfx950 device).
+static int generic_per_cu() {
+    static int per_cu = 0;
+    if (!per_cu) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, ah_scan_kernel, 256, 0) != hipSuccess || v <= 0) v = 1;
+        per_cu = v;
+    }
+    return per_cu;
+}
+
+static bool jit_active(ah_primer_set ps, int dev) {
+    const AhJit *j = (const AhJit *)ps->jit;
+    return j && ps->use_jit && j->device == dev;
+}
+
+extern "C" ah_status ah_primers_launch_shape(ah_primer_set ps, int32_t wg_per_cu, int32_t *max_wg_per_cu) {
+    if (!ps || wg_per_cu < 0) return AH_E_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return AH_E_HIP;
+    ps->wg_per_cu = wg_per_cu;
+    if (max_wg_per_cu) *max_wg_per_cu = jit_active(ps, dev) ? ((const AhJit *)ps->jit)->per_cu : generic_per_cu();
+    return AH_OK;
+}
+
 // ---------------------------------------------------------------- entry point
-static int g_scan_grid = 0;
 
 extern "C" ah_status ah_scan_primers(const ah_store *st, ah_primer_set ps, const uint32_t *d_seq_subset,
                                      uint32_t n_subset, ah_hit *d_hits, uint64_t hit_cap, uint64_t *d_n_hits,
@@ -276,21 +300,17 @@ extern "C" ah_status ah_scan_primers(const ah_store *st, ah_primer_set ps, const
     a.n_hits = d_n_hits;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    AhJit *j = (AhJit *)ps->jit;
-    if (j && ps->use_jit && j->device == dev) {
+    const bool use_j = jit_active(ps, dev);
+    // persistent grid: the workgroups that can be resident at once (or fewer, as set)
+    int per_cu = use_j ? ((const AhJit *)ps->jit)->per_cu : generic_per_cu();
+    if (ps->wg_per_cu > 0 && ps->wg_per_cu < per_cu) per_cu = ps->wg_per_cu;
+    const unsigned grid = (unsigned)(device_cus(dev) * per_cu);
+    if (use_j) {
         void *args[] = {&a};
-        if (hipModuleLaunchKernel(j->fn, (unsigned)j->grid, 1, 1, 256, 1, 1, 0, s, args, nullptr) != hipSuccess)
+        if (hipModuleLaunchKernel(((AhJit *)ps->jit)->fn, grid, 1, 1, 256, 1, 1, 0, s, args, nullptr) != hipSuccess)
             return AH_E_HIP;
         return AH_OK;
     }
-    if (!g_scan_grid) {
-        // persistent grid: the workgroups that can be resident at once
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ah_scan_kernel, 256, 0) != hipSuccess ||
-            per_cu <= 0)
-            per_cu = 2;
-        g_scan_grid = device_cus(dev) * per_cu;
-    }
-    hipLaunchKernelGGL(ah_scan_kernel, dim3(g_scan_grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(ah_scan_kernel, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
 }

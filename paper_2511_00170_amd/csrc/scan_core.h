@@ -340,6 +340,13 @@ __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat
             Sl[i][1] = ah_funnel(nl0, l1, i);
         }
         for (uint32_t g = 0; g < groups; g++) {
+            // Mark the shifted planes as redefined in every iteration (an empty
+            // asm, no instruction): otherwise, with compile-time codes, the
+            // compiler hoists every group's set tests out of this loop as
+            // invariants and runs out of registers once there are many groups.
+#pragma unroll
+            for (int i = 0; i < AH_WMAX; i++)
+                asm volatile("" : "+v"(Sh[i][0]), "+v"(Sh[i][1]), "+v"(Sl[i][0]), "+v"(Sl[i][1]));
             uint32_t C[8];
             f.filter(g, Sh, Sl, v, v, C);
             const uint32_t any = (C[0] | C[1] | C[2] | C[3]) | (C[4] | C[5] | C[6] | C[7]);
