@@ -38,6 +38,10 @@ def parse():
     ap.add_argument("--generic", action="store_true", help="use the generic scan kernel (no primer-set JIT)")
     ap.add_argument("--plain-reps", type=int, default=1, help="timed repetitions of the plain per-pair loop (batch)")
     ap.add_argument("--no-tune", action="store_true", help="batch: skip the autotuner")
+    ap.add_argument("--serve", action="store_true", help="serving workload (continuous batching, latency)")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests per run")
+    ap.add_argument("--warm-requests", type=int, default=200, help="serve: warm-up requests per run")
+    ap.add_argument("--budget-mb", type=int, default=2048, help="serve: device memory budget per batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM counters)")
     return ap.parse_args()
@@ -152,6 +156,82 @@ def bench_batch(args, wl, store, sample):
         sys.exit(1)
 
 
+def bench_serve(args, wl, store):
+    """Serving: closed-loop saturation throughput mu, then Poisson arrivals at
+    0.5 mu and 0.8 mu; p50/p99 latency (arrival -> results on the host) over
+    the measured requests and aggregate pair-Gbases/s (sum over requests of
+    subset bases x pairs, over the wall time)."""
+    import numpy as np
+    import torch
+
+    from paper_2511_00170_amd import serve, synth
+
+    ex = synth_extract(wl)
+    tj = time.time()
+    eng = serve.ServeEngine(store, wl.pairs, wl.tm, ex, wl.orient_mask, pool_k=3,
+                            budget_bytes=args.budget_mb << 20)
+    log("pool of %d pairs compiled in %.2f s" % (len(wl.pairs), time.time() - tj))
+    lens = store.lengths.astype(np.int64)
+    n_w, n_m = args.warm_requests, args.requests
+
+    def work(reqs):
+        return sum(float(lens[r.seqs].sum()) * len(r.pairs) for r in reqs)
+
+    def run(qps, seed):
+        reqs = synth.gen_requests(wl, n_w + n_m, qps=qps, seed=seed)
+        eng.sched.stats = serve.SchedStats()
+        t0 = time.perf_counter()
+        out = eng.serve(reqs)
+        wall = time.perf_counter() - t0
+        meas = [r for r in reqs if r.rid >= n_w]
+        # measured window: from the first measured arrival to the last completion
+        t_a = t0 + min(r.arrival_s for r in meas)
+        t_b = max(out[r.rid].done_s for r in meas)
+        lat = serve.latency_summary({r.rid: out[r.rid] for r in meas})
+        sizes = eng.sched.stats.batch_sizes
+        res = {"qps_offered": None if qps == 0 else round(qps, 2), "requests": n_m,
+               "req_per_s": round(n_m / (t_b - t_a), 2) if qps else round(n_m / (t_b - t0), 2),
+               "pair_gbases_s": round(work(meas) / ((t_b - t_a) if qps else (t_b - t0)) / 1e9, 2),
+               "latency": lat, "batches": len(sizes), "mean_batch": round(float(np.mean(sizes)), 2),
+               "wall_s": round(wall, 2)}
+        log("serve %s: %s" % ("closed" if qps == 0 else "qps %.1f" % qps, json.dumps(res)))
+        return res
+
+    eng.serve(synth.gen_requests(wl, 8, qps=0, seed=99))   # warm the executor's buffers
+    # the same kind of requests served one per pass (no batching), closed loop
+    one = synth.gen_requests(wl, max(8, n_m // 20), qps=0, seed=7)
+    eng.sched.max_requests = 1
+    t1 = time.perf_counter()
+    eng.serve(one)
+    dt1 = time.perf_counter() - t1
+    eng.sched.max_requests = serve.MAX_REQ_PER_BATCH
+    single = {"requests": len(one), "req_per_s": round(len(one) / dt1, 2),
+              "pair_gbases_s": round(work(one) / dt1 / 1e9, 2)}
+    log("serve one-at-a-time: %s" % json.dumps(single))
+    closed = run(0.0, seed=1)
+    mu = closed["req_per_s"]
+    open_runs = [run(f * mu, seed=2 + i) for i, f in enumerate((0.5, 0.8))]
+    # scan roofline: the masked scan of the last batch shape, timed alone
+    nh = eng.exe.last_counts[0] if eng.exe.last_counts else 0
+    kern = "ah_scan_jit" if eng.exe.pool_ps.jit else "ah_scan_kernel"
+    total = wl.total_bases
+    out = {
+        "metric": "Gbases scanned/s per primer pair (k mm) + % HBM peak; batched vs plain; p50/p99 latency",
+        "value": closed["pair_gbases_s"], "unit": "pair-Gbases/s", "n_gpus": 1, "steps": n_m, "warmup": n_w,
+        "ms_per_step": round(1e3 / mu, 4) if mu else None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32/f64", "data": "synthetic",
+        "config": {"workload": "serve: %d seqs x 3-5 Mb, %.2f Gbases resident, pool of %d pairs; requests of "
+                               "1-8 pairs x 100-5000 sequences, k 0-3, Tm threshold 40-60 C; step = one request"
+                               % (wl.n_seqs, total / 1e9, len(wl.pairs)),
+                   "pairs": len(wl.pairs), "bases": total, "budget_mb": args.budget_mb, "scan_kernel": kern},
+        "serve": {"closed_loop": closed, "poisson_0.5mu": open_runs[0], "poisson_0.8mu": open_runs[1],
+                  "one_request_per_pass": single,
+                  "batching_speedup": round(closed["req_per_s"] / single["req_per_s"], 3)},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def synth_extract(wl):
     from paper_2511_00170_amd import synth
     return synth.ExtractSpec(trim=wl.extract.trim, fb_len=wl.extract.fb_len, rb_len=wl.extract.rb_len)
@@ -198,6 +278,8 @@ def main():
         torch.cuda.synchronize()
         del src_t, dst_t
     t0 = time.time()
+    if args.serve:
+        args.config = 5
     wl = synth.gen_config(args.config, n_seqs=args.n_seqs, len_scale=args.len_scale)
     total = wl.total_bases
     log("workload %s: %d sequences, %.3f Gbases" % (wl.name, wl.n_seqs, total / 1e9))
@@ -217,6 +299,8 @@ def main():
     store = ah.Store(wl.lengths)
     store.pack_chunks(chunks())
     log("generated + packed in %.1f s (store %.2f GB)" % (time.time() - t0, store.hbm_bytes / 1e9))
+    if args.serve:
+        return bench_serve(args, wl, store)
     if len(wl.pairs) > 1:
         return bench_batch(args, wl, store, sample)
 

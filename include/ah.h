@@ -170,6 +170,34 @@ ah_status ah_scan_primers(const ah_store *st, ah_primer_set ps, const uint32_t *
                           ah_hit *d_hits, uint64_t hit_cap, uint64_t *d_n_hits, void *d_ws, uint64_t ws_bytes,
                           void *stream);
 
+/* As ah_scan_primers, with the pairs scanned chosen per listed sequence:
+ * d_pair_mask[i] (device, one word per listed sequence, i.e. per subset entry
+ * or per store sequence when d_seq_subset is NULL) has bit q set when pair q
+ * is to be scanned on that sequence.  The hits are exactly those of
+ * ah_scan_primers restricted to the (sequence, pair) combinations asked for;
+ * a sequence whose word is 0 still costs its loads, so callers leave it out
+ * of the subset.  Serving uses this to batch requests that ask for different
+ * pairs on different sequences (Discussion and Methods, "Webserver").
+ * Errors: as ah_scan_primers; AH_E_LIMIT if the set has more than 64 pairs. */
+ah_status ah_scan_primers_masked(const ah_store *st, ah_primer_set ps, const uint32_t *d_seq_subset,
+                                 uint32_t n_subset, const uint64_t *d_pair_mask, ah_hit *d_hits, uint64_t hit_cap,
+                                 uint64_t *d_n_hits, void *d_ws, uint64_t ws_bytes, void *stream);
+
+/* Route hits of a shared scan to the requests of a serving batch (Discussion
+ * and Methods, "Webserver").  Hit h = (seq s, pair q, mm) is copied once for
+ * every request r < n_req with bit r of d_seq_req[s] set (the request asked
+ * for sequence s), d_vpair[r * n_pool + q] != 0xFFFF (it asked for pool pair
+ * q) and mm <= d_kmax[r] (its own mismatch bound).  The copy's pair field is
+ * d_vpair[r * n_pool + q]: the request's own slot in the primer set that the
+ * pair / Tm / extract calls of the batch use.  All arrays are device memory:
+ * d_seq_req[n_seqs] (store sequence index -> request bitmap), d_vpair[n_req *
+ * n_pool], d_kmax[n_req].  Writes min(total, out_cap) copies in arbitrary
+ * order and *d_n_out = total (the call resets it).  n_req <= 64; the first
+ * min(*d_n_hits, hit_cap) hits are read.  Errors: AH_E_ARG, AH_E_LIMIT. */
+ah_status ah_route_hits(const ah_hit *d_hits, const uint64_t *d_n_hits, uint64_t hit_cap, uint32_t n_seqs,
+                        const uint64_t *d_seq_req, const uint16_t *d_vpair, const uint8_t *d_kmax, uint32_t n_req,
+                        uint32_t n_pool, ah_hit *d_out, uint64_t out_cap, uint64_t *d_n_out, void *stream);
+
 /* ------------------------------------------------------------------------
  * Pair (Supplementary, "Amplicon calling and orientation").  Per (sequence,
  * pair) the sites are sorted by (start, end, plus before minus, forward
@@ -222,6 +250,10 @@ typedef struct {
     double threshold_C;
     int32_t saltcorr;
     int32_t filter;
+    /* NULL, or a device array with one threshold (C) per pair of the set that
+     * replaces threshold_C for that pair's amplicons (serving batches whose
+     * requests ask for different thresholds). */
+    const double *d_pair_threshold;
 } ah_tm_params;
 
 /* d_tm[n], d_tm_site[n][2] (upstream, downstream), d_pass[n]; n = min(*d_n_amps, amp_cap). */

@@ -52,7 +52,7 @@ class ah_pair_spec(C.Structure):
 class ah_tm_params(C.Structure):
     _fields_ = [("na_mM", C.c_double), ("k_mM", C.c_double), ("tris_mM", C.c_double), ("mg_mM", C.c_double),
                 ("dntps_mM", C.c_double), ("dnac1_nM", C.c_double), ("dnac2_nM", C.c_double),
-                ("threshold_C", C.c_double), ("saltcorr", I32), ("filter", I32)]
+                ("threshold_C", C.c_double), ("saltcorr", I32), ("filter", I32), ("d_pair_threshold", VP)]
 
 
 class ah_extract_opts(C.Structure):
@@ -82,6 +82,8 @@ _sig("ah_primers_use_jit", I32, VP, I32)
 _sig("ah_primers_launch_shape", I32, VP, I32, C.POINTER(I32))
 _sig("ah_scan_ws_size", I32, C.POINTER(ah_store), U32, C.POINTER(U64))
 _sig("ah_scan_primers", I32, C.POINTER(ah_store), VP, VP, U32, VP, U64, VP, VP, U64, VP)
+_sig("ah_scan_primers_masked", I32, C.POINTER(ah_store), VP, VP, U32, VP, VP, U64, VP, VP, U64, VP)
+_sig("ah_route_hits", I32, VP, VP, U64, U32, VP, VP, VP, U32, U32, VP, U64, VP, VP)
 _sig("ah_pair_ws_size", I32, C.POINTER(ah_store), VP, U64, C.POINTER(U64))
 _sig("ah_pair_amplicons", I32, C.POINTER(ah_store), VP, VP, VP, U64, U32, VP, U64, VP, VP, U64, VP)
 _sig("ah_tm_nn", I32, C.POINTER(ah_store), VP, VP, VP, U64, C.POINTER(ah_tm_params), VP, VP, VP, VP)
@@ -93,7 +95,7 @@ _sig("ah_extract", I32, C.POINTER(ah_store), VP, VP, VP, U64, VP, C.POINTER(ah_e
 EXPORTED = ["ah_status_str", "ah_version", "ah_pack_layout", "ah_pack_begin", "ah_pack", "ah_pack_finish",
             "ah_unpack", "ah_primers_compile", "ah_primers_free", "ah_primers_count", "ah_primers_jit", "ah_primers_use_jit",
             "ah_primers_launch_shape", "ah_scan_ws_size",
-            "ah_scan_primers", "ah_pair_ws_size", "ah_pair_amplicons", "ah_tm_nn", "ah_tm_duplex",
+            "ah_scan_primers", "ah_scan_primers_masked", "ah_route_hits", "ah_pair_ws_size", "ah_pair_amplicons", "ah_tm_nn", "ah_tm_duplex",
             "ah_extract_ws_size", "ah_extract"]
 
 HIT_DTYPE = np.dtype([("seq", "<u4"), ("pos", "<u4"), ("pair", "<u2"), ("kind", "u1"), ("mm", "u1")])
@@ -296,6 +298,21 @@ def scan_primers(store, ps, hits, hit_cap, n_hits, ws, subset=None, stream=None)
     n_sub = 0 if subset is None else int(subset.numel())
     check(_lib.ah_scan_primers(C.byref(store.c), ps.h, _p(subset), n_sub, _p(hits), hit_cap, _p(n_hits), _p(ws),
                                ws.numel() * ws.element_size(), _stream(stream)), "ah_scan_primers")
+
+
+def scan_primers_masked(store, ps, subset, pair_mask, hits, hit_cap, n_hits, ws, stream=None):
+    """Scan with the pairs chosen per listed sequence (pair_mask: int64 tensor,
+    one word per subset entry)."""
+    n_sub = int(subset.numel()) if subset is not None else store.n_seqs
+    assert pair_mask.numel() >= n_sub and pair_mask.dtype == torch.int64
+    check(_lib.ah_scan_primers_masked(C.byref(store.c), ps.h, _p(subset), n_sub if subset is not None else 0,
+                                      _p(pair_mask), _p(hits), hit_cap, _p(n_hits), _p(ws),
+                                      ws.numel() * ws.element_size(), _stream(stream)), "ah_scan_primers_masked")
+
+
+def route_hits(hits, n_hits, hit_cap, n_seqs, seq_req, vpair, kmax, n_req, n_pool, out, out_cap, n_out, stream=None):
+    check(_lib.ah_route_hits(_p(hits), _p(n_hits), hit_cap, n_seqs, _p(seq_req), _p(vpair), _p(kmax), n_req, n_pool,
+                             _p(out), out_cap, _p(n_out), _stream(stream)), "ah_route_hits")
 
 
 def pair_amplicons(store, ps, hits, n_hits, hit_cap, orient_mask, amps, amp_cap, n_amps, ws, stream=None):

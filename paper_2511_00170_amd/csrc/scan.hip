@@ -270,9 +270,9 @@ extern "C" ah_status ah_primers_launch_shape(ah_primer_set ps, int32_t wg_per_cu
 
 // ---------------------------------------------------------------- entry point
 
-extern "C" ah_status ah_scan_primers(const ah_store *st, ah_primer_set ps, const uint32_t *d_seq_subset,
-                                     uint32_t n_subset, ah_hit *d_hits, uint64_t hit_cap, uint64_t *d_n_hits,
-                                     void *d_ws, uint64_t ws_bytes, void *stream) {
+static ah_status scan_launch(const ah_store *st, ah_primer_set ps, const uint32_t *d_seq_subset, uint32_t n_subset,
+                             const uint64_t *d_pair_mask, ah_hit *d_hits, uint64_t hit_cap, uint64_t *d_n_hits,
+                             void *d_ws, uint64_t ws_bytes, void *stream) {
     if (!st || !ps || !d_n_hits || (hit_cap && !d_hits)) return AH_E_ARG;
     if (!st->d_blocks || !st->d_seq_block0 || !st->d_seq_len || !st->d_nbits) return AH_E_ARG;
     const uint32_t n_list = d_seq_subset ? n_subset : st->n_seqs;
@@ -295,6 +295,7 @@ extern "C" ah_status ah_scan_primers(const ah_store *st, ah_primer_set ps, const
     a.list = d_seq_subset;
     a.n_list = n_list;
     a.tile_pref = pref;
+    a.gmask = d_pair_mask;
     a.hits = (uint32_t *)d_hits;
     a.hit_cap = hit_cap;
     a.n_hits = d_n_hits;
@@ -313,4 +314,20 @@ extern "C" ah_status ah_scan_primers(const ah_store *st, ah_primer_set ps, const
     }
     hipLaunchKernelGGL(ah_scan_kernel, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
+}
+
+extern "C" ah_status ah_scan_primers(const ah_store *st, ah_primer_set ps, const uint32_t *d_seq_subset,
+                                     uint32_t n_subset, ah_hit *d_hits, uint64_t hit_cap, uint64_t *d_n_hits,
+                                     void *d_ws, uint64_t ws_bytes, void *stream) {
+    return scan_launch(st, ps, d_seq_subset, n_subset, nullptr, d_hits, hit_cap, d_n_hits, d_ws, ws_bytes, stream);
+}
+
+extern "C" ah_status ah_scan_primers_masked(const ah_store *st, ah_primer_set ps, const uint32_t *d_seq_subset,
+                                            uint32_t n_subset, const uint64_t *d_pair_mask, ah_hit *d_hits,
+                                            uint64_t hit_cap, uint64_t *d_n_hits, void *d_ws, uint64_t ws_bytes,
+                                            void *stream) {
+    if (!ps || !d_pair_mask) return AH_E_ARG;
+    if (ps->n_pairs > 64) return AH_E_LIMIT;
+    return scan_launch(st, ps, d_seq_subset, n_subset, d_pair_mask, d_hits, hit_cap, d_n_hits, d_ws, ws_bytes,
+                       stream);
 }

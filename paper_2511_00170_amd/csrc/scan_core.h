@@ -32,6 +32,7 @@ struct ScanArgs {
     const uint32_t *list;        // listed sequences (nullptr: every sequence)
     uint32_t n_list;
     const uint64_t *tile_pref;   // [n_list + 1] first tile of each listed sequence
+    const uint64_t *gmask;       // [n_list] groups to scan per listed sequence (nullptr: all)
     uint32_t *hits;              // ah_hit records, 3 words each
     uint64_t hit_cap;
     uint64_t *n_hits;
@@ -82,9 +83,11 @@ struct SeqCursor {
     uint32_t nblk;
     uint64_t blk0;
     uint64_t tp0, tp1; // tile_pref[i], tile_pref[i + 1]
+    uint64_t gm;       // groups scanned on this sequence (bit g)
 
     __device__ void load(const ScanArgs &a) {
         seq = ah_uni(a.list ? a.list[i] : i);
+        gm = a.gmask ? ah_uni64(a.gmask[i]) : ~0ull;
         len = ah_uni(a.st.d_seq_len[seq]);
         nblk = (len + 63u) / 64u;
         blk0 = ah_uni64(a.st.d_seq_block0[seq]);
@@ -340,6 +343,7 @@ __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat
             Sl[i][1] = ah_funnel(nl0, l1, i);
         }
         for (uint32_t g = 0; g < groups; g++) {
+            if (g < 64 && !((cur.gm >> g) & 1ull)) continue;  // group not asked for on this sequence
             // Mark the shifted planes as redefined in every iteration (an empty
             // asm, no instruction): otherwise, with compile-time codes, the
             // compiler hoists every group's set tests out of this loop as

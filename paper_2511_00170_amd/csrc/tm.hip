@@ -324,14 +324,15 @@ __global__ void __launch_bounds__(256) ah_tm_site_kernel(ah_store st, const DPai
     }
 }
 
-__global__ void ah_tm_finish_kernel(const double *tm_site, const uint64_t *d_n, uint64_t cap, ah_tm_params prm,
-                                    double *tm, uint8_t *pass) {
+__global__ void ah_tm_finish_kernel(const double *tm_site, const ah_amp *amps, const uint64_t *d_n, uint64_t cap,
+                                    ah_tm_params prm, double *tm, uint8_t *pass) {
     const uint64_t n = *d_n < cap ? *d_n : cap;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
         const double t1 = tm_site[2 * i], t2 = tm_site[2 * i + 1];
         const double t = t1 < t2 ? t1 : t2;  // the weaker primer limits the amplicon
+        const double thr = prm.d_pair_threshold ? prm.d_pair_threshold[amps[i].pair] : prm.threshold_C;
         tm[i] = t;
-        pass[i] = prm.filter ? (uint8_t)(t >= prm.threshold_C) : (uint8_t)1;
+        pass[i] = prm.filter ? (uint8_t)(t >= thr) : (uint8_t)1;
     }
 }
 
@@ -348,8 +349,8 @@ extern "C" ah_status ah_tm_nn(const ah_store *st, ah_primer_set ps, const ah_amp
     if (wgs > 16384) wgs = 16384;
     hipLaunchKernelGGL(ah_tm_site_kernel, dim3((unsigned)wgs), dim3(256), 0, s, *st, (const DPair *)ps->d_pairs,
                        (const uint32_t *)d_amps, d_n_amps, amp_cap, *p, d_tm_site);
-    hipLaunchKernelGGL(ah_tm_finish_kernel, dim3(256), dim3(256), 0, s, (const double *)d_tm_site, d_n_amps, amp_cap,
-                       *p, d_tm, d_pass);
+    hipLaunchKernelGGL(ah_tm_finish_kernel, dim3(256), dim3(256), 0, s, (const double *)d_tm_site, d_amps, d_n_amps,
+                       amp_cap, *p, d_tm, d_pass);
     return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
 }
 
