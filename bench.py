@@ -51,6 +51,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def scan_source_hash():
+    """sha256 over the sources the scan kernel is built from (host launcher,
+    device core, device types); the counters are trusted only for this hash."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("scan.hip", "scan_core.h", "ah_dev.h"):
+        h.update(open(os.path.join(ROOT, "paper_2511_00170_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_from_profiles(kernel_src_hash):
     """HBM bytes per scan launch from committed rocprofv3 counter runs, if they
     were taken on the current scan kernel source; else None."""
@@ -262,7 +272,6 @@ def main():
         print("bench.py: this build runs on one GPU; --gpus %d is not supported (use --gpus 1)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
-    import hashlib
 
     import numpy as np
     import torch
@@ -333,8 +342,7 @@ def main():
     gbases_s = total / (ms_step / 1e3) / 1e9
     alg_bytes = BYTES_PER_BASE * total + 12.0 * n_hits
     achieved = alg_bytes / (scan_ms / 1e3) / 1e9
-    src = open(os.path.join(ROOT, "paper_2511_00170_amd", "csrc", "scan.hip"), "rb").read()
-    traffic = traffic_from_profiles(hashlib.sha256(src).hexdigest())
+    traffic = traffic_from_profiles(scan_source_hash())
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "ah_scan_jit" if ps.jit else "ah_scan_kernel", "kernel_ms": round(scan_ms, 4),

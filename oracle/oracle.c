@@ -20,6 +20,12 @@
  *     extraction"; header fields: Supplementary "Headers and outputs".
  * Where the paper is silent the readings are named in comments (R-...).
  *
+ * Parity unpinned: the numeric values of the internal-mismatch and
+ * terminal-mismatch nearest-neighbour stacks.  They are transcribed from the
+ * primary papers cited at the tables, but no published Tm of a mismatched
+ * duplex is available to pin them; the Watson-Crick stacks, the salt and
+ * concentration terms and the documented Biopython value are pinned.
+ *
  * Records exchanged with the Python wrapper (oracle/__init__.py):
  *   hit: 4 x u32 = {seq, pos, pair, kind | mm << 8}
  *        kind bit0 = reverse primer, bit1 = minus strand (site of rc(primer))
