@@ -129,6 +129,13 @@ uint32_t ah_primers_count(ah_primer_set ps);
  * AH_E_HIP if hipRTC or module loading fails (the generic kernel stays). */
 ah_status ah_primers_jit(ah_primer_set ps);
 
+/* Generate and compile (without loading) the specialised scan kernel of the
+ * primer pairs h_pairs[n_pairs] for the GPU architecture `arch` (e.g.
+ * "gfx950"); touches no device.  AH_OK when it compiles; the primer errors
+ * of ah_primers_compile; AH_E_HIP when hipRTC fails (its log goes to
+ * stderr).  For build checks on machines without a GPU. */
+ah_status ah_primers_jit_check(const ah_pair_spec *h_pairs, uint32_t n_pairs, const char *arch);
+
 /* Switch between the specialised (on != 0, needs ah_primers_jit first) and
  * the generic scan kernel for this set. */
 ah_status ah_primers_use_jit(ah_primer_set ps, int32_t on);

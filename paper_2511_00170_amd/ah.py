@@ -78,6 +78,7 @@ _sig("ah_primers_compile", I32, C.POINTER(ah_pair_spec), U32, C.POINTER(VP))
 _sig("ah_primers_free", None, VP)
 _sig("ah_primers_count", U32, VP)
 _sig("ah_primers_jit", I32, VP)
+_sig("ah_primers_jit_check", I32, C.POINTER(ah_pair_spec), U32, C.c_char_p)
 _sig("ah_primers_use_jit", I32, VP, I32)
 _sig("ah_primers_launch_shape", I32, VP, I32, C.POINTER(I32))
 _sig("ah_scan_ws_size", I32, C.POINTER(ah_store), U32, C.POINTER(U64))
@@ -93,7 +94,7 @@ _sig("ah_extract", I32, C.POINTER(ah_store), VP, VP, VP, U64, VP, C.POINTER(ah_e
      VP, VP, VP, VP, VP, U64, VP)
 
 EXPORTED = ["ah_status_str", "ah_version", "ah_pack_layout", "ah_pack_begin", "ah_pack", "ah_pack_finish",
-            "ah_unpack", "ah_primers_compile", "ah_primers_free", "ah_primers_count", "ah_primers_jit", "ah_primers_use_jit",
+            "ah_unpack", "ah_primers_compile", "ah_primers_free", "ah_primers_count", "ah_primers_jit", "ah_primers_jit_check", "ah_primers_use_jit",
             "ah_primers_launch_shape", "ah_scan_ws_size",
             "ah_scan_primers", "ah_scan_primers_masked", "ah_route_hits", "ah_pair_ws_size", "ah_pair_amplicons", "ah_tm_nn", "ah_tm_duplex",
             "ah_extract_ws_size", "ah_extract"]
@@ -262,6 +263,18 @@ class PrimerSet:
             self.close()
         except Exception:
             pass
+
+
+def jit_check(pairs, arch: str = "gfx950") -> int:
+    """Generate and compile the specialised scan kernel of `pairs` for `arch`
+    without loading it (no GPU needed); returns the ah_status."""
+    arr = (ah_pair_spec * max(len(pairs), 1))()
+    keep = []
+    for i, p in enumerate(pairs):
+        f, r = p.fwd.encode(), p.rev.encode()
+        keep += [f, r]
+        arr[i] = ah_pair_spec(f, r, int(p.k), int(p.clamp), int(p.min_len), int(p.max_len))
+    return int(_lib.ah_primers_jit_check(arr, len(pairs), arch.encode()))
 
 
 def tm_params(tm) -> ah_tm_params:

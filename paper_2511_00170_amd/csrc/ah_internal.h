@@ -23,6 +23,9 @@ struct ah_primer_set_ {
 };
 
 void ah_jit_free(void *jit);
+// Host tables of a primer set; with host_only no device memory is touched
+// (such a set may only be inspected or freed).
+ah_status ah_build_primer_set(const ah_pair_spec *h_pairs, uint32_t n_pairs, bool host_only, ah_primer_set *out);
 
 // ---------------------------------------------------------------- helpers
 #define AH_CHECK_HIP(x)                         \

@@ -113,7 +113,8 @@ static void make_primer(const int *m, int L, DPrimer *p) {
     p->D = D > AH_MAX_VARIANTS ? 0u : (uint32_t)D;  // 0: too many variants for Tm
 }
 
-extern "C" ah_status ah_primers_compile(const ah_pair_spec *h_pairs, uint32_t n_pairs, ah_primer_set *out) {
+// Build the primer set's host tables; unless host_only, also its device tables.
+ah_status ah_build_primer_set(const ah_pair_spec *h_pairs, uint32_t n_pairs, bool host_only, ah_primer_set *out) {
     if (!out || (!h_pairs && n_pairs)) return AH_E_ARG;
     if (n_pairs == 0) return AH_E_ARG;
     if (n_pairs > AH_MAX_PAIRS) return AH_E_LIMIT;
@@ -163,6 +164,10 @@ extern "C" ah_status ah_primers_compile(const ah_pair_spec *h_pairs, uint32_t n_
     memcpy(ps->h_pats, pats.data(), pats.size() * sizeof(DPat));
     ps->h_pairs = new DPair[n_pairs];
     memcpy(ps->h_pairs, prs.data(), prs.size() * sizeof(DPair));
+    if (host_only) {
+        *out = ps;
+        return AH_OK;
+    }
     if (hipGetDevice(&ps->device) != hipSuccess ||
         hipMalloc((void **)&ps->d_pats, pats.size() * sizeof(DPat)) != hipSuccess ||
         hipMalloc((void **)&ps->d_pairs, prs.size() * sizeof(DPair)) != hipSuccess ||
@@ -173,6 +178,10 @@ extern "C" ah_status ah_primers_compile(const ah_pair_spec *h_pairs, uint32_t n_
     }
     *out = ps;
     return AH_OK;
+}
+
+extern "C" ah_status ah_primers_compile(const ah_pair_spec *h_pairs, uint32_t n_pairs, ah_primer_set *out) {
+    return ah_build_primer_set(h_pairs, n_pairs, false, out);
 }
 
 extern "C" void ah_primers_free(ah_primer_set ps) {

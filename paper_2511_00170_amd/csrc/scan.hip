@@ -76,6 +76,8 @@ struct GenericFilter {
     }
 };
 
+// kLdsOnly: every pattern record fits in LDS (at most AH_LDS_PATS patterns).
+template <bool kLdsOnly>
 __global__ void __launch_bounds__(256) ah_scan_kernel(ScanArgs a) {
     __shared__ DPat sPat[AH_LDS_PATS];
     __shared__ TileCtx sCtx[4][AH_NCTX];
@@ -84,7 +86,7 @@ __global__ void __launch_bounds__(256) ah_scan_kernel(ScanArgs a) {
     ah_stage_patterns(a, sPat, AH_LDS_PATS);
     const uint32_t n_lds = a.n_pats < AH_LDS_PATS ? a.n_pats : AH_LDS_PATS;
     GenericFilter f{sPat, a.pats, n_lds};
-    ah_scan_body(a, f, sPat, n_lds, sCtx, sQ, sW);
+    ah_scan_body<kLdsOnly>(a, f, sPat, n_lds, sCtx, sQ, sW);
 }
 
 // ---------------------------------------------------------------- tile table
@@ -161,6 +163,7 @@ static std::string jit_source(const ah_primer_set_ *ps) {
     s += "    }\n  }\n};\n";
     const uint32_t n_lds = ps->n_pats < AH_LDS_PATS ? ps->n_pats : AH_LDS_PATS;
     s += "#define AH_JIT_LDS_PATS " + std::to_string(n_lds) + "u\n";
+    s += std::string("#define AH_JIT_LDS_ONLY ") + (ps->n_pats <= AH_LDS_PATS ? "true" : "false") + "\n";
     s += "extern \"C\" __global__ void __launch_bounds__(256) ah_scan_jit(ScanArgs a) {\n"
          "  __shared__ DPat sPat[AH_JIT_LDS_PATS];\n"
          "  __shared__ TileCtx sCtx[4][AH_NCTX];\n"
@@ -168,7 +171,7 @@ static std::string jit_source(const ah_primer_set_ *ps) {
          "  __shared__ uint32_t sW[4][AH_NCTX][2][AH_TW];\n"
          "  ah_stage_patterns(a, sPat, AH_JIT_LDS_PATS);\n"
          "  JitFilter f;\n"
-         "  ah_scan_body(a, f, sPat, AH_JIT_LDS_PATS, sCtx, sQ, sW);\n"
+         "  ah_scan_body<AH_JIT_LDS_ONLY>(a, f, sPat, AH_JIT_LDS_PATS, sCtx, sQ, sW);\n"
          "}\n";
     return s;
 }
@@ -179,23 +182,13 @@ static int device_cus(int dev) {
     return cus;
 }
 
-extern "C" ah_status ah_primers_jit(ah_primer_set ps) {
-    if (!ps) return AH_E_ARG;
-    if (ps->jit) {
-        ps->use_jit = 1;
-        return AH_OK;
-    }
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return AH_E_HIP;
+// Compile the specialised kernel for `arch` (e.g. "gfx950"); code object in *code.
+static ah_status jit_compile(const ah_primer_set_ *ps, const std::string &arch, std::vector<char> *code) {
     const std::string src = jit_source(ps);
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.c_str(), "ah_scan_jit.hip", AH_JIT_NHEADERS, kJitHeaderText,
                             kJitHeaderNames) != HIPRTC_SUCCESS)
         return AH_E_HIP;
-    std::string arch = prop.gcnArchName;
-    const size_t colon = arch.find(':');  // drop feature suffixes such as ":sramecc+:xnack-"
-    if (colon != std::string::npos) arch = arch.substr(0, colon);
     const std::string arch_opt = "--offload-arch=" + arch;
     const char *opts[] = {arch_opt.c_str(), "-O3", "-std=c++17", "-ffp-contract=off"};
     if (hiprtcCompileProgram(prog, 4, opts) != HIPRTC_SUCCESS) {
@@ -209,9 +202,38 @@ extern "C" ah_status ah_primers_jit(ah_primer_set ps) {
     }
     size_t code_n = 0;
     hiprtcGetCodeSize(prog, &code_n);
-    std::vector<char> code(code_n);
-    hiprtcGetCode(prog, code.data());
+    code->assign(code_n, 0);
+    hiprtcGetCode(prog, code->data());
     hiprtcDestroyProgram(&prog);
+    return AH_OK;
+}
+
+extern "C" ah_status ah_primers_jit_check(const ah_pair_spec *h_pairs, uint32_t n_pairs, const char *arch) {
+    if (!arch || !*arch) return AH_E_ARG;
+    ah_primer_set ps = nullptr;
+    ah_status st = ah_build_primer_set(h_pairs, n_pairs, true, &ps);
+    if (st != AH_OK) return st;
+    std::vector<char> code;
+    st = jit_compile(ps, arch, &code);
+    ah_primers_free(ps);
+    return st;
+}
+
+extern "C" ah_status ah_primers_jit(ah_primer_set ps) {
+    if (!ps) return AH_E_ARG;
+    if (ps->jit) {
+        ps->use_jit = 1;
+        return AH_OK;
+    }
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return AH_E_HIP;
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');  // drop feature suffixes such as ":sramecc+:xnack-"
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    std::vector<char> code;
+    const ah_status st = jit_compile(ps, arch, &code);
+    if (st != AH_OK) return st;
     AhJit *j = new AhJit();
     if (hipModuleLoadData(&j->mod, code.data()) != hipSuccess ||
         hipModuleGetFunction(&j->fn, j->mod, "ah_scan_jit") != hipSuccess) {
@@ -248,7 +270,8 @@ static int generic_per_cu() {
     static int per_cu = 0;
     if (!per_cu) {
         int v = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, ah_scan_kernel, 256, 0) != hipSuccess || v <= 0) v = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, ah_scan_kernel<false>, 256, 0) != hipSuccess || v <= 0)
+            v = 1;
         per_cu = v;
     }
     return per_cu;
@@ -312,7 +335,10 @@ static ah_status scan_launch(const ah_store *st, ah_primer_set ps, const uint32_
             return AH_E_HIP;
         return AH_OK;
     }
-    hipLaunchKernelGGL(ah_scan_kernel, dim3(grid), dim3(256), 0, s, a);
+    if (ps->n_pats <= AH_LDS_PATS)
+        hipLaunchKernelGGL(ah_scan_kernel<true>, dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(ah_scan_kernel<false>, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
 }
 

@@ -62,10 +62,10 @@ struct TileCtx {
 };
 
 #ifndef AH_QCAP
-#define AH_QCAP 128                       // queue entries per wave (>= 128)
+#define AH_QCAP 320                       // queue entries per wave: < 64 left over + 4 x 64 of one group
 #endif
 #ifndef AH_NCTX
-#define AH_NCTX 4                         // tiles whose candidates may wait in the queue (<= 4)
+#define AH_NCTX 2                         // tiles whose candidates may wait in the queue (<= 4)
 #endif
 #define AH_TW (2 * AH_TILE_BLOCKS + 2)    // words per plane of a tile (+ one word each side)
 
@@ -118,51 +118,51 @@ struct SeqCursor {
 struct TileLoad {
     uint4 blk;       // this lane's block (lanes past the end repeat the last one)
     uint4 hal;       // lane 0: the block before the tile; lane 63: the block after it
-    uint32_t nbw;    // N-bitmap word holding this lane's block
-    uint32_t nbw_h;  // N-bitmap word holding the halo block
+    uint32_t nbw;    // lanes 0-3: the N-bitmap words around the tile (others repeat word 3)
     uint32_t nb;     // blocks in the tile (uniform)
     uint32_t rel0;   // first block of the tile within its sequence (uniform)
     uint64_t gb0;    // store block of the tile's first block (uniform)
-    uint32_t prev;   // a block precedes the tile in its sequence (uniform)
-    uint32_t next;   // a block follows the tile in its sequence (uniform)
 };
 
 __device__ __forceinline__ void tile_issue(const ScanArgs &a, const SeqCursor &c, uint64_t t, TileLoad &L) {
     const uint32_t lane = ah_lane();
-    const uint4 *blocks = (const uint4 *)a.st.d_blocks;
     L.rel0 = (uint32_t)(t - c.tp0) * AH_TILE_BLOCKS;
     const uint32_t left = c.nblk - L.rel0;
     L.nb = left < AH_TILE_BLOCKS ? left : AH_TILE_BLOCKS;
     L.gb0 = c.blk0 + L.rel0;
-    L.prev = L.rel0 > 0;
-    L.next = L.rel0 + AH_TILE_BLOCKS < c.nblk;
-    const uint4 *tb = blocks + L.gb0;
+    // Addresses are a uniform base plus a 32-bit per-lane byte offset (one
+    // vector op per load).  The base is the block before the tile (its
+    // address is formed but only read when that block is in the sequence):
+    // lane l reads block 1 + own, lane 0's halo is block 0 when the tile has
+    // a predecessor, lane 63's halo is block 65 when it has a successor.
+    const uint64_t base = (uint64_t)a.st.d_blocks + 16u * (uint64_t)L.gb0 - 16u;
     const uint32_t own = lane < L.nb ? lane : L.nb - 1;
-    int32_t hoff = (int32_t)own;
-    if (lane == 0 && L.prev) hoff = -1;
-    if (lane == 63 && L.next) hoff = AH_TILE_BLOCKS;
-    L.blk = tb[own];
-    L.hal = tb[hoff];
-    L.nbw = a.st.d_nbits[(L.gb0 + own) >> 5];
-    L.nbw_h = a.st.d_nbits[(uint64_t)((int64_t)L.gb0 + hoff) >> 5];
+    uint32_t o_hal = own + 1;
+    if (lane == 0 && L.rel0 != 0) o_hal = 0;
+    if (lane == 63 && L.rel0 + AH_TILE_BLOCKS < c.nblk) o_hal = AH_TILE_BLOCKS + 1;
+    L.blk = *(const uint4 *)(base + 16u * (own + 1));
+    L.hal = *(const uint4 *)(base + 16u * o_hal);
+    // N-bitmap words: the four words from wb = max(gb0/32, 1) - 1 cover
+    // blocks gb0-1 .. gb0+64.  A nonzero word means the tile may touch an N
+    // -- a superset, which only costs exact per-block lookups in verification.
+    const uint64_t q = L.gb0 >> 5;
+    const uint64_t wb = (q > 1 ? q : 1) - 1;
+    const uint64_t nw = (a.st.n_blocks + 31) >> 5;
+    const uint32_t room = (uint32_t)(nw - 1 - wb);  // words after wb
+    const uint32_t wi = lane < 3 ? (lane < room ? lane : room) : (3u < room ? 3u : room);
+    L.nbw = *(const uint32_t *)((uint64_t)a.st.d_nbits + 4u * (uint64_t)wb + 4u * wi);
 }
 
-// Any N in the tile's blocks or its halo blocks (wave-uniform result).
-__device__ __forceinline__ bool tile_has_n(const TileLoad &L) {
-    const uint32_t lane = ah_lane();
-    const uint32_t own = lane < L.nb ? lane : L.nb - 1;
-    const uint64_t gown = L.gb0 + own;
-    bool nf = (L.nbw >> (gown & 31)) & 1u;
-    if ((lane == 0 && L.prev) || (lane == 63 && L.next)) {
-        const uint64_t gh = lane == 0 ? L.gb0 - 1 : L.gb0 + AH_TILE_BLOCKS;
-        nf = nf || ((L.nbw_h >> (gh & 31)) & 1u);
-    }
-    return __ballot(nf) != 0;
-}
+// Any N in the tile's blocks or its halo blocks (wave-uniform, conservative).
+__device__ __forceinline__ bool tile_has_n(const TileLoad &L) { return __ballot(L.nbw != 0) != 0; }
 
+template <bool kLdsOnly>
 __device__ __forceinline__ void ah_pattern_record(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, uint32_t X,
                                                   uint4 &p0, uint4 &p1) {
-    if (X < n_lds) {
+    // With every record in LDS no global load is issued here: a global load
+    // in the verification path would have to wait for the next tile's
+    // prefetch as well (the vector memory counter is in order).
+    if (kLdsOnly || X < n_lds) {
         p0 = *(const uint4 *)&sPat[X].P[0];
         p1 = *(const uint4 *)&sPat[X].clampmask;
     } else {
@@ -174,6 +174,7 @@ __device__ __forceinline__ void ah_pattern_record(const ScanArgs &a, const DPat 
 // Verify queued entries [e0, e1) (at most 64: one per lane).  Entry =
 // {candidate mask bits 0-31, bits 32-63, X << 8 | ctx << 6 | lane}; windows
 // are read from the tile words kept in LDS (sW[ctx][plane][word]).
+template <bool kLdsOnly>
 __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
                                 const uint32_t (*sQ)[3], uint32_t e0, uint32_t e1,
                                 const uint32_t (*sW)[2][AH_TW]) {
@@ -184,7 +185,7 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
     const uint32_t X = tag >> 8, ci = (tag >> 6) & 3u, ln = tag & 63u;
     const TileCtx c = sCtx[ci];
     uint4 p0, p1;
-    ah_pattern_record(a, sPat, n_lds, X, p0, p1);
+    ah_pattern_record<kLdsOnly>(a, sPat, n_lds, X, p0, p1);
     const uint32_t L = p1.z & 0xFFu, k = (p1.z >> 8) & 0xFFu, shift = p1.z >> 24;
     const uint32_t *Wh = sW[ci][0], *Wl = sW[ci][1];
     // window starts (tile-relative) allowed by the sequence bounds
@@ -227,15 +228,16 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
 
 // Verify whole rounds of 64 queued entries; with drain, also the remainder.
 // Entries left over move to the front of the queue.
+template <bool kLdsOnly>
 __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
                                          uint32_t (*sQ)[3], uint32_t &qn, const uint32_t (*sW)[2][AH_TW],
                                          bool drain) {
     ah_wave_sync();
     uint32_t e0 = 0;
-    for (; e0 + 64 <= qn; e0 += 64) ah_verify_round(a, sPat, n_lds, sCtx, sQ, e0, e0 + 64, sW);
+    for (; e0 + 64 <= qn; e0 += 64) ah_verify_round<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, e0, e0 + 64, sW);
     if (drain) {
-        if (e0 < qn) ah_verify_round(a, sPat, n_lds, sCtx, sQ, e0, qn, sW);
-        qn = 0;
+        if (e0 < qn) ah_verify_round<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, e0, qn, sW);
+        qn = 0u;
     } else if (e0 > 0) {
         const uint32_t rest = qn - e0;  // < 64
         const uint32_t lane = ah_lane();
@@ -251,21 +253,110 @@ __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, ui
             sQ[lane][1] = v1;
             sQ[lane][2] = v2;
         }
-        qn = rest;
+        qn = ah_uni(rest);
     }
     ah_wave_sync();
+}
+
+// One tile, its blocks already loaded into L: record its context and words
+// for deferred verification, filter every pattern group, queue candidates,
+// and verify full rounds of queued candidates.
+template <bool kLdsOnly, class F>
+__device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds, TileCtx *sCtx,
+                                        uint32_t (*sQ)[3], uint32_t (*sW)[2][AH_TW], const TileLoad &L,
+                                        const SeqCursor &cur, uint32_t groups, uint32_t &qn, uint32_t &nctx) {
+    const uint32_t lane = ah_lane();
+    if (nctx == AH_NCTX) {  // every context slot is referenced: verify all
+        ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, true);
+        nctx = 0;
+    }
+    const uint32_t ci = nctx;
+    nctx = ah_uni(nctx + 1);
+    const bool has_n = tile_has_n(L);
+    if (lane == 0) {
+        TileCtx c;
+        c.gbase = L.gb0 * 64;
+        c.seq = cur.seq;
+        c.len = cur.len;
+        c.pos0 = L.rel0 * 64;
+        c.has_n = has_n;
+        sCtx[ci] = c;
+    }
+    const uint32_t h0 = L.blk.x, l0 = L.blk.y, h1 = L.blk.z, l1 = L.blk.w;
+    uint32_t nh0 = __shfl_down(h0, 1, 64), nl0 = __shfl_down(l0, 1, 64);
+    if (lane == 63) {
+        nh0 = L.hal.x;
+        nl0 = L.hal.y;
+    }
+    uint32_t *Wh = sW[ci][0], *Wl = sW[ci][1];
+    Wh[1 + 2 * lane] = h0;
+    Wh[2 + 2 * lane] = h1;
+    Wl[1 + 2 * lane] = l0;
+    Wl[2 + 2 * lane] = l1;
+    if (lane == 0) {
+        Wh[0] = L.hal.z;
+        Wl[0] = L.hal.w;
+    }
+    if (lane == 63) {
+        Wh[AH_TW - 1] = nh0;
+        Wl[AH_TW - 1] = nl0;
+    }
+    // lanes past the sequence end hold a repeated block: no candidates there
+    // (windows reaching past the end are rejected in verification)
+    const uint32_t v = lane < L.nb ? 0xFFFFFFFFu : 0u;
+    // bit q of S*[i][w]: plane bit of base q + i (w selects bases 0-31 / 32-63)
+    uint32_t Sh[AH_WMAX][2], Sl[AH_WMAX][2];
+#pragma unroll
+    for (int i = 0; i < AH_WMAX; i++) {
+        Sh[i][0] = ah_funnel(h1, h0, i);
+        Sh[i][1] = ah_funnel(nh0, h1, i);
+        Sl[i][0] = ah_funnel(l1, l0, i);
+        Sl[i][1] = ah_funnel(nl0, l1, i);
+    }
+    for (uint32_t g = 0; g < groups; g++) {
+        if (g < 64 && !((cur.gm >> g) & 1ull)) continue;  // group not asked for on this sequence
+        // Mark the shifted planes as redefined in every iteration (an empty
+        // asm, no instruction): otherwise, with compile-time codes, the
+        // compiler hoists every group's set tests out of this loop as
+        // invariants and runs out of registers once there are many groups.
+#pragma unroll
+        for (int i = 0; i < AH_WMAX; i++)
+            asm volatile("" : "+v"(Sh[i][0]), "+v"(Sh[i][1]), "+v"(Sl[i][0]), "+v"(Sl[i][1]));
+        uint32_t C[8];
+        f.filter(g, Sh, Sl, v, v, C);
+        const uint32_t any = (C[0] | C[1] | C[2] | C[3]) | (C[4] | C[5] | C[6] | C[7]);
+        if (__ballot(any != 0) == 0) continue;
+        // room for this group's candidates (at most 4 x 64 entries); a
+        // non-draining flush leaves fewer than 64
+        if (qn > AH_QCAP - 256) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, false);
+#pragma unroll
+        for (int x = 0; x < 4; x++) {
+            const bool nz = (C[2 * x] | C[2 * x + 1]) != 0;
+            const uint64_t bal = __ballot(nz);
+            if (nz) {
+                const uint32_t slot = qn + ah_mbcnt(bal);
+                sQ[slot][0] = C[2 * x];
+                sQ[slot][1] = C[2 * x + 1];
+                sQ[slot][2] = ((4 * g + (uint32_t)x) << 8) | (ci << 6) | lane;
+            }
+            qn = ah_uni(qn + (uint32_t)__popcll(bal));  // keeps the queue count in a scalar register
+        }
+    }
+    if (qn >= 64) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, false);
 }
 
 // The kernel body.  Filter F provides
 //   f.groups(a)                         number of pattern groups (primer pairs),
 //   f.filter(g, Sh, Sl, v0, v1, C)      candidate words of group g (C[2x], C[2x+1]:
 //                                       clamp sites 0-31 / 32-63 of pattern x).
-// n_lds: pattern records staged in sPat.
-template <class F>
+// n_lds: pattern records staged in sPat; kLdsOnly: n_lds covers every record.
+template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds,
                                              TileCtx (*sCtx_all)[AH_NCTX], uint32_t (*sQ_all)[AH_QCAP][3],
                                              uint32_t (*sW_all)[AH_NCTX][2][AH_TW]) {
-    const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform across the wave; saying so keeps the tile
+    // walk, the cursor and the queue bookkeeping in scalar registers
+    const uint32_t wv = ah_uni(threadIdx.x >> 6);
     TileCtx *sCtx = sCtx_all[wv];
     uint32_t(*sQ)[3] = sQ_all[wv];
     uint32_t(*sW)[2][AH_TW] = sW_all[wv];
@@ -280,102 +371,32 @@ __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat
     const uint64_t tend = t + per < total ? t + per : total;
     if (t >= tend) return;
 
-    SeqCursor cur;
-    cur.init(a, t);
-    TileLoad L;
-    tile_issue(a, cur, t, L);
     const uint32_t groups = f.groups(a);
     uint32_t qn = 0, nctx = 0;
-
-    for (; t < tend; t++) {
-        // issue the next tile's loads before working on this one (the last
-        // tile reloads itself, so the loads are unconditional)
-        const uint64_t tn = t + 1 < tend ? t + 1 : t;
+    SeqCursor cur;
+    cur.init(a, t);
+    // Two load sets used in turn: the next tile's loads go to the set not being
+    // processed, so no register copy (which would wait for them) is needed.
+    // The last tile reloads itself, so the loads are unconditional.
+    TileLoad A, B;
+    tile_issue(a, cur, t, A);
+    for (;;) {
+        uint64_t tn = t + 1 < tend ? t + 1 : t;
         SeqCursor nc = cur;
         nc.advance(a, tn);
-        TileLoad NL;
-        tile_issue(a, nc, tn, NL);
-
-        if (nctx == AH_NCTX) {  // every context slot is referenced: verify all
-            ah_flush(a, sPat, n_lds, sCtx, sQ, qn, sW, true);
-            nctx = 0;
-        }
-        const uint32_t ci = nctx++;
-        const bool has_n = tile_has_n(L);
-        if (lane == 0) {
-            TileCtx c;
-            c.gbase = L.gb0 * 64;
-            c.seq = cur.seq;
-            c.len = cur.len;
-            c.pos0 = L.rel0 * 64;
-            c.has_n = has_n;
-            sCtx[ci] = c;
-        }
-        const uint32_t h0 = L.blk.x, l0 = L.blk.y, h1 = L.blk.z, l1 = L.blk.w;
-        uint32_t nh0 = __shfl_down(h0, 1, 64), nl0 = __shfl_down(l0, 1, 64);
-        if (lane == 63) {
-            nh0 = L.hal.x;
-            nl0 = L.hal.y;
-        }
-        uint32_t *Wh = sW[ci][0], *Wl = sW[ci][1];
-        Wh[1 + 2 * lane] = h0;
-        Wh[2 + 2 * lane] = h1;
-        Wl[1 + 2 * lane] = l0;
-        Wl[2 + 2 * lane] = l1;
-        if (lane == 0) {
-            Wh[0] = L.hal.z;
-            Wl[0] = L.hal.w;
-        }
-        if (lane == 63) {
-            Wh[AH_TW - 1] = nh0;
-            Wl[AH_TW - 1] = nl0;
-        }
-        // lanes past the sequence end hold a repeated block: no candidates there
-        // (windows reaching past the end are rejected in verification)
-        const uint32_t v = lane < L.nb ? 0xFFFFFFFFu : 0u;
-        // bit q of S*[i][w]: plane bit of base q + i (w selects bases 0-31 / 32-63)
-        uint32_t Sh[AH_WMAX][2], Sl[AH_WMAX][2];
-#pragma unroll
-        for (int i = 0; i < AH_WMAX; i++) {
-            Sh[i][0] = ah_funnel(h1, h0, i);
-            Sh[i][1] = ah_funnel(nh0, h1, i);
-            Sl[i][0] = ah_funnel(l1, l0, i);
-            Sl[i][1] = ah_funnel(nl0, l1, i);
-        }
-        for (uint32_t g = 0; g < groups; g++) {
-            if (g < 64 && !((cur.gm >> g) & 1ull)) continue;  // group not asked for on this sequence
-            // Mark the shifted planes as redefined in every iteration (an empty
-            // asm, no instruction): otherwise, with compile-time codes, the
-            // compiler hoists every group's set tests out of this loop as
-            // invariants and runs out of registers once there are many groups.
-#pragma unroll
-            for (int i = 0; i < AH_WMAX; i++)
-                asm volatile("" : "+v"(Sh[i][0]), "+v"(Sh[i][1]), "+v"(Sl[i][0]), "+v"(Sl[i][1]));
-            uint32_t C[8];
-            f.filter(g, Sh, Sl, v, v, C);
-            const uint32_t any = (C[0] | C[1] | C[2] | C[3]) | (C[4] | C[5] | C[6] | C[7]);
-            if (__ballot(any != 0) == 0) continue;
-#pragma unroll
-            for (int x = 0; x < 4; x++) {
-                const bool nz = (C[2 * x] | C[2 * x + 1]) != 0;
-                const uint64_t bal = __ballot(nz);
-                if (!bal) continue;
-                const uint32_t cnt = (uint32_t)__popcll(bal);
-                if (qn + cnt > AH_QCAP) ah_flush(a, sPat, n_lds, sCtx, sQ, qn, sW, false);
-                if (nz) {
-                    const uint32_t slot = qn + ah_mbcnt(bal);
-                    sQ[slot][0] = C[2 * x];
-                    sQ[slot][1] = C[2 * x + 1];
-                    sQ[slot][2] = ((4 * g + (uint32_t)x) << 8) | (ci << 6) | lane;
-                }
-                qn += cnt;
-            }
-        }
-        if (qn >= 64) ah_flush(a, sPat, n_lds, sCtx, sQ, qn, sW, false);
+        tile_issue(a, nc, tn, B);
+        ah_tile<kLdsOnly>(a, f, sPat, n_lds, sCtx, sQ, sW, A, cur, groups, qn, nctx);
         cur = nc;
-        L = NL;
+        if (++t >= tend) break;
+        tn = t + 1 < tend ? t + 1 : t;
+        nc = cur;
+        nc.advance(a, tn);
+        tile_issue(a, nc, tn, A);
+        ah_tile<kLdsOnly>(a, f, sPat, n_lds, sCtx, sQ, sW, B, cur, groups, qn, nctx);
+        cur = nc;
+        if (++t >= tend) break;
     }
-    if (qn) ah_flush(a, sPat, n_lds, sCtx, sQ, qn, sW, true);
+    if (qn) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, true);
 }
 
 // Stage the first n pattern records in LDS (all threads of the block).

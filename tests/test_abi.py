@@ -61,3 +61,14 @@ def test_primer_compile_rejects_bad_input_without_gpu():
     assert lib.ah_primers_compile(clamp, 1, ctypes.byref(h)) == 3
     window = (Spec * 1)(Spec(b"ACGT", b"ACG", 1, 1, 100, 10))
     assert lib.ah_primers_compile(window, 1, ctypes.byref(h)) == 1
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 5])
+def test_specialised_scan_kernel_compiles_without_gpu(cfg):
+    """The hipRTC source generated for a primer set compiles for gfx950 (the
+    same headers and options the library uses at run time)."""
+    if not os.path.exists(LIB):
+        pytest.fail("libah.so is not built")
+    from paper_2511_00170_amd import ah, synth
+    wl = synth.gen_config(cfg, n_seqs=2, len_scale=1e-4)
+    assert ah.jit_check(wl.pairs, "gfx950") == ah.AH_OK
