@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--serve", action="store_true", help="serving workload (continuous batching, latency)")
     ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests per run")
     ap.add_argument("--warm-requests", type=int, default=200, help="serve: warm-up requests per run")
-    ap.add_argument("--budget-mb", type=int, default=2048, help="serve: device memory budget per batch")
+    ap.add_argument("--budget-mb", type=int, default=16384, help="serve: device memory budget per batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM counters)")
     return ap.parse_args()
@@ -190,6 +190,7 @@ def bench_serve(args, wl, store):
     def run(qps, seed):
         reqs = synth.gen_requests(wl, n_w + n_m, qps=qps, seed=seed)
         eng.sched.stats = serve.SchedStats()
+        eng.exe.host_s = dict(launch=0.0, wait=0.0, d2h=0.0, collect=0.0, batches=0, bytes=0)
         t0 = time.perf_counter()
         out = eng.serve(reqs)
         wall = time.perf_counter() - t0
@@ -203,7 +204,11 @@ def bench_serve(args, wl, store):
                "req_per_s": round(n_m / (t_b - t_a), 2) if qps else round(n_m / (t_b - t0), 2),
                "pair_gbases_s": round(work(meas) / ((t_b - t_a) if qps else (t_b - t0)) / 1e9, 2),
                "latency": lat, "batches": len(sizes), "mean_batch": round(float(np.mean(sizes)), 2),
-               "wall_s": round(wall, 2)}
+               "wall_s": round(wall, 2),
+               "host_ms_per_batch": {k: round(1e3 * v / max(eng.exe.host_s["batches"], 1), 3)
+                                     for k, v in eng.exe.host_s.items() if k not in ("batches", "bytes")},
+               "result_mb_per_batch": round(eng.exe.host_s.get("bytes", 0) / max(eng.exe.host_s["batches"], 1) / 1e6,
+                                            3)}
         log("serve %s: %s" % ("closed" if qps == 0 else "qps %.1f" % qps, json.dumps(res)))
         return res
 

@@ -121,6 +121,17 @@ ah_status ah_primers_compile(const ah_pair_spec *h_pairs, uint32_t n_pairs, ah_p
 void ah_primers_free(ah_primer_set ps);
 uint32_t ah_primers_count(ah_primer_set ps);
 
+/* As ah_primers_compile, but the device tables go into caller memory d_buf
+ * (at least ah_primers_table_bytes(n_pairs) bytes) by an asynchronous copy on
+ * `stream`: no allocation, no synchronisation, so a per-batch primer set can
+ * be built while other streams run (serving).  The handle does not own
+ * d_buf; keep both alive until the work using the set on `stream` is done,
+ * then ah_primers_free.  Errors: as ah_primers_compile; AH_E_WORKSPACE when
+ * d_buf is too small. */
+ah_status ah_primers_compile_into(const ah_pair_spec *h_pairs, uint32_t n_pairs, void *d_buf, uint64_t buf_bytes,
+                                  void *stream, ah_primer_set *out);
+uint64_t ah_primers_table_bytes(uint32_t n_pairs);
+
 /* Optional set-up step: compile, with hipRTC, a scan kernel whose clamp
  * pre-filter has this primer set's IUPAC codes as compile-time constants
  * (each set test folds into one bit operation) and use it for later

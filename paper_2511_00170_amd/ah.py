@@ -76,6 +76,8 @@ _sig("ah_pack_finish", I32, C.POINTER(ah_store), VP, U64, VP)
 _sig("ah_unpack", I32, C.POINTER(ah_store), U32, U64, U64, VP, VP)
 _sig("ah_primers_compile", I32, C.POINTER(ah_pair_spec), U32, C.POINTER(VP))
 _sig("ah_primers_free", None, VP)
+_sig("ah_primers_compile_into", I32, C.POINTER(ah_pair_spec), U32, VP, U64, VP, C.POINTER(VP))
+_sig("ah_primers_table_bytes", U64, U32)
 _sig("ah_primers_count", U32, VP)
 _sig("ah_primers_jit", I32, VP)
 _sig("ah_primers_jit_check", I32, C.POINTER(ah_pair_spec), U32, C.c_char_p)
@@ -94,7 +96,7 @@ _sig("ah_extract", I32, C.POINTER(ah_store), VP, VP, VP, U64, VP, C.POINTER(ah_e
      VP, VP, VP, VP, VP, U64, VP)
 
 EXPORTED = ["ah_status_str", "ah_version", "ah_pack_layout", "ah_pack_begin", "ah_pack", "ah_pack_finish",
-            "ah_unpack", "ah_primers_compile", "ah_primers_free", "ah_primers_count", "ah_primers_jit", "ah_primers_jit_check", "ah_primers_use_jit",
+            "ah_unpack", "ah_primers_compile", "ah_primers_compile_into", "ah_primers_table_bytes", "ah_primers_free", "ah_primers_count", "ah_primers_jit", "ah_primers_jit_check", "ah_primers_use_jit",
             "ah_primers_launch_shape", "ah_scan_ws_size",
             "ah_scan_primers", "ah_scan_primers_masked", "ah_route_hits", "ah_pair_ws_size", "ah_pair_amplicons", "ah_tm_nn", "ah_tm_duplex",
             "ah_extract_ws_size", "ah_extract"]
@@ -219,7 +221,9 @@ class PrimerSet:
     """Compiled primer pairs.  jit=True also compiles (hipRTC) a scan kernel
     specialised to these pairs; results are identical to the generic kernel."""
 
-    def __init__(self, pairs, jit: bool = False):
+    def __init__(self, pairs, jit: bool = False, table: Optional[torch.Tensor] = None, stream=None):
+        """table: optional device buffer (>= table_bytes(len(pairs)) bytes) that
+        receives the device tables by an asynchronous copy on `stream`."""
         self.pairs = list(pairs)
         arr = (ah_pair_spec * len(self.pairs))()
         self._keep = []
@@ -228,7 +232,12 @@ class PrimerSet:
             self._keep += [f, r]
             arr[i] = ah_pair_spec(f, r, int(p.k), int(p.clamp), int(p.min_len), int(p.max_len))
         h = VP()
-        check(_lib.ah_primers_compile(arr, len(self.pairs), C.byref(h)), "ah_primers_compile")
+        if table is None:
+            check(_lib.ah_primers_compile(arr, len(self.pairs), C.byref(h)), "ah_primers_compile")
+        else:
+            check(_lib.ah_primers_compile_into(arr, len(self.pairs), _p(table), table.numel() * table.element_size(),
+                                               _stream(stream), C.byref(h)), "ah_primers_compile_into")
+            self._table = table
         self.h = h
         self.jit = False       # specialised kernel selected
         self.has_jit = False   # specialised kernel compiled
@@ -263,6 +272,10 @@ class PrimerSet:
             self.close()
         except Exception:
             pass
+
+
+def table_bytes(n_pairs: int) -> int:
+    return int(_lib.ah_primers_table_bytes(n_pairs))
 
 
 def jit_check(pairs, arch: str = "gfx950") -> int:

@@ -20,6 +20,7 @@ struct ah_primer_set_ {
     void *jit;    // primer-set specialised scan kernel (ah_primers_jit), or null
     int use_jit;
     int wg_per_cu;  // persistent scan workgroups per CU (0 = resident maximum)
+    int owns_device; // d_pats / d_pairs were allocated by the library
 };
 
 void ah_jit_free(void *jit);
@@ -37,6 +38,8 @@ ah_status ah_build_primer_set(const ah_pair_spec *h_pairs, uint32_t n_pairs, boo
 static inline hipStream_t ah_stream(void *s) { return (hipStream_t)s; }
 
 static inline uint64_t ah_align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+// Device table layout inside one buffer: patterns first, then pair records.
+static inline uint64_t ah_pat_bytes(uint32_t n_pairs) { return ah_align_up(4ull * n_pairs * sizeof(DPat), 256); }
 
 static inline int ah_bits_for(uint64_t n) {  // bits to represent values 0..n-1
     int b = 0;

@@ -168,6 +168,7 @@ ah_status ah_build_primer_set(const ah_pair_spec *h_pairs, uint32_t n_pairs, boo
         *out = ps;
         return AH_OK;
     }
+    ps->owns_device = 1;
     if (hipGetDevice(&ps->device) != hipSuccess ||
         hipMalloc((void **)&ps->d_pats, pats.size() * sizeof(DPat)) != hipSuccess ||
         hipMalloc((void **)&ps->d_pairs, prs.size() * sizeof(DPair)) != hipSuccess ||
@@ -184,10 +185,39 @@ extern "C" ah_status ah_primers_compile(const ah_pair_spec *h_pairs, uint32_t n_
     return ah_build_primer_set(h_pairs, n_pairs, false, out);
 }
 
+extern "C" uint64_t ah_primers_table_bytes(uint32_t n_pairs) {
+    return ah_pat_bytes(n_pairs) + (uint64_t)n_pairs * sizeof(DPair);
+}
+
+extern "C" ah_status ah_primers_compile_into(const ah_pair_spec *h_pairs, uint32_t n_pairs, void *d_buf,
+                                             uint64_t buf_bytes, void *stream, ah_primer_set *out) {
+    if (!out) return AH_E_ARG;
+    if (!d_buf || buf_bytes < ah_primers_table_bytes(n_pairs)) return AH_E_WORKSPACE;
+    ah_primer_set ps = nullptr;
+    ah_status st = ah_build_primer_set(h_pairs, n_pairs, true, &ps);
+    if (st != AH_OK) return st;
+    hipStream_t s = ah_stream(stream);
+    ps->d_pats = (DPat *)d_buf;
+    ps->d_pairs = (DPair *)((char *)d_buf + ah_pat_bytes(n_pairs));
+    ps->owns_device = 0;
+    if (hipGetDevice(&ps->device) != hipSuccess ||
+        hipMemcpyAsync(ps->d_pats, ps->h_pats, 4ull * n_pairs * sizeof(DPat), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(ps->d_pairs, ps->h_pairs, (uint64_t)n_pairs * sizeof(DPair), hipMemcpyHostToDevice, s) !=
+            hipSuccess) {
+        ps->d_pats = nullptr;
+        ps->d_pairs = nullptr;
+        ah_primers_free(ps);
+        return AH_E_HIP;
+    }
+    *out = ps;
+    return AH_OK;
+}
+
 extern "C" void ah_primers_free(ah_primer_set ps) {
     if (!ps) return;
-    if (ps->d_pats) (void)hipFree(ps->d_pats);
-    if (ps->d_pairs) (void)hipFree(ps->d_pairs);
+    if (ps->owns_device && ps->d_pats) (void)hipFree(ps->d_pats);
+    if (ps->owns_device && ps->d_pairs) (void)hipFree(ps->d_pairs);
     ah_jit_free(ps->jit);
     delete[] ps->h_pats;
     delete[] ps->h_pairs;

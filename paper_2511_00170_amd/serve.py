@@ -13,21 +13,21 @@ batch of requests:
   pair, Tm, extract  over all routed hits at once, with per-slot windows and
                  per-slot Tm thresholds;
 
-then splits the amplicons by slot.  Requests join the batch formed at the
-next pass (iteration-level batching): whatever has arrived when the GPU frees
-up is admitted in arrival order while the batch's estimated device memory
-stays within the budget.  A request's result does not depend on what it was
-batched with: routing applies exactly its (sequence, pair, k) selection to
-hits that do not depend on the batch, and pairing, Tm and extraction are per
-(sequence, slot).
+then splits the amplicons by slot.  Up to ``n_slots`` batches are in flight
+at once, each with its own device buffers and stream: whenever a slot is
+free, the requests that have arrived are admitted in arrival order while the
+batch's estimated device memory stays within the budget, and that batch runs
+alongside the ones already on the GPU (its scan starts as the earlier scan's
+workgroups retire; copies and host work of one batch overlap another's
+kernels).  A request's result does not depend on what it was batched with:
+routing applies exactly its (sequence, pair, k) selection to hits that do not
+depend on the batch, and pairing, Tm and extraction are per (sequence, slot).
 
 The scheduler is separate from the GPU executor so that its policy can be
 tested without a GPU.
 """
 from __future__ import annotations
 
-import heapq
-import math
 import time
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional, Sequence
@@ -43,18 +43,33 @@ MAX_POOL = 64               # pair bitmap of the masked scan
 # --------------------------------------------------------------------------
 # Results
 # --------------------------------------------------------------------------
-@dataclass
 class RequestResult:
-    rid: int
-    amps: np.ndarray            # AMP_DTYPE, pair = index into the request's pair list
-    tm: np.ndarray
-    tm_site: np.ndarray
-    passed: np.ndarray
-    seq: bytes                  # amplicon sequences (passing amplicons only)
-    seq_off: np.ndarray
-    arrival_s: float = 0.0
-    done_s: float = 0.0
-    batch: int = -1
+    """One request's amplicons (pair = index into the request's pair list),
+    their Tm, pass flags and sequences.  ``seq`` may be given as bytes or as
+    (batch buffer, per-amplicon start offsets): the per-request byte string is
+    then cut out of the batch's host buffer when first read."""
+
+    def __init__(self, rid: int, amps: np.ndarray, tm: np.ndarray, tm_site: np.ndarray, passed: np.ndarray, seq,
+                 seq_off: np.ndarray):
+        self.rid, self.amps, self.tm, self.tm_site, self.passed = rid, amps, tm, tm_site, passed
+        self._seq = seq
+        self.seq_off = seq_off
+        self.arrival_s = 0.0
+        self.done_s = 0.0
+        self.batch = -1
+
+    @property
+    def seq(self) -> bytes:
+        if isinstance(self._seq, tuple):
+            buf, starts = self._seq
+            lens = np.diff(self.seq_off.astype(np.int64))
+            tot = int(lens.sum())
+            if tot:
+                pos = np.repeat(starts - (np.cumsum(lens) - lens), lens) + np.arange(tot, dtype=np.int64)
+                self._seq = buf[pos].tobytes()
+            else:
+                self._seq = b""
+        return self._seq
 
     @property
     def latency_s(self) -> float:
@@ -96,19 +111,26 @@ class SchedStats:
 
 
 class Scheduler:
-    """Iteration-level batching.  ``executor(batch) -> {rid: RequestResult}``
-    runs one pass; ``clock()`` gives the current time and ``sleep_until(t)``
-    waits (both replaceable for simulated time)."""
+    """Iteration-level batching with batches in flight concurrently.
 
-    def __init__(self, executor: Callable[[List[Request]], Dict[int, RequestResult]],
-                 cost: Callable[[Request], int], budget_bytes: int, max_requests: int = MAX_REQ_PER_BATCH,
-                 clock: Callable[[], float] = time.perf_counter, sleep_until: Optional[Callable[[float], None]] = None):
+    The executor either runs a batch synchronously (``executor(batch) ->
+    {rid: RequestResult}``) or, when it has ``launch/ready/collect`` and
+    ``free_slots``, asynchronously: a batch is launched whenever a slot (a
+    set of device buffers and a stream) is free and requests are waiting, so
+    a batch formed from requests that arrived while others were on the GPU
+    runs alongside them.  ``clock()`` gives the current time and
+    ``sleep_until(t)`` waits (both replaceable for simulated time)."""
+
+    def __init__(self, executor, cost: Callable[[Request], int], budget_bytes: int,
+                 max_requests: int = MAX_REQ_PER_BATCH, clock: Callable[[], float] = time.perf_counter,
+                 sleep_until: Optional[Callable[[float], None]] = None, poll_s: float = 2e-4):
         self.executor = executor
         self.cost = cost
         self.budget = budget_bytes
         self.max_requests = max_requests
         self.clock = clock
         self.sleep_until = sleep_until or (lambda t: time.sleep(max(0.0, t - self.clock())))
+        self.poll_s = poll_s
         self.stats = SchedStats()
 
     def admit(self, queue: List[Request]) -> List[Request]:
@@ -124,34 +146,61 @@ class Scheduler:
             used += c
         return batch
 
+    def _finish(self, batch, res, t0, ts, te, out):
+        self.stats.batches += 1
+        self.stats.batch_sizes.append(len(batch))
+        self.stats.busy_s += te - ts
+        for r in batch:
+            rr = res[r.rid]
+            rr.arrival_s = t0 + r.arrival_s
+            rr.done_s = te
+            rr.batch = self.stats.batches - 1
+            out[r.rid] = rr
+
     def run(self, requests: Sequence[Request], t0: Optional[float] = None) -> Dict[int, RequestResult]:
         """Serve ``requests`` (arrival_s relative to t0) to completion."""
         pending = sorted(requests, key=lambda r: (r.arrival_s, r.rid))
         t0 = self.clock() if t0 is None else t0
         queue: List[Request] = []
         out: Dict[int, RequestResult] = {}
+        inflight = []  # (ticket, batch, launch time), oldest first
+        asyn = hasattr(self.executor, "launch")
         i = 0
-        while i < len(pending) or queue:
+        while i < len(pending) or queue or inflight:
             now = self.clock() - t0
             while i < len(pending) and pending[i].arrival_s <= now:
                 queue.append(pending[i])
                 i += 1
-            if not queue:
-                self.sleep_until(t0 + pending[i].arrival_s)
+            # completed batches first (their slots free up)
+            if inflight and self.executor.ready(inflight[0][0]):
+                tk, batch, ts = inflight.pop(0)
+                res = self.executor.collect(tk)
+                self._finish(batch, res, t0, ts, self.clock(), out)
                 continue
-            batch = self.admit(queue)
-            ts = self.clock()
-            res = self.executor(batch)
-            te = self.clock()
-            self.stats.batches += 1
-            self.stats.batch_sizes.append(len(batch))
-            self.stats.busy_s += te - ts
-            for r in batch:
-                rr = res[r.rid]
-                rr.arrival_s = t0 + r.arrival_s
-                rr.done_s = te
-                rr.batch = self.stats.batches - 1
-                out[r.rid] = rr
+            if queue and (not asyn or self.executor.free_slots() > 0):
+                batch = self.admit(queue)
+                ts = self.clock()
+                if asyn:
+                    inflight.append((self.executor.launch(batch), batch, ts))
+                else:
+                    res = self.executor(batch)
+                    self._finish(batch, res, t0, ts, self.clock(), out)
+                continue
+            if inflight:
+                if queue or i >= len(pending):
+                    # no slot for the waiting requests, or nothing more will
+                    # arrive: wait for the oldest batch
+                    tk, batch, ts = inflight.pop(0)
+                    res = self.executor.collect(tk)
+                    self._finish(batch, res, t0, ts, self.clock(), out)
+                else:
+                    # a slot is free: wake up for the next arrival or a completion
+                    nxt = t0 + pending[i].arrival_s
+                    eta = self.executor.eta(inflight[0][0]) if hasattr(self.executor, "eta") else None
+                    wake = min(nxt, self.clock() + self.poll_s) if eta is None else min(nxt, eta)
+                    self.sleep_until(wake)
+                continue
+            self.sleep_until(t0 + pending[i].arrival_s)
         return out
 
 
@@ -212,28 +261,67 @@ def split_results(plan: BatchPlan, amps, tm, tm_site, passed, seq: bytes, seq_of
     out = {}
     req_of = plan.slot_req[amps["pair"].astype(np.int64)] if len(amps) else np.zeros(0, np.int64)
     spi = np.asarray(slot_pair_index, np.uint16)
+    sb = np.frombuffer(seq, np.uint8) if isinstance(seq, (bytes, bytearray)) else np.asarray(seq, np.uint8)
+    off = seq_off.astype(np.int64)
+    lens_all = off[1:] - off[:-1]
+    buf = sb.copy()                                     # the batch's bytes, shared by its requests
+    order = np.argsort(req_of, kind="stable")          # amplicons grouped by request, order kept
+    bounds = np.searchsorted(req_of[order], np.arange(len(plan.reqs) + 1))
     for r, rq in enumerate(plan.reqs):
-        idx = np.nonzero(req_of == r)[0]
+        idx = order[bounds[r]:bounds[r + 1]]
         a = amps[idx].copy()
         if len(a):
             a["pair"] = spi[a["pair"].astype(np.int64)]
-        lens = (seq_off[idx + 1] - seq_off[idx]).astype(np.int64)
+        lens = lens_all[idx]
         so = np.zeros(len(idx) + 1, np.uint64)
         so[1:] = np.cumsum(lens)
-        s = b"".join(seq[int(seq_off[i]):int(seq_off[i + 1])] for i in idx)
-        out[rq.rid] = RequestResult(rq.rid, a, tm[idx], tm_site[idx], passed[idx], s, so)
+        out[rq.rid] = RequestResult(rq.rid, a, tm[idx].copy(), tm_site[idx].copy(), passed[idx].copy(),
+                                    (buf, off[idx]), so)
     return out
 
 
 # --------------------------------------------------------------------------
 # GPU executor
 # --------------------------------------------------------------------------
+class _Slot:
+    """Device buffers, pinned staging and a stream for one batch in flight."""
+
+    def __init__(self, torch, dev, n_seqs):
+        self.torch, self.dev = torch, dev
+        self.stream = torch.cuda.Stream()
+        self.caps = dict(hits=1 << 20, routed=1 << 20, amps=1 << 16, seq=1 << 24)
+        self.bufs = {}
+        pin = dict(dtype=torch.uint8, pin_memory=True)
+        self.h_tables = torch.empty(max(n_seqs, 1) * 20 + (MAX_REQ_PER_BATCH * (2 * MAX_POOL + 1)) +
+                                    8 * MAX_REQ_PER_BATCH * MAX_POOL + 64, **pin)
+        self.h_cnt = torch.zeros(8, dtype=torch.int64, pin_memory=True)
+        self.h_out = None  # pinned landing buffer for a batch's results
+        self.event = torch.cuda.Event()
+
+    def buf(self, name, n, dtype):
+        t = self.bufs.get(name)
+        if t is None or t.numel() < n or t.dtype != dtype:
+            t = self.torch.empty(max(n, 1), dtype=dtype, device=self.dev)
+            self.bufs[name] = t
+        return t
+
+
+@dataclass
+class Ticket:
+    slot: "_Slot"
+    plan: BatchPlan
+    vps: object
+    tables: dict
+
+
 class GpuExecutor:
     """Runs batches on one GPU against a resident store and a pool primer set
-    compiled once (hipRTC-specialised scan at the pool's largest k)."""
+    compiled once (hipRTC-specialised scan at the pool's largest k).  Up to
+    ``n_slots`` batches are in flight at once, each on its own stream with its
+    own buffers, so one batch's stages and copies overlap another's scan."""
 
     def __init__(self, store, pool: Sequence[PairSpec], tm: TmSpec, ex=None, orient_mask: int = 0xF,
-                 pool_k: int = 3, jit: bool = True):
+                 pool_k: int = 3, jit: bool = True, n_slots: int = 2):
         import torch
 
         from . import ah
@@ -247,91 +335,161 @@ class GpuExecutor:
         self.ex = ex
         self.orient_mask = orient_mask
         self.dev = store.blocks.device
-        self.stream = torch.cuda.Stream()
-        self.caps = dict(hits=1 << 20, routed=1 << 20, amps=1 << 16, seq=1 << 24)
-        self._bufs = {}
+        self.slots = [_Slot(torch, self.dev, store.n_seqs) for _ in range(n_slots)]
+        self.free = list(range(n_slots))[::-1]
         self.last_counts = None
+        self.host_s = dict(launch=0.0, wait=0.0, collect=0.0, batches=0)  # host time by phase
 
-    def _buf(self, name, n, dtype):
-        t = self._bufs.get(name)
-        if t is None or t.numel() < n or t.dtype != dtype:
-            t = self.torch.empty(max(n, 1), dtype=dtype, device=self.dev)
-            self._bufs[name] = t
-        return t
+    # -- compatibility: the first slot's capacities --------------------------
+    @property
+    def caps(self):
+        return self.slots[0].caps
 
-    def _h2d(self, name, arr: np.ndarray, dtype):
-        host = self.torch.from_numpy(np.ascontiguousarray(arr))
-        t = self._buf(name, host.numel(), dtype)
-        t[:host.numel()].copy_(host.view(dtype) if host.dtype != dtype else host, non_blocking=False)
-        return t
+    @caps.setter
+    def caps(self, c):
+        for sl in self.slots:
+            sl.caps = dict(c)
+
+    def free_slots(self) -> int:
+        return len(self.free)
 
     def __call__(self, batch: List[Request]) -> Dict[int, RequestResult]:
-        plan = plan_batch(batch, self.pool, self.store.n_seqs)
-        return self.execute(plan)
+        return self.collect(self.launch(batch))
 
     def execute(self, plan: BatchPlan) -> Dict[int, RequestResult]:
-        ah, torch = self.ah, self.torch
-        st = self.store
-        T = torch
+        return self.collect(self._launch_plan(plan))
+
+    def launch(self, batch: List[Request]) -> Ticket:
+        return self._launch_plan(plan_batch(batch, self.pool, self.store.n_seqs))
+
+    def ready(self, tk: Ticket) -> bool:
+        return tk.slot.event.query()
+
+    def _launch_plan(self, plan: BatchPlan) -> Ticket:
+        t_in = time.perf_counter()
+        tk = self._launch_plan_timed(plan)
+        self.host_s["launch"] += time.perf_counter() - t_in
+        return tk
+
+    def _launch_plan_timed(self, plan: BatchPlan) -> Ticket:
+        ah, T = self.ah, self.torch
+        assert self.free, "no free slot"
+        sl = self.slots[self.free.pop()]
+        # the batch's own primer set (pair / Tm / extract), its tables copied
+        # into the slot's buffer on the slot's stream: no allocation, no sync
+        tbl = sl.buf("ptable", ah.table_bytes(len(plan.slots)), T.uint8)
+        vps = ah.PrimerSet(plan.slots, table=tbl, stream=sl.stream)
+        # stage the routing tables in pinned memory and copy them asynchronously
+        arrs = [("list", plan.seq_list.view(np.int32), T.int32), ("pmask", plan.pair_mask.view(np.int64), T.int64),
+                ("seq_req", plan.seq_req.view(np.int64), T.int64),
+                ("vpair", plan.vpair.reshape(-1).view(np.int16), T.int16),
+                ("kmax", plan.kmax.view(np.uint8), T.uint8), ("thr", plan.slot_thr, T.float64)]
+        host = sl.h_tables.numpy()
+        tables, at = {}, 0
+        with T.cuda.stream(sl.stream):
+            for name, arr, dt in arrs:
+                raw = np.ascontiguousarray(arr).view(np.uint8).reshape(-1)
+                at = (at + 7) & ~7
+                host[at:at + raw.size] = raw
+                d = sl.buf(name, max(arr.size, 1), dt)
+                if raw.size:
+                    d.view(T.uint8)[:raw.size].copy_(sl.h_tables[at:at + raw.size], non_blocking=True)
+                tables[name] = d
+                at += raw.size
+        tk = Ticket(sl, plan, vps, tables)
+        self._enqueue(tk)
+        return tk
+
+    def _enqueue(self, tk: Ticket):
+        ah, T = self.ah, self.torch
+        st, sl, plan, vps, tb = self.store, tk.slot, tk.plan, tk.vps, tk.tables
         n_list = len(plan.seq_list)
-        vps = ah.PrimerSet(plan.slots)  # pair / Tm / extract of this batch (host compile only)
-        with torch.cuda.stream(self.stream):
-            s = self.stream
-            lst = self._h2d("list", plan.seq_list.view(np.int32), T.int32)
-            pmask = self._h2d("pmask", plan.pair_mask.view(np.int64), T.int64)
-            seq_req = self._h2d("seq_req", plan.seq_req.view(np.int64), T.int64)
-            vpair = self._h2d("vpair", plan.vpair.reshape(-1).view(np.int16), T.int16)
-            kmax = self._h2d("kmax", plan.kmax.view(np.uint8), T.uint8)
-            thr = self._h2d("thr", plan.slot_thr, T.float64)
-            params = ah.tm_params(self.tm)
-            params.filter = 1
-            params.d_pair_threshold = thr.data_ptr()
-            opts = ah.extract_opts(self.ex) if self.ex is not None else ah.extract_opts(_NoExtract())
-            cnt = self._buf("cnt", 8, T.int64)
-            while True:
-                c = self.caps
-                hits = self._buf("hits", 3 * c["hits"], T.int32)
-                rh = self._buf("routed", 3 * c["routed"], T.int32)
-                amps = self._buf("amps", 4 * c["amps"], T.int32)
-                tmv = self._buf("tm", c["amps"], T.float64)
-                tms = self._buf("tm_site", 2 * c["amps"], T.float64)
-                pas = self._buf("pass", c["amps"], T.uint8)
-                seqb = self._buf("seq", c["seq"], T.uint8)
-                soff = self._buf("seq_off", c["amps"] + 1, T.int64)
-                fb = self._buf("fb", c["amps"] * max(opts.fb_len, 1), T.uint8)
-                rb = self._buf("rb", c["amps"] * max(opts.rb_len, 1), T.uint8)
-                bcl = self._buf("bcl", 2 * c["amps"], T.uint8)
-                fpr = self._buf("fpr", 32 * c["amps"], T.uint8)
-                rpr = self._buf("rpr", 32 * c["amps"], T.uint8)
-                wsz = max(ah.ws_scan(st, n_list), ah.ws_pair(st, vps, c["routed"]), ah.ws_extract(c["amps"]))
-                ws = self._buf("ws", wsz // 8 + 1, T.int64)
-                ah.scan_primers_masked(st, self.pool_ps, lst[:n_list], pmask, hits, c["hits"], cnt[0:1], ws, s)
-                ah.route_hits(hits, cnt[0:1], c["hits"], st.n_seqs, seq_req, vpair, kmax, len(plan.reqs),
-                              len(self.pool), rh, c["routed"], cnt[1:2], s)
-                ah.pair_amplicons(st, vps, rh, cnt[1:2], c["routed"], self.orient_mask, amps, c["amps"], cnt[2:3],
-                                  ws, s)
-                ah.tm_nn(st, vps, amps, cnt[2:3], c["amps"], params, tmv, tms, pas, s)
-                ah.extract(st, vps, amps, cnt[2:3], c["amps"], pas, opts, seqb, c["seq"], soff, fb, rb, bcl, fpr, rpr,
-                           cnt[3:4], ws, s)
-                v = cnt[:4].cpu().numpy()  # synchronises the stream
-                nh, nr, na, nb = (int(x) for x in v)
-                if nh <= c["hits"] and nr <= c["routed"] and na <= c["amps"] and nb <= c["seq"]:
-                    break
-                self.caps = dict(hits=max(c["hits"], int(nh * 1.25) + 1024),
-                                 routed=max(c["routed"], int(nr * 1.25) + 1024),
-                                 amps=max(c["amps"], int(na * 1.25) + 1024), seq=max(c["seq"], int(nb * 1.25) + 4096))
-            self.last_counts = (nh, nr, na, nb)
-            a_host = amps[:4 * na].cpu().numpy().view(np.uint8).reshape(-1).view(ah.AMP_DTYPE)
-            tm_h = tmv[:na].cpu().numpy()
-            tms_h = tms[:2 * na].cpu().numpy().reshape(-1, 2)
-            pas_h = pas[:na].cpu().numpy()
-            seq_h = seqb[:nb].cpu().numpy().tobytes()
-            soff_h = soff[:na + 1].cpu().numpy().astype(np.uint64)
+        params = ah.tm_params(self.tm)
+        params.filter = 1
+        params.d_pair_threshold = tb["thr"].data_ptr()
+        opts = ah.extract_opts(self.ex) if self.ex is not None else ah.extract_opts(_NoExtract())
+        c = sl.caps
+        with T.cuda.stream(sl.stream):
+            s = sl.stream
+            cnt = sl.buf("cnt", 8, T.int64)
+            hits = sl.buf("hits", 3 * c["hits"], T.int32)
+            rh = sl.buf("routed", 3 * c["routed"], T.int32)
+            amps = sl.buf("amps", 4 * c["amps"], T.int32)
+            tmv = sl.buf("tm", c["amps"], T.float64)
+            tms = sl.buf("tm_site", 2 * c["amps"], T.float64)
+            pas = sl.buf("pass", c["amps"], T.uint8)
+            seqb = sl.buf("seq", c["seq"], T.uint8)
+            soff = sl.buf("seq_off", c["amps"] + 1, T.int64)
+            fb = sl.buf("fb", c["amps"] * max(opts.fb_len, 1), T.uint8)
+            rb = sl.buf("rb", c["amps"] * max(opts.rb_len, 1), T.uint8)
+            bcl = sl.buf("bcl", 2 * c["amps"], T.uint8)
+            fpr = sl.buf("fpr", 32 * c["amps"], T.uint8)
+            rpr = sl.buf("rpr", 32 * c["amps"], T.uint8)
+            wsz = max(ah.ws_scan(st, n_list), ah.ws_pair(st, vps, c["routed"]), ah.ws_extract(c["amps"]))
+            ws = sl.buf("ws", wsz // 8 + 1, T.int64)
+            ah.scan_primers_masked(st, self.pool_ps, tb["list"][:n_list], tb["pmask"], hits, c["hits"], cnt[0:1],
+                                   ws, s)
+            ah.route_hits(hits, cnt[0:1], c["hits"], st.n_seqs, tb["seq_req"], tb["vpair"], tb["kmax"],
+                          len(plan.reqs), len(self.pool), rh, c["routed"], cnt[1:2], s)
+            ah.pair_amplicons(st, vps, rh, cnt[1:2], c["routed"], self.orient_mask, amps, c["amps"], cnt[2:3], ws, s)
+            ah.tm_nn(st, vps, amps, cnt[2:3], c["amps"], params, tmv, tms, pas, s)
+            ah.extract(st, vps, amps, cnt[2:3], c["amps"], pas, opts, seqb, c["seq"], soff, fb, rb, bcl, fpr, rpr,
+                       cnt[3:4], ws, s)
+            sl.h_cnt.copy_(cnt, non_blocking=True)
+            sl.event.record(s)
+
+    def collect(self, tk: Ticket) -> Dict[int, RequestResult]:
+        ah = self.ah
+        sl = tk.slot
+        t_in = time.perf_counter()
+        while True:
+            sl.event.synchronize()
+            nh, nr, na, nb = (int(x) for x in sl.h_cnt.numpy()[:4])
+            c = sl.caps
+            if nh <= c["hits"] and nr <= c["routed"] and na <= c["amps"] and nb <= c["seq"]:
+                break
+            # a buffer overflowed: grow and run the batch again (exact)
+            sl.caps = dict(hits=max(c["hits"], int(nh * 1.25) + 1024), routed=max(c["routed"], int(nr * 1.25) + 1024),
+                           amps=max(c["amps"], int(na * 1.25) + 1024), seq=max(c["seq"], int(nb * 1.25) + 4096))
+            self._enqueue(tk)
+        self.last_counts = (nh, nr, na, nb)
+        t_got = time.perf_counter()
+        self.host_s["wait"] += t_got - t_in
+        # results to pinned host buffers (asynchronous copies on the slot's stream)
+        T = self.torch
+        b = sl.bufs
+        parts = [("amps", b["amps"], 16 * na), ("tm", b["tm"], 8 * na), ("tm_site", b["tm_site"], 16 * na),
+                 ("pass", b["pass"], na), ("seq_off", b["seq_off"], 8 * (na + 1)), ("seq", b["seq"], nb)]
+        need = sum((n + 255) & ~255 for _, _, n in parts)
+        if sl.h_out is None or sl.h_out.numel() < need:
+            sl.h_out = T.empty(int(need * 1.25) + 4096, dtype=T.uint8, pin_memory=True)
+        host, at, views = sl.h_out.numpy(), 0, {}
+        with T.cuda.stream(sl.stream):
+            for name, d, n in parts:
+                if n:
+                    sl.h_out[at:at + n].copy_(d.view(T.uint8)[:n], non_blocking=True)
+                views[name] = host[at:at + n]
+                at += (n + 255) & ~255
+            sl.event.record(sl.stream)
+        sl.event.synchronize()
+        t_d2h = time.perf_counter()
+        self.host_s["d2h"] = self.host_s.get("d2h", 0.0) + t_d2h - t_got
+        self.host_s["bytes"] = self.host_s.get("bytes", 0) + need
+        a_host = views["amps"].view(ah.AMP_DTYPE)
+        tm_h = views["tm"].view(np.float64)
+        tms_h = views["tm_site"].view(np.float64).reshape(-1, 2)
+        pas_h = views["pass"]
+        soff_h = views["seq_off"].view(np.int64).astype(np.uint64)
         slot_pair_index = []
-        for r, rq in enumerate(plan.reqs):
+        for rq in tk.plan.reqs:
             slot_pair_index += list(range(len(rq.pairs)))
-        vps.close()
-        return split_results(plan, a_host, tm_h, tms_h, pas_h, seq_h, soff_h, slot_pair_index)
+        # split copies everything out of the pinned buffer, which the slot reuses
+        res = split_results(tk.plan, a_host, tm_h, tms_h, pas_h, views["seq"], soff_h, slot_pair_index)
+        tk.vps.close()
+        self.free.append(self.slots.index(sl))
+        self.host_s["collect"] += time.perf_counter() - t_got
+        self.host_s["batches"] += 1
+        return res
 
     def alone_reference(self, req: Request) -> RequestResult:
         """The request through the plain single-request path (its own primer
@@ -361,8 +519,9 @@ class ServeEngine:
     """Scheduler + GPU executor over one resident store."""
 
     def __init__(self, store, pool, tm: TmSpec, ex=None, orient_mask: int = 0xF, pool_k: int = 3,
-                 budget_bytes: int = 2 << 30, max_requests: int = MAX_REQ_PER_BATCH, jit: bool = True):
-        self.exe = GpuExecutor(store, pool, tm, ex, orient_mask, pool_k, jit)
+                 budget_bytes: int = 2 << 30, max_requests: int = MAX_REQ_PER_BATCH, jit: bool = True,
+                 n_slots: int = 2):
+        self.exe = GpuExecutor(store, pool, tm, ex, orient_mask, pool_k, jit, n_slots)
         lens = store.lengths.astype(np.int64)
         self.sched = Scheduler(self.exe, lambda r: request_bytes(r, self.exe.pool, lens, pool_k), budget_bytes,
                                max_requests)

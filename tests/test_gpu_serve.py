@@ -163,3 +163,19 @@ def test_engine_serves_poisson_stream(env):
     # every result equals the request served alone
     for r in reqs[:6]:
         assert serve.results_equal(out[r.rid], eng.exe([r])[r.rid])
+
+
+def test_two_batches_in_flight_match_alone(env):
+    ah, serve, wl, st = env
+    reqs = _reqs(wl, 8, seed=21)
+    _say("two in flight")
+    exe = serve.GpuExecutor(st, wl.pairs, wl.tm, ExtractSpec(), wl.orient_mask, pool_k=3, jit=True, n_slots=2)
+    t1 = exe.launch(reqs[:5])
+    t2 = exe.launch(reqs[5:])
+    assert exe.free_slots() == 0
+    r2 = exe.collect(t2)      # collected out of order
+    r1 = exe.collect(t1)
+    assert exe.free_slots() == 2
+    both = {**r1, **r2}
+    for r in reqs:
+        assert serve.results_equal(both[r.rid], exe.alone_reference(r)), r.rid

@@ -112,3 +112,70 @@ def test_request_cost_grows_with_subset_and_pairs():
     small = Request(0, 0.0, [0], np.arange(5, dtype=np.uint32), 0, 50.0)
     big = Request(1, 0.0, [0, 1, 2], np.arange(50, dtype=np.uint32), 0, 50.0)
     assert serve.request_bytes(small, wl.pairs, lens, 3) < serve.request_bytes(big, wl.pairs, lens, 3)
+
+
+class FakeAsyncExecutor:
+    """A GPU that runs launched batches one after another (FIFO), each taking
+    fixed_s + per_req_s x requests, with n_slots batches in flight at most."""
+
+    def __init__(self, clock, n_slots=2, per_req_s=0.01, fixed_s=0.02):
+        self.clock, self.n_slots, self.per, self.fixed = clock, n_slots, per_req_s, fixed_s
+        self.busy_until = 0.0
+        self.inflight = 0
+        self.log = []
+
+    def free_slots(self):
+        return self.n_slots - self.inflight
+
+    def launch(self, batch):
+        assert self.inflight < self.n_slots
+        self.inflight += 1
+        start = max(self.clock.t, self.busy_until)
+        self.busy_until = start + self.fixed + self.per * len(batch)
+        self.log.append(([r.rid for r in batch], self.clock.t, start, self.busy_until))
+        return (batch, self.busy_until)
+
+    def ready(self, tk):
+        return self.clock.t >= tk[1]
+
+    def eta(self, tk):
+        return tk[1]
+
+    def collect(self, tk):
+        batch, done = tk
+        self.clock.t = max(self.clock.t, done)
+        self.inflight -= 1
+        return {r.rid: serve.RequestResult(r.rid, np.zeros(0), np.zeros(0), np.zeros((0, 2)), np.zeros(0, np.uint8),
+                                           b"", np.zeros(1, np.uint64)) for r in batch}
+
+
+def test_async_batches_overlap_and_new_arrivals_launch_while_others_run():
+    clock = SimClock()
+    exe = FakeAsyncExecutor(clock, n_slots=2, per_req_s=0.0, fixed_s=0.1)
+    sch = serve.Scheduler(exe, cost=lambda r: 1, budget_bytes=100, clock=clock, sleep_until=clock.sleep_until)
+    # r0 at 0 starts batch A; r1 arrives during A and is launched at once in the
+    # second slot (it queues on the device behind A); r2 and r3 arrive while
+    # both slots are busy and are launched together when A's slot frees up
+    out = sch.run(_reqs([0.0, 0.03, 0.05, 0.06]), t0=0.0)
+    launches = [(ids, round(t, 3)) for ids, t, _, _ in exe.log]
+    assert launches == [([0], 0.0), ([1], 0.03), ([2, 3], 0.1)]
+    assert out[0].done_s == pytest.approx(0.1)
+    assert out[1].done_s == pytest.approx(0.2)
+    assert out[2].done_s == pytest.approx(0.3) and out[3].done_s == pytest.approx(0.3)
+    assert sorted(out) == [0, 1, 2, 3]
+
+
+def test_async_scheduler_serves_everything_once_under_load():
+    clock = SimClock()
+    exe = FakeAsyncExecutor(clock, n_slots=3, per_req_s=0.002, fixed_s=0.01)
+    sch = serve.Scheduler(exe, cost=lambda r: 1, budget_bytes=8, clock=clock, sleep_until=clock.sleep_until)
+    rng = np.random.default_rng(0)
+    reqs = _reqs(np.cumsum(rng.exponential(0.004, 300)))
+    out = sch.run(reqs, t0=0.0)
+    assert sorted(out) == list(range(300))
+    flat = [rid for ids, _, _, _ in exe.log for rid in ids]
+    assert flat == list(range(300))                       # arrival order, each once
+    assert all(len(ids) <= 8 for ids, _, _, _ in exe.log)  # budget
+    assert exe.inflight == 0
+    for r in reqs:
+        assert out[r.rid].done_s >= r.arrival_s
