@@ -38,7 +38,8 @@ struct GenericFilter {
     const DPat *gPat;
     uint32_t n_lds;
     __device__ uint32_t groups(const ScanArgs &a) const { return a.n_groups; }
-    __device__ __forceinline__ void filter(uint32_t g, const uint32_t (&Sh)[AH_WMAX][2],
+    static constexpr bool kUsesBase = false;
+    __device__ __forceinline__ void filter(uint32_t g, const AhBase &, const uint32_t (&Sh)[AH_WMAX][2],
                                            const uint32_t (&Sl)[AH_WMAX][2], uint32_t v0, uint32_t v1,
                                            uint32_t (&C)[8]) const {
         uint32_t fc[4][2], W = 0;
@@ -131,14 +132,108 @@ struct AhJit {
     int device = -1;
 };
 
-// Kernel source specialised to a primer set: the clamp codes of every
-// oriented pattern become template constants of the set tests.
+// ---------------------------------------------------------------- filter plan
+// The clamp positions alone let through about prod(|set|/4) of all windows;
+// with a small clamp and many patterns, verifying those candidates dominates.
+// A hit has at most k mismatches outside the clamp, so of k+1 disjoint
+// groups of non-clamp positions at least one matches exactly (pigeonhole):
+// "clamp exact AND some group exact" is still a necessary condition.  Groups
+// take the non-clamp positions nearest the clamp (same offsets for the two
+// patterns of a strand, so their shifted planes are shared), round-robin.
+// The group size s (0 = clamp only) minimises an estimate of vector
+// instructions per 4096-base tile: tests and shifts against candidates
+// verified (about 2.25 instructions each, measured).
+struct FiltPos {
+    int d;           // offset from the clamp site
+    unsigned code;   // IUPAC set (bit b = base b)
+};
+struct FiltPlan {
+    std::vector<FiltPos> groups[AH_MAXL];
+    int n_groups = 0;
+};
+
+static unsigned pat_code(const DPat &P, int j) {
+    unsigned m = 0;
+    for (int b = 0; b < 4; b++)
+        if ((P.P[b] >> j) & 1u) m |= 1u << b;
+    return m;
+}
+
+static double set_frac(unsigned m) { return __builtin_popcount(m) / 4.0; }
+
+static FiltPlan plan_filter(const DPat &P) {
+    FiltPlan best;
+    const int L = (int)(P.meta & 0xFFu), k = (int)((P.meta >> 8) & 0xFFu), W = (int)((P.meta >> 16) & 0xFFu);
+    const int shift = (int)(P.meta >> 24);
+    const bool minus = ((P.pk >> 16) & 2u) != 0;
+    if (k + 1 > AH_MAXL) return best;
+    double p_clamp = 1.0;
+    for (int i = 0; i < W; i++) p_clamp *= set_frac(P.fcode[i]);
+    // non-clamp positions (N codes excluded: they match everything), nearest
+    // to the clamp first
+    std::vector<FiltPos> near;
+    if (minus) {
+        for (int j = 0; j < L; j++)
+            if (!((P.clampmask >> j) & 1u) && pat_code(P, j) != 15u) near.push_back({j - shift, pat_code(P, j)});
+    } else {
+        for (int j = L - 1; j >= 0; j--)
+            if (!((P.clampmask >> j) & 1u) && pat_code(P, j) != 15u) near.push_back({j - shift, pat_code(P, j)});
+    }
+    const double kVerify = 2.25, kTile = 4096.0;
+    double best_cost = 2.0 * W + kTile * p_clamp * kVerify + 6.0;
+    for (int sz = 1; sz <= 4; sz++) {
+        const int need = sz * (k + 1);
+        if (need > (int)near.size()) break;
+        FiltPlan plan;
+        plan.n_groups = k + 1;
+        bool ok = true;
+        double p_any = 0.0;
+        for (int g = 0; g <= k; g++) {
+            double pg = 1.0;
+            for (int t = 0; t < sz; t++) {
+                const FiltPos &fp = near[g + t * (k + 1)];
+                if (fp.d <= -32 || fp.d >= 32) ok = false;
+                plan.groups[g].push_back(fp);
+                pg *= set_frac(fp.code);
+            }
+            p_any += pg;
+        }
+        if (!ok) break;
+        if (p_any > 1.0) p_any = 1.0;
+        // tests: 2 words per position; shifts: 4 funnel shifts per position,
+        // shared by the two patterns of a strand; one OR per group and word
+        const double cost = 2.0 * W + 2.0 * (k + 1) + 4.0 * need + kTile * p_clamp * p_any * kVerify + 6.0;
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = plan;
+        }
+    }
+    return best;
+}
+
+static std::string set_test_chain(std::string acc, const std::vector<FiltPos> &pos, int word) {
+    for (const FiltPos &fp : pos)
+        acc = "ah_and_at<" + std::to_string(fp.code) + "u, " + std::to_string(fp.d) + ", " + std::to_string(word) +
+              ">(" + acc + ", B)";
+    return acc;
+}
+
+// Kernel source specialised to a primer set: the codes of every oriented
+// pattern's filter positions become template constants of the set tests.
 static std::string jit_source(const ah_primer_set_ *ps) {
     std::string s;
+    std::vector<FiltPlan> plans(ps->n_pats);
+    bool any_groups = false;
+    for (uint32_t X = 0; X < ps->n_pats; X++) {
+        plans[X] = plan_filter(ps->h_pats[X]);
+        any_groups = any_groups || plans[X].n_groups > 0;
+    }
     s += "#include \"scan_core.h\"\n";
+    s += std::string("#define AH_JIT_USES_BASE ") + (any_groups ? "true" : "false") + "\n";
     s += "struct JitFilter {\n";
+    s += "  static constexpr bool kUsesBase = AH_JIT_USES_BASE;\n";
     s += "  __device__ uint32_t groups(const ScanArgs &) const { return " + std::to_string(ps->n_pairs) + "u; }\n";
-    s += "  __device__ __forceinline__ void filter(uint32_t g, const uint32_t (&Sh)[AH_WMAX][2], "
+    s += "  __device__ __forceinline__ void filter(uint32_t g, const AhBase &B, const uint32_t (&Sh)[AH_WMAX][2], "
          "const uint32_t (&Sl)[AH_WMAX][2], uint32_t v0, uint32_t v1, uint32_t (&C)[8]) const {\n";
     s += "    switch (g) {\n";
     for (uint32_t g = 0; g < ps->n_pairs; g++) {
@@ -153,6 +248,18 @@ static std::string jit_source(const ah_primer_set_ *ps) {
                 const std::string I = std::to_string(i), M = std::to_string(m);
                 c0 = "ah_and_set<" + M + "u>(" + c0 + ", Sh[" + I + "][0], Sl[" + I + "][0])";
                 c1 = "ah_and_set<" + M + "u>(" + c1 + ", Sh[" + I + "][1], Sl[" + I + "][1])";
+            }
+            const FiltPlan &plan = plans[4 * g + x];
+            if (plan.n_groups) {
+                std::string any0, any1;
+                for (int q = 0; q < plan.n_groups; q++) {
+                    const std::string t0 = set_test_chain("0xFFFFFFFFu", plan.groups[q], 0);
+                    const std::string t1 = set_test_chain("0xFFFFFFFFu", plan.groups[q], 1);
+                    any0 += (q ? " | " : "") + t0;
+                    any1 += (q ? " | " : "") + t1;
+                }
+                c0 = "(" + c0 + ") & (" + any0 + ")";
+                c1 = "(" + c1 + ") & (" + any1 + ")";
             }
             s += "      C[" + std::to_string(2 * x) + "] = " + c0 + ";\n";
             s += "      C[" + std::to_string(2 * x + 1) + "] = " + c1 + ";\n";
@@ -185,6 +292,13 @@ static int device_cus(int dev) {
 // Compile the specialised kernel for `arch` (e.g. "gfx950"); code object in *code.
 static ah_status jit_compile(const ah_primer_set_ *ps, const std::string &arch, std::vector<char> *code) {
     const std::string src = jit_source(ps);
+    // AH_JIT_DUMP=<path>: also write the generated source there (inspection)
+    if (const char *dump = getenv("AH_JIT_DUMP")) {
+        if (FILE *f = fopen(dump, "w")) {
+            fwrite(src.data(), 1, src.size(), f);
+            fclose(f);
+        }
+    }
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.c_str(), "ah_scan_jit.hip", AH_JIT_NHEADERS, kJitHeaderText,
                             kJitHeaderNames) != HIPRTC_SUCCESS)

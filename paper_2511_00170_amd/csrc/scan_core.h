@@ -52,6 +52,30 @@ __device__ __forceinline__ uint32_t ah_and_set(uint32_t acc, uint32_t h, uint32_
     return acc & ((h & high) | (~h & low));
 }
 
+// The lane's 64 positions of both planes with their neighbours: p = the 32
+// positions before them (previous lane, or the block before the tile), x0/x1
+// = their two words, n = the 32 positions after them.
+struct AhBase {
+    uint32_t ph, h0, h1, nh;
+    uint32_t pl, l0, l1, nl;
+};
+
+// Word Wd (0: positions 0-31, 1: 32-63) of a plane shifted by D positions
+// (bit q = base q + D), -31 <= D <= 31: one funnel shift, none for D = 0.
+template <int D, int Wd>
+__device__ __forceinline__ uint32_t ah_shw(uint32_t p, uint32_t x0, uint32_t x1, uint32_t n) {
+    static_assert(D > -32 && D < 32, "shift out of range");
+    if constexpr (D == 0) return Wd == 0 ? x0 : x1;
+    else if constexpr (D > 0) return Wd == 0 ? ah_funnel(x1, x0, D) : ah_funnel(n, x1, D);
+    else return Wd == 0 ? ah_funnel(x0, p, 32 + D) : ah_funnel(x1, x0, 32 + D);
+}
+
+// acc AND (bit q: base q + D is in IUPAC set M), from the base words
+template <uint32_t M, int D, int Wd>
+__device__ __forceinline__ uint32_t ah_and_at(uint32_t acc, const AhBase &b) {
+    return ah_and_set<M>(acc, ah_shw<D, Wd>(b.ph, b.h0, b.h1, b.nh), ah_shw<D, Wd>(b.pl, b.l0, b.l1, b.nl));
+}
+
 // Per-tile context kept for deferred verification.
 struct TileCtx {
     uint64_t gbase;  // store position (block index * 64) of the tile's first base
@@ -288,6 +312,18 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
         nh0 = L.hal.x;
         nl0 = L.hal.y;
     }
+    AhBase B = {};
+    if (F::kUsesBase) {
+        // the previous 32 positions (lane 0: the block before the tile; at a
+        // sequence start they are another sequence's or padding, which only
+        // windows that verification rejects can see)
+        uint32_t ph1 = __shfl_up(h1, 1, 64), pl1 = __shfl_up(l1, 1, 64);
+        if (lane == 0) {
+            ph1 = L.hal.z;
+            pl1 = L.hal.w;
+        }
+        B = AhBase{ph1, h0, h1, nh0, pl1, l0, l1, nl0};
+    }
     uint32_t *Wh = sW[ci][0], *Wl = sW[ci][1];
     Wh[1 + 2 * lane] = h0;
     Wh[2 + 2 * lane] = h1;
@@ -322,8 +358,11 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
 #pragma unroll
         for (int i = 0; i < AH_WMAX; i++)
             asm volatile("" : "+v"(Sh[i][0]), "+v"(Sh[i][1]), "+v"(Sl[i][0]), "+v"(Sl[i][1]));
+        if (F::kUsesBase)
+            asm volatile("" : "+v"(B.ph), "+v"(B.h0), "+v"(B.h1), "+v"(B.nh), "+v"(B.pl), "+v"(B.l0), "+v"(B.l1),
+                         "+v"(B.nl));
         uint32_t C[8];
-        f.filter(g, Sh, Sl, v, v, C);
+        f.filter(g, B, Sh, Sl, v, v, C);
         const uint32_t any = (C[0] | C[1] | C[2] | C[3]) | (C[4] | C[5] | C[6] | C[7]);
         if (__ballot(any != 0) == 0) continue;
         // room for this group's candidates (at most 4 x 64 entries); a
@@ -347,8 +386,11 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
 
 // The kernel body.  Filter F provides
 //   f.groups(a)                         number of pattern groups (primer pairs),
-//   f.filter(g, Sh, Sl, v0, v1, C)      candidate words of group g (C[2x], C[2x+1]:
-//                                       clamp sites 0-31 / 32-63 of pattern x).
+//   f.filter(g, B, Sh, Sl, v0, v1, C)   candidate words of group g (C[2x], C[2x+1]:
+//                                       clamp sites 0-31 / 32-63 of pattern x); a
+//                                       candidate must pass a necessary condition
+//                                       of a hit; verification decides.
+//   F::kUsesBase                        whether filter reads the base words B.
 // n_lds: pattern records staged in sPat; kLdsOnly: n_lds covers every record.
 template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds,
