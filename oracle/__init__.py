@@ -61,6 +61,8 @@ def lib():
                               C.c_uint32, C.c_uint32, C.c_void_p, C.c_uint64]
         L.or_nn_thermo.restype = C.c_int
         L.or_nn_thermo.argtypes = [C.c_char_p, C.c_char_p, P(C.c_double), P(C.c_double)]
+        L.or_salt_correction.restype = C.c_int
+        L.or_salt_correction.argtypes = [C.c_void_p, C.c_char_p, P(C.c_double), P(C.c_int)]
         L.or_tm_duplex.restype = C.c_double
         L.or_tm_duplex.argtypes = [C.c_char_p, C.c_char_p, C.c_void_p, P(C.c_int)]
         L.or_tm_amps.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
@@ -165,6 +167,16 @@ def nn_thermo(seq: str, cseq: str):
     if st == 2:
         raise ValueError("bad duplex")
     return None if st == 1 else (dh.value, ds.value)
+
+
+def salt_correction(tm, seq: str):
+    """(correction, kind): kind 1 = added to Tm (C), 5 = added to dS,
+    6 = added to 1/Tm (1/K), 0 = none.  ValueError for zero concentrations."""
+    cond = _cond(tm)
+    corr, kind = C.c_double(0), C.c_int(0)
+    if lib().or_salt_correction(C.byref(cond), seq.encode(), C.byref(corr), C.byref(kind)):
+        raise ValueError("salt correction %d undefined for these concentrations" % tm.saltcorr)
+    return corr.value, kind.value
 
 
 def tm_duplex(seq: str, cseq: str, tm) -> float:

@@ -21,10 +21,14 @@
  * Where the paper is silent the readings are named in comments (R-...).
  *
  * Parity unpinned: the numeric values of the internal-mismatch and
- * terminal-mismatch nearest-neighbour stacks.  They are transcribed from the
- * primary papers cited at the tables, but no published Tm of a mismatched
- * duplex is available to pin them; the Watson-Crick stacks, the salt and
- * concentration terms and the documented Biopython value are pinned.
+ * terminal-mismatch nearest-neighbour stacks, and the coefficients of salt
+ * corrections 3, 4, 6 and 7.  They are transcribed from the primary papers
+ * cited at them, but no published Tm of a mismatched duplex, and no
+ * documented value for those corrections, is available to pin them (their
+ * structure is checked: unit conversion, limits, monotonicity, the 2008
+ * model's fall-back to the 2004 one).  The Watson-Crick stacks, corrections
+ * 1, 2 and 5, the sodium equivalent and the strand concentration term are
+ * pinned to documented values.
  *
  * Records exchanged with the Python wrapper (oracle/__init__.py):
  *   hit: 4 x u32 = {seq, pos, pair, kind | mm << 8}
@@ -521,6 +525,79 @@ static double mono_equiv_M(const or_tm_cond *c)
 }
 
 /*
+ * Salt correction of the nearest-neighbour Tm, the seven methods the Tm_NN
+ * model offers (Implementations, "AHv2" paragraph: every salt correction
+ * method), each written from its paper.  `seq` is the primer strand (length
+ * N, G+C fraction fgc).  mon = Na + K + Tris/2 plus, for methods 1-6, the
+ * von Ahsen (2001) Mg2+ equivalent 120 sqrt(Mg - dNTPs) when Mg > dNTPs; M.
+ *   1 Schildkraut & Lifson 1965   dTm = 16.6 log10(mon)
+ *   2 Wetmur 1991                 dTm = 16.6 log10(mon / (1 + 0.7 mon))
+ *   3 SantaLucia et al. 1996      dTm = 12.5 log10(mon)
+ *   4 SantaLucia 1998             dTm = 11.7 log10(mon)
+ *   5 SantaLucia 1998             dS += 0.368 (N - 1) ln(mon)
+ *   6 Owczarzy et al. 2004        d(1/Tm) = (4.29 fgc - 3.95) 1e-5 ln(mon) + 9.40e-6 ln(mon)^2
+ *   7 Owczarzy et al. 2008        Mg2+ model: free Mg2+ after dNTP binding
+ *                                 (Ka = 3e4 /M); ratio R = sqrt(Mg)/mon; R < 0.22:
+ *                                 method 6; otherwise d(1/Tm) = 1e-5 [a + b ln Mg
+ *                                 + fgc (c + d ln Mg) + (e + f ln Mg + g ln^2 Mg)
+ *                                 / (2 (N - 1))], with a, d, g depending on mon
+ *                                 when R < 6.
+ * *kind: 1 add to Tm (C), 5 add to dS, 6 add to 1/Tm (1/K).  Returns 0, or 2
+ * when a logarithm of a zero concentration would be needed.
+ */
+int or_salt_correction(const or_tm_cond *c, const char *seq, double *corr, int *kind)
+{
+    int N = (int)strlen(seq), gc = 0;
+    for (int j = 0; j < N; j++) gc += (seq[j] == 'G' || seq[j] == 'C' || seq[j] == 'S');
+    double fgc = N ? (double)gc / N : 0.0;
+    *corr = 0.0;
+    *kind = 0;
+    if (c->saltcorr == 0) return 0;
+    if (c->saltcorr >= 1 && c->saltcorr <= 6) {
+        double mon = mono_equiv_M(c);
+        if (!(mon > 0.0)) return 2;
+        switch (c->saltcorr) {
+        case 1: *corr = 16.6 * log10(mon); *kind = 1; break;
+        case 2: *corr = 16.6 * log10(mon / (1.0 + 0.7 * mon)); *kind = 1; break;
+        case 3: *corr = 12.5 * log10(mon); *kind = 1; break;
+        case 4: *corr = 11.7 * log10(mon); *kind = 1; break;
+        case 5: *corr = 0.368 * (double)(N - 1) * log(mon); *kind = 5; break;
+        default:
+            *corr = (4.29 * fgc - 3.95) * 1e-5 * log(mon) + 9.40e-6 * log(mon) * log(mon);
+            *kind = 6;
+        }
+        return 0;
+    }
+    if (c->saltcorr != 7) return 2;
+    double mon = (c->na + c->k + c->tris / 2.0) * 1e-3;
+    double mg = c->mg * 1e-3;
+    if (c->dntps > 0.0) {
+        /* free Mg2+: [Mg][dNTP] / [MgdNTP] = 1 / Ka with both totals conserved */
+        double ka = 3e4, dn = c->dntps * 1e-3;
+        double bq = ka * dn - ka * mg + 1.0;
+        mg = (-bq + sqrt(bq * bq + 4.0 * ka * mg)) / (2.0 * ka);
+    }
+    *kind = 6;
+    double a = 3.92, b = -0.911, cc = 6.26, d = 1.42, e = -48.2, f = 52.5, g = 8.31;
+    if (mon > 0.0) {
+        double R = sqrt(mg) / mon, lm = log(mon);
+        if (R < 0.22) {
+            *corr = (4.29 * fgc - 3.95) * 1e-5 * lm + 9.40e-6 * lm * lm;
+            return 0;
+        }
+        if (R < 6.0) {
+            a = 3.92 * (0.843 - 0.352 * sqrt(mon) * lm);
+            d = 1.42 * (1.279 - 4.03e-3 * lm - 8.03e-3 * lm * lm);
+            g = 8.31 * (0.486 - 0.258 * lm + 5.25e-3 * lm * lm * lm);
+        }
+    }
+    if (!(mg > 0.0) || N < 2) return 2;
+    double lg = log(mg);
+    *corr = (a + b * lg + fgc * (cc + d * lg) + (e + f * lg + g * lg * lg) / (2.0 * (N - 1))) * 1e-5;
+    return 0;
+}
+
+/*
  * dH and dS (before salt correction) of the duplex of `seq` (5'->3') with
  * `cseq` (its partner strand written 3'->5', position j pairing with seq[j]);
  * both of equal length L >= 2.  Steps 1-3 below; returns 0 ok, 1 untabulated
@@ -594,24 +671,22 @@ int or_nn_thermo(const char *seq, const char *cseq, double *dh_out, double *ds_o
 
 double or_tm_duplex(const char *seq, const char *cseq, const or_tm_cond *cond, int *status)
 {
-    int L = (int)strlen(seq);
     double dh = 0.0, ds = 0.0;
     *status = or_nn_thermo(seq, cseq, &dh, &ds);
     if (*status == 2) return 0.0;
     if (*status == 1) return -INFINITY;
 
     /* 4. salt correction and Tm */
-    double mon = mono_equiv_M(cond);
-    double tm_add = 0.0;
-    switch (cond->saltcorr) {
-    case 0: break;
-    case 5: ds += 0.368 * (double)(L - 1) * log(mon); break;
-    default: *status = 2; return 0.0;
-    }
+    double corr = 0.0;
+    int kind = 0;
+    if (or_salt_correction(cond, seq, &corr, &kind)) { *status = 2; return 0.0; }
+    if (kind == 5) ds += corr;
     double hiC = cond->dnac1 > cond->dnac2 ? cond->dnac1 : cond->dnac2;
     double loC = cond->dnac1 > cond->dnac2 ? cond->dnac2 : cond->dnac1;
     double C = (hiC - loC / 2.0) * 1e-9;
-    double tm = (1000.0 * dh) / (ds + 1.987 * log(C)) - 273.15 + tm_add;
+    double tm = (1000.0 * dh) / (ds + 1.987 * log(C)) - 273.15;
+    if (kind == 1) tm += corr;
+    if (kind == 6) tm = 1.0 / (1.0 / (tm + 273.15) + corr) - 273.15;
     return tm;
 }
 

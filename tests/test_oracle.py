@@ -532,3 +532,66 @@ def test_extract_planted_barcodes_dense_config():
     Lf, Lr = len(wl.pairs[0].fwd), len(wl.pairs[0].rev)
     for i, a in enumerate(r.amps):
         assert len(r.ext.amplicon(i)) == int(a[2] - a[1]) - Lf - Lr
+
+
+# ------------------------------------------------------------------ salt corrections
+def test_salt_correction_documented_values():
+    rows = _read_golden("salt_correction_documented.txt")
+    assert len(rows) == 4
+    for row in rows:
+        m = int(row[0])
+        na, k, tris, mg, dntps, want = (float(x) for x in row[1:])
+        t = TmSpec(na_mM=na, k_mM=k, tris_mM=tris, mg_mM=mg, dntps_mM=dntps, saltcorr=m)
+        corr, kind = oracle.salt_correction(t, "ACGTACGTAC")
+        assert kind == 1
+        assert round(corr, 2) == pytest.approx(want, abs=1e-9)
+
+
+def test_salt_logarithmic_methods_vanish_at_one_molar():
+    """Methods 1, 3, 4, 5 and 6 scale with the logarithm of the monovalent
+    concentration in mol/L: at 1 M they leave the uncorrected Tm (a wrong
+    unit -- mM instead of M -- or a dropped conversion fails this)."""
+    seq = "ACGTTGCAAGGCTTACGA"
+    base = oracle.tm_duplex(seq, comp(seq), TmSpec(na_mM=1000.0, saltcorr=0))
+    for m in (1, 3, 4, 5, 6):
+        t = oracle.tm_duplex(seq, comp(seq), TmSpec(na_mM=1000.0, saltcorr=m))
+        assert t == pytest.approx(base, abs=1e-9), m
+    # equivalents: 900 mM Na + 100 mM K, or 800 mM Na + 400 mM Tris, are 1 M too
+    for kw in (dict(na_mM=900.0, k_mM=100.0), dict(na_mM=800.0, tris_mM=400.0)):
+        assert oracle.tm_duplex(seq, comp(seq), TmSpec(saltcorr=4, **kw)) == pytest.approx(base, abs=1e-9)
+
+
+def test_salt_methods_raise_tm_with_sodium_and_method7_reduces_to_6_without_mg():
+    seq = "GGACTTAGCCATGCAAGTTA"
+    for m in range(1, 8):
+        vals = [oracle.tm_duplex(seq, comp(seq), TmSpec(na_mM=na, saltcorr=m)) for na in (20, 50, 150, 400)]
+        assert all(b > a for a, b in zip(vals, vals[1:])), (m, vals)
+    for na in (10.0, 50.0, 300.0):
+        assert oracle.tm_duplex(seq, comp(seq), TmSpec(na_mM=na, saltcorr=7)) == \
+            oracle.tm_duplex(seq, comp(seq), TmSpec(na_mM=na, saltcorr=6))
+    # with magnesium, method 7 uses its Mg2+ model: Tm rises with Mg2+
+    vals = [oracle.tm_duplex(seq, comp(seq), TmSpec(na_mM=20, mg_mM=mg, saltcorr=7)) for mg in (0.5, 1.5, 5.0)]
+    assert all(b > a for a, b in zip(vals, vals[1:]))
+    # dNTPs bind Mg2+: less free Mg2+, lower Tm
+    t0 = oracle.tm_duplex(seq, comp(seq), TmSpec(na_mM=20, mg_mM=2.0, saltcorr=7))
+    t1 = oracle.tm_duplex(seq, comp(seq), TmSpec(na_mM=20, mg_mM=2.0, dntps_mM=0.8, saltcorr=7))
+    assert t1 < t0
+
+
+def test_salt_methods_6_7_follow_gc_content():
+    """Owczarzy's corrections depend on the G+C fraction of the primer strand:
+    at low salt (negative ln) a GC-rich strand is corrected less."""
+    at_rich, gc_rich = "ATTATAATTAATATTAAT", "GCCGCGGCGGCCGCGCGG"
+    t = TmSpec(na_mM=20.0, saltcorr=6)
+    c_at, _ = oracle.salt_correction(t, at_rich)
+    c_gc, _ = oracle.salt_correction(t, gc_rich)
+    assert c_at > c_gc   # a larger 1/Tm increment lowers Tm more
+
+
+def test_salt_invalid_conditions_rejected():
+    with pytest.raises(ValueError):
+        oracle.salt_correction(TmSpec(na_mM=0.0, saltcorr=1), "ACGT")
+    with pytest.raises(ValueError):
+        oracle.salt_correction(TmSpec(na_mM=50.0, saltcorr=8), "ACGT")
+    with pytest.raises(ValueError):
+        oracle.salt_correction(TmSpec(na_mM=0.0, mg_mM=0.0, saltcorr=7), "ACGT")
