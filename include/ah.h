@@ -257,10 +257,22 @@ ah_status ah_pair_amplicons(const ah_store *st, ah_primer_set ps, const ah_hit *
  * (Allawi & SantaLucia 1997/1998, Peyret et al. 1999), terminal mismatches
  * (Bommarito et al. 2000).  A variant with a stack none of them covers is
  * skipped; a site with no usable variant has Tm = -inf.
- * saltcorr: 0 none, 5 = SantaLucia 1998 entropy correction
- * dS += 0.368 (N-1) ln[Na+eq] with [Na+eq] = Na + K + Tris/2 + 120 sqrt(Mg -
- * dNTPs) mM (the last term only when Mg > dNTPs).  Strand concentration
- * C = C_high - C_low / 2.
+ * saltcorr (the corrections the Tm_NN model offers; [Na+eq] = Na + K +
+ * Tris/2 + 120 sqrt(Mg - dNTPs) mM, the last term only when Mg > dNTPs
+ * (von Ahsen et al. 2001); N and the G+C fraction are the primer strand's):
+ *   0 none
+ *   1 Tm += 16.6 log10[Na+eq]                    (Schildkraut & Lifson 1965)
+ *   2 Tm += 16.6 log10([Na+eq] / (1 + 0.7 [Na+eq]))   (Wetmur 1991)
+ *   3 Tm += 12.5 log10[Na+eq]                    (SantaLucia et al. 1996)
+ *   4 Tm += 11.7 log10[Na+eq]                    (SantaLucia 1998)
+ *   5 dS += 0.368 (N - 1) ln[Na+eq]              (SantaLucia 1998)
+ *   6 1/Tm += (4.29 fGC - 3.95) 1e-5 ln[Na+eq] + 9.40e-6 ln^2[Na+eq]
+ *                                                (Owczarzy et al. 2004)
+ *   7 1/Tm += the Mg2+ model of Owczarzy et al. 2008 (free Mg2+ after dNTP
+ *     binding; monovalent ions Na + K + Tris/2; the 2004 formula when
+ *     sqrt[Mg2+]/[mon] < 0.22)
+ * AH_E_ARG for another value or a zero concentration under a logarithm.
+ * Strand concentration C = C_high - C_low / 2.
  * ---------------------------------------------------------------------- */
 typedef struct {
     double na_mM, k_mM, tris_mM, mg_mM, dntps_mM;

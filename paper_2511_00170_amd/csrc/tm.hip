@@ -126,24 +126,83 @@ constexpr NNTable make_terminal_table() {
 __constant__ NNTable g_stack = make_stack_table();
 __constant__ NNTable g_term = make_terminal_table();
 
+// Salt terms (the seven corrections of the Tm_NN model, each from its
+// paper): 1-4 add a constant to Tm; 5 adds 0.368 (N-1) ln(mon) to dS;
+// 6 (Owczarzy 2004) and 7 (Owczarzy 2008, Mg2+) add a term depending on the
+// G+C fraction and length of the primer strand to 1/Tm.
 struct TmConst {
-    int saltcorr;     // 0 none, 5 SantaLucia 1998 entropy term
-    double ln_mon;    // ln of the monovalent-equivalent concentration (M)
+    int saltcorr;
+    double ln_mon;    // ln of the monovalent-equivalent concentration (M; methods 5, 6, 7-monovalent)
+    double dtm;       // methods 1-4: added to Tm
+    int mg_model;     // method 7: 1 = Mg2+ formula, 0 = monovalent formula of method 6
+    double a, b, c, d, e, f, g, ln_mg;  // method 7 Mg2+ formula
     double rlnc;      // R ln C, C = C_high - C_low / 2 (M)
     double threshold;
     int filter;
 };
 
-__device__ TmConst tm_const(const ah_tm_params &p) {
-    TmConst k;
+// Everything here also runs on the host (ah_tm_nn checks the conditions).
+__host__ __device__ inline int tm_salt_setup(const ah_tm_params &p, TmConst *k) {
     double mon = p.na_mM + p.k_mM + p.tris_mM / 2.0;
     if (p.dntps_mM < p.mg_mM) mon += 120.0 * sqrt(p.mg_mM - p.dntps_mM);  // von Ahsen et al. 2001
     mon = mon * 1e-3;
+    k->saltcorr = p.saltcorr;
+    k->ln_mon = 0.0;
+    k->dtm = 0.0;
+    k->mg_model = 0;
+    k->a = k->b = k->c = k->d = k->e = k->f = k->g = k->ln_mg = 0.0;
+    if (p.saltcorr == 0) return 0;
+    if (p.saltcorr >= 1 && p.saltcorr <= 6) {
+        if (!(mon > 0.0)) return 1;
+        k->ln_mon = log(mon);
+        if (p.saltcorr == 1) k->dtm = 16.6 * log10(mon);                       // Schildkraut & Lifson 1965
+        if (p.saltcorr == 2) k->dtm = 16.6 * log10(mon / (1.0 + 0.7 * mon));   // Wetmur 1991
+        if (p.saltcorr == 3) k->dtm = 12.5 * log10(mon);                       // SantaLucia et al. 1996
+        if (p.saltcorr == 4) k->dtm = 11.7 * log10(mon);                       // SantaLucia 1998
+        return 0;
+    }
+    if (p.saltcorr != 7) return 1;
+    // Owczarzy et al. 2008: monovalent ions without the Mg2+ equivalent, free
+    // Mg2+ after dNTP binding (association constant 3e4 /M)
+    const double mon7 = (p.na_mM + p.k_mM + p.tris_mM / 2.0) * 1e-3;
+    double mg = p.mg_mM * 1e-3;
+    if (p.dntps_mM > 0.0) {
+        const double ka = 3e4, dn = p.dntps_mM * 1e-3;
+        const double bq = ka * dn - ka * mg + 1.0;
+        mg = (-bq + sqrt(bq * bq + 4.0 * ka * mg)) / (2.0 * ka);
+    }
+    double a = 3.92, d = 1.42, g = 8.31;
+    if (mon7 > 0.0) {
+        const double R = sqrt(mg) / mon7, lm = log(mon7);
+        if (R < 0.22) {  // monovalent ions dominate: the 2004 formula
+            k->ln_mon = lm;
+            return 0;
+        }
+        if (R < 6.0) {
+            a = 3.92 * (0.843 - 0.352 * sqrt(mon7) * lm);
+            d = 1.42 * (1.279 - 4.03e-3 * lm - 8.03e-3 * lm * lm);
+            g = 8.31 * (0.486 - 0.258 * lm + 5.25e-3 * lm * lm * lm);
+        }
+    }
+    if (!(mg > 0.0)) return 1;
+    k->mg_model = 1;
+    k->a = a;
+    k->b = -0.911;
+    k->c = 6.26;
+    k->d = d;
+    k->e = -48.2;
+    k->f = 52.5;
+    k->g = g;
+    k->ln_mg = log(mg);
+    return 0;
+}
+
+__device__ TmConst tm_const(const ah_tm_params &p) {
+    TmConst k;
+    (void)tm_salt_setup(p, &k);
     const double hiC = p.dnac1_nM > p.dnac2_nM ? p.dnac1_nM : p.dnac2_nM;
     const double loC = p.dnac1_nM > p.dnac2_nM ? p.dnac2_nM : p.dnac1_nM;
     const double C = (hiC - loC / 2.0) * 1e-9;
-    k.saltcorr = p.saltcorr;
-    k.ln_mon = log(mon);
     k.rlnc = 1.987 * log(C);
     k.threshold = p.threshold_C;
     k.filter = p.filter;
@@ -196,7 +255,21 @@ __device__ bool duplex_tm(uint64_t V, uint64_t C, int L, const double *sdh, cons
         ds += sds[i];
     }
     if (k.saltcorr == 5) ds += 0.368 * (double)(L - 1) * k.ln_mon;
-    *out = (1000.0 * dh) / (ds + k.rlnc) - 273.15;
+    double tm = (1000.0 * dh) / (ds + k.rlnc) - 273.15;
+    if (k.saltcorr >= 1 && k.saltcorr <= 4) tm += k.dtm;
+    if (k.saltcorr >= 6) {
+        // G+C fraction of V: codes 1 (C) and 2 (G) have differing bits
+        const uint64_t lmask = L >= 32 ? ~0ull : ((1ull << (2 * L)) - 1);
+        const double fgc = (double)__popcll((V ^ (V >> 1)) & 0x5555555555555555ull & lmask) / (double)L;
+        double corr;
+        if (k.mg_model)
+            corr = (k.a + k.b * k.ln_mg + fgc * (k.c + k.d * k.ln_mg) +
+                    (k.e + k.f * k.ln_mg + k.g * k.ln_mg * k.ln_mg) / (2.0 * (L - 1))) * 1e-5;
+        else
+            corr = (4.29 * fgc - 3.95) * 1e-5 * k.ln_mon + 9.40e-6 * k.ln_mon * k.ln_mon;
+        tm = 1.0 / (1.0 / (tm + 273.15) + corr) - 273.15;
+    }
+    *out = tm;
     return true;
 }
 
@@ -340,7 +413,10 @@ extern "C" ah_status ah_tm_nn(const ah_store *st, ah_primer_set ps, const ah_amp
                               uint64_t amp_cap, const ah_tm_params *p, double *d_tm, double *d_tm_site,
                               uint8_t *d_pass, void *stream) {
     if (!st || !ps || !p || !d_n_amps || (amp_cap && (!d_amps || !d_tm || !d_tm_site || !d_pass))) return AH_E_ARG;
-    if (p->saltcorr != 0 && p->saltcorr != 5) return AH_E_ARG;
+    {
+        TmConst k;
+        if (tm_salt_setup(*p, &k)) return AH_E_ARG;  // unknown method or a zero concentration under a logarithm
+    }
     for (uint32_t q = 0; q < ps->n_pairs; q++)
         if (!ps->h_pairs[q].prim[0].D || !ps->h_pairs[q].prim[1].D) return AH_E_LIMIT;
     if (!amp_cap) return AH_OK;
@@ -391,7 +467,10 @@ __global__ void ah_tm_duplex_kernel(const char *seq, const char *cseq, const uin
 extern "C" ah_status ah_tm_duplex(const char *d_seq, const char *d_cseq, const uint32_t *d_len, uint32_t n,
                                   uint32_t stride, const ah_tm_params *p, double *d_tm, void *stream) {
     if (!p || (n && (!d_seq || !d_cseq || !d_len || !d_tm))) return AH_E_ARG;
-    if (p->saltcorr != 0 && p->saltcorr != 5) return AH_E_ARG;
+    {
+        TmConst k;
+        if (tm_salt_setup(*p, &k)) return AH_E_ARG;  // unknown method or a zero concentration under a logarithm
+    }
     if (!n) return AH_OK;
     unsigned blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;

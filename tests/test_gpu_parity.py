@@ -200,3 +200,65 @@ def test_tm_duplex_random_mismatches_match_oracle(ah):
         fin = ~np.isnan(o)
         assert fin.sum() > 5000
         assert np.abs(g[fin] - o[fin]).max() <= P.TM_TOL
+
+
+SALT_CONDITIONS = [
+    dict(na_mM=50),
+    dict(na_mM=10, k_mM=40, tris_mM=10, mg_mM=1.5, dntps_mM=0.2),
+    dict(na_mM=20, mg_mM=3.0),                 # method 7: Mg2+ model, 0.22 <= R < 6
+    dict(na_mM=1, mg_mM=10.0),                 # method 7: R >= 6
+    dict(na_mM=0, mg_mM=2.0, dntps_mM=0.5),    # method 7: no monovalent ions
+    dict(na_mM=200, mg_mM=0.1),                # method 7: R < 0.22, the 2004 formula
+]
+
+
+@pytest.mark.parametrize("method", [1, 2, 3, 4, 5, 6, 7])
+def test_tm_duplex_every_salt_correction_matches_oracle(ah, method):
+    rng = np.random.default_rng(70 + method)
+    comp = {"A": "T", "C": "G", "G": "C", "T": "A"}
+    seqs, cseqs = [], []
+    for _ in range(3000):
+        L = int(rng.integers(2, 33))
+        s = "".join(rng.choice(list("ACGT"), size=L))
+        c = [comp[x] for x in s]
+        for j in rng.choice(L, size=int(rng.integers(0, min(L, 3) + 1)), replace=False):
+            c[j] = rng.choice([b for b in "ACGT" if b != c[j]])
+        seqs.append(s)
+        cseqs.append("".join(c))
+    _say("salt method", method)
+    for kw in SALT_CONDITIONS:
+        cond = TmSpec(saltcorr=method, **kw)
+        try:
+            oracle.salt_correction(cond, "ACGT")
+        except ValueError:
+            # undefined for these concentrations: the library refuses as well
+            with pytest.raises(ah.AhError):
+                ah.tm_duplex(seqs[:4], cseqs[:4], cond)
+            continue
+        g = ah.tm_duplex(seqs, cseqs, cond)
+        o = np.array([oracle.tm_duplex(s, c, cond) for s, c in zip(seqs, cseqs)])
+        assert (np.isnan(g) == np.isnan(o)).all(), kw
+        fin = ~np.isnan(o)
+        assert fin.sum() > 1000
+        assert np.abs(g[fin] - o[fin]).max() <= P.TM_TOL, kw
+
+
+@pytest.mark.parametrize("method", [2, 6, 7])
+def test_amplicon_tm_with_other_salt_corrections(ah, method):
+    wl = synth.gen_config(1, n_seqs=60)
+    buf, off = wl.concat()
+    st = ah.Store.from_workload(wl)
+    tm = TmSpec(na_mM=30, mg_mM=2.0, dntps_mM=0.4, saltcorr=method, threshold_C=50.0)
+    _say("amplicon Tm salt", method)
+    r = P.gpu_run(st, wl.pairs, wl.orient_mask, tm, None)
+    o = oracle.run(buf, off, wl.pairs, wl.orient_mask, tm, None)
+    P.compare_amps(r["amps"], o.amps)
+    P.compare_tm(r["tm"], r["tm_site"], r["pass"], o.tm)
+    assert len(o.amps) > 0
+
+
+def test_invalid_salt_method_is_rejected(ah):
+    with pytest.raises(ah.AhError):
+        ah.tm_duplex(["ACGTACGT"], ["TGCATGCA"], TmSpec(saltcorr=8))
+    with pytest.raises(ah.AhError):
+        ah.tm_duplex(["ACGTACGT"], ["TGCATGCA"], TmSpec(na_mM=0, saltcorr=1))
