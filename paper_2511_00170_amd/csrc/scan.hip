@@ -39,6 +39,9 @@ struct GenericFilter {
     uint32_t n_lds;
     __device__ uint32_t groups(const ScanArgs &a) const { return a.n_groups; }
     static constexpr bool kUsesBase = false;
+    static constexpr int kW = AH_WMAX;
+    static constexpr bool kHoistGuard = false;  // codes are read at run time
+    static constexpr bool kSkipEmpty = true;
     __device__ __forceinline__ void filter(uint32_t g, const AhBase &, const uint32_t (&Sh)[AH_WMAX][2],
                                            const uint32_t (&Sl)[AH_WMAX][2], uint32_t v0, uint32_t v1,
                                            uint32_t (&C)[8]) const {
@@ -232,6 +235,9 @@ static std::string jit_source(const ah_primer_set_ *ps) {
     s += std::string("#define AH_JIT_USES_BASE ") + (any_groups ? "true" : "false") + "\n";
     s += "struct JitFilter {\n";
     s += "  static constexpr bool kUsesBase = AH_JIT_USES_BASE;\n";
+    s += "  static constexpr int kW = " + std::to_string(ps->max_W > 0 ? ps->max_W : 1) + ";\n";
+    s += std::string("  static constexpr bool kHoistGuard = ") + (ps->n_pairs > 1 ? "true" : "false") + ";\n";
+    s += std::string("  static constexpr bool kSkipEmpty = ") + (ps->n_pairs > 1 ? "true" : "false") + ";\n";
     s += "  __device__ uint32_t groups(const ScanArgs &) const { return " + std::to_string(ps->n_pairs) + "u; }\n";
     s += "  __device__ __forceinline__ void filter(uint32_t g, const AhBase &B, const uint32_t (&Sh)[AH_WMAX][2], "
          "const uint32_t (&Sl)[AH_WMAX][2], uint32_t v0, uint32_t v1, uint32_t (&C)[8]) const {\n";

@@ -337,13 +337,14 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
         Wh[AH_TW - 1] = nh0;
         Wl[AH_TW - 1] = nl0;
     }
-    // lanes past the sequence end hold a repeated block: no candidates there
-    // (windows reaching past the end are rejected in verification)
-    const uint32_t v = lane < L.nb ? 0xFFFFFFFFu : 0u;
-    // bit q of S*[i][w]: plane bit of base q + i (w selects bases 0-31 / 32-63)
+    // Lanes past the sequence end hold a repeated block; their candidates are
+    // windows past the end, which verification rejects, so no lane mask.
+    const uint32_t v = 0xFFFFFFFFu;
+    // bit q of S*[i][w]: plane bit of base q + i (w selects bases 0-31 / 32-63);
+    // only the F::kW offsets the filter reads are formed
     uint32_t Sh[AH_WMAX][2], Sl[AH_WMAX][2];
 #pragma unroll
-    for (int i = 0; i < AH_WMAX; i++) {
+    for (int i = 0; i < F::kW; i++) {
         Sh[i][0] = ah_funnel(h1, h0, i);
         Sh[i][1] = ah_funnel(nh0, h1, i);
         Sl[i][0] = ah_funnel(l1, l0, i);
@@ -355,16 +356,20 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
         // asm, no instruction): otherwise, with compile-time codes, the
         // compiler hoists every group's set tests out of this loop as
         // invariants and runs out of registers once there are many groups.
+        if (F::kHoistGuard) {
 #pragma unroll
-        for (int i = 0; i < AH_WMAX; i++)
-            asm volatile("" : "+v"(Sh[i][0]), "+v"(Sh[i][1]), "+v"(Sl[i][0]), "+v"(Sl[i][1]));
-        if (F::kUsesBase)
+            for (int i = 0; i < F::kW; i++)
+                asm volatile("" : "+v"(Sh[i][0]), "+v"(Sh[i][1]), "+v"(Sl[i][0]), "+v"(Sl[i][1]));
+        }
+        if (F::kUsesBase && F::kHoistGuard)
             asm volatile("" : "+v"(B.ph), "+v"(B.h0), "+v"(B.h1), "+v"(B.nh), "+v"(B.pl), "+v"(B.l0), "+v"(B.l1),
                          "+v"(B.nl));
         uint32_t C[8];
         f.filter(g, B, Sh, Sl, v, v, C);
-        const uint32_t any = (C[0] | C[1] | C[2] | C[3]) | (C[4] | C[5] | C[6] | C[7]);
-        if (__ballot(any != 0) == 0) continue;
+        if (F::kSkipEmpty) {  // many groups: most have no candidate in a tile
+            const uint32_t any = (C[0] | C[1] | C[2] | C[3]) | (C[4] | C[5] | C[6] | C[7]);
+            if (__ballot(any != 0) == 0) continue;
+        }
         // room for this group's candidates (at most 4 x 64 entries); a
         // non-draining flush leaves fewer than 64
         if (qn > AH_QCAP - 256) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, false);
@@ -390,7 +395,11 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
 //                                       clamp sites 0-31 / 32-63 of pattern x); a
 //                                       candidate must pass a necessary condition
 //                                       of a hit; verification decides.
-//   F::kUsesBase                        whether filter reads the base words B.
+//   F::kUsesBase                        whether filter reads the base words B,
+//   F::kW                               shifted planes it reads (offsets 0 .. kW-1),
+//   F::kHoistGuard                      its codes are compile-time and there are
+//                                       several groups (see the group loop),
+//   F::kSkipEmpty                       test for a group without candidates first.
 // n_lds: pattern records staged in sPat; kLdsOnly: n_lds covers every record.
 template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds,
