@@ -20,8 +20,12 @@ typedef __hip_internal::int64_t int64_t;
 // Pre-filter width: at most this many clamp positions are tested with
 // bit-parallel word operations before a candidate window is verified.
 #define AH_WMAX 6
-// Bases per wave tile = 64 blocks x 64 bases; one block per lane.
-#define AH_TILE_BLOCKS 64
+// A scan tile is 64 lanes x AH_BPL blocks of 64 bases.
+#ifndef AH_BPL
+#define AH_BPL 1                              // 64-base blocks per lane in the scan
+#endif
+#define AH_NW (2 * AH_BPL)                    // 32-bit words per lane and bit plane
+#define AH_TILE_BLOCKS (64 * AH_BPL)
 #define AH_TILE_BASES (AH_TILE_BLOCKS * 64)
 #define AH_MAXL 32
 // Variants per primer the Tm kernel will enumerate.

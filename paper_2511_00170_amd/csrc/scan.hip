@@ -42,9 +42,8 @@ struct GenericFilter {
     static constexpr int kW = AH_WMAX;
     static constexpr bool kHoistGuard = false;  // codes are read at run time
     static constexpr bool kSkipEmpty = true;
-    __device__ __forceinline__ void filter(uint32_t g, const AhBase &, const uint32_t (&Sh)[AH_WMAX][2],
-                                           const uint32_t (&Sl)[AH_WMAX][2], uint32_t v0, uint32_t v1,
-                                           uint32_t (&C)[8]) const {
+    __device__ __forceinline__ void filter(uint32_t g, const AhBase &, const uint32_t (&Sh)[AH_WMAX][AH_NW],
+                                           const uint32_t (&Sl)[AH_WMAX][AH_NW], uint32_t (&C)[4 * AH_NW]) const {
         uint32_t fc[4][2], W = 0;
 #pragma unroll
         for (int x = 0; x < 4; x++) {
@@ -61,20 +60,21 @@ struct GenericFilter {
             fc[x][0] = (uint32_t)codes;
             fc[x][1] = (uint32_t)(codes >> 32);
             W = wx > W ? wx : W;
-            C[2 * x] = v0;
-            C[2 * x + 1] = v1;
+#pragma unroll
+            for (int w = 0; w < AH_NW; w++) C[AH_NW * x + w] = 0xFFFFFFFFu;
         }
 #pragma unroll
         for (int i = 0; i < AH_WMAX; i++) {
             if ((uint32_t)i >= W) break;
-            const uint32_t h0 = Sh[i][0], l0 = Sl[i][0], h1 = Sh[i][1], l1 = Sl[i][1];
-            const uint32_t a0 = ~(h0 | l0), c0 = ~h0 & l0, g0 = h0 & ~l0, t0 = h0 & l0;
-            const uint32_t a1 = ~(h1 | l1), c1 = ~h1 & l1, g1 = h1 & ~l1, t1 = h1 & l1;
 #pragma unroll
-            for (int x = 0; x < 4; x++) {
-                const uint32_t m = ((i < 4 ? fc[x][0] >> (8 * i) : fc[x][1] >> (8 * (i - 4)))) & 0xFu;
-                C[2 * x] &= ah_pick(a0, c0, g0, t0, m);
-                C[2 * x + 1] &= ah_pick(a1, c1, g1, t1, m);
+            for (int w = 0; w < AH_NW; w++) {
+                const uint32_t h = Sh[i][w], l = Sl[i][w];
+                const uint32_t aa = ~(h | l), cc = ~h & l, gg = h & ~l, tt = h & l;
+#pragma unroll
+                for (int x = 0; x < 4; x++) {
+                    const uint32_t m = ((i < 4 ? fc[x][0] >> (8 * i) : fc[x][1] >> (8 * (i - 4)))) & 0xFu;
+                    C[AH_NW * x + w] &= ah_pick(aa, cc, gg, tt, m);
+                }
             }
         }
     }
@@ -85,7 +85,7 @@ template <bool kLdsOnly>
 __global__ void __launch_bounds__(256) ah_scan_kernel(ScanArgs a) {
     __shared__ DPat sPat[AH_LDS_PATS];
     __shared__ TileCtx sCtx[4][AH_NCTX];
-    __shared__ uint32_t sQ[4][AH_QCAP][3];
+    __shared__ uint32_t sQ[4][AH_QCAP][AH_QW];
     __shared__ uint32_t sW[4][AH_NCTX][2][AH_TW];
     ah_stage_patterns(a, sPat, AH_LDS_PATS);
     const uint32_t n_lds = a.n_pats < AH_LDS_PATS ? a.n_pats : AH_LDS_PATS;
@@ -239,40 +239,36 @@ static std::string jit_source(const ah_primer_set_ *ps) {
     s += std::string("  static constexpr bool kHoistGuard = ") + (ps->n_pairs > 1 ? "true" : "false") + ";\n";
     s += std::string("  static constexpr bool kSkipEmpty = ") + (ps->n_pairs > 1 ? "true" : "false") + ";\n";
     s += "  __device__ uint32_t groups(const ScanArgs &) const { return " + std::to_string(ps->n_pairs) + "u; }\n";
-    s += "  __device__ __forceinline__ void filter(uint32_t g, const AhBase &B, const uint32_t (&Sh)[AH_WMAX][2], "
-         "const uint32_t (&Sl)[AH_WMAX][2], uint32_t v0, uint32_t v1, uint32_t (&C)[8]) const {\n";
+    s += "  __device__ __forceinline__ void filter(uint32_t g, const AhBase &B, const uint32_t (&Sh)[AH_WMAX][AH_NW], "
+         "const uint32_t (&Sl)[AH_WMAX][AH_NW], uint32_t (&C)[4 * AH_NW]) const {\n";
     s += "    switch (g) {\n";
     for (uint32_t g = 0; g < ps->n_pairs; g++) {
         s += "    case " + std::to_string(g) + "u: {\n";
         for (int x = 0; x < 4; x++) {
             const DPat &P = ps->h_pats[4 * g + x];
             const uint32_t W = (P.meta >> 16) & 0xFFu;
-            std::string c0 = "v0", c1 = "v1";
-            for (uint32_t i = 0; i < W; i++) {
-                const unsigned m = P.fcode[i];
-                if (m == 15) continue;  // N matches every base
-                const std::string I = std::to_string(i), M = std::to_string(m);
-                c0 = "ah_and_set<" + M + "u>(" + c0 + ", Sh[" + I + "][0], Sl[" + I + "][0])";
-                c1 = "ah_and_set<" + M + "u>(" + c1 + ", Sh[" + I + "][1], Sl[" + I + "][1])";
-            }
             const FiltPlan &plan = plans[4 * g + x];
-            if (plan.n_groups) {
-                std::string any0, any1;
-                for (int q = 0; q < plan.n_groups; q++) {
-                    const std::string t0 = set_test_chain("0xFFFFFFFFu", plan.groups[q], 0);
-                    const std::string t1 = set_test_chain("0xFFFFFFFFu", plan.groups[q], 1);
-                    any0 += (q ? " | " : "") + t0;
-                    any1 += (q ? " | " : "") + t1;
+            for (int w = 0; w < AH_NW; w++) {
+                const std::string Ws = std::to_string(w);
+                std::string c = "0xFFFFFFFFu";
+                for (uint32_t i = 0; i < W; i++) {
+                    const unsigned m = P.fcode[i];
+                    if (m == 15) continue;  // N matches every base
+                    const std::string I = std::to_string(i), M = std::to_string(m);
+                    c = "ah_and_set<" + M + "u>(" + c + ", Sh[" + I + "][" + Ws + "], Sl[" + I + "][" + Ws + "])";
                 }
-                c0 = "(" + c0 + ") & (" + any0 + ")";
-                c1 = "(" + c1 + ") & (" + any1 + ")";
+                if (plan.n_groups) {
+                    std::string any;
+                    for (int q = 0; q < plan.n_groups; q++)
+                        any += (q ? " | " : "") + set_test_chain("0xFFFFFFFFu", plan.groups[q], w);
+                    c = "(" + c + ") & (" + any + ")";
+                }
+                s += "      C[" + std::to_string(AH_NW * x + w) + "] = " + c + ";\n";
             }
-            s += "      C[" + std::to_string(2 * x) + "] = " + c0 + ";\n";
-            s += "      C[" + std::to_string(2 * x + 1) + "] = " + c1 + ";\n";
         }
         s += "      break; }\n";
     }
-    s += "    default: for (int w = 0; w < 8; w++) C[w] = 0u;\n";
+    s += "    default: for (int w = 0; w < 4 * AH_NW; w++) C[w] = 0u;\n";
     s += "    }\n  }\n};\n";
     const uint32_t n_lds = ps->n_pats < AH_LDS_PATS ? ps->n_pats : AH_LDS_PATS;
     s += "#define AH_JIT_LDS_PATS " + std::to_string(n_lds) + "u\n";
@@ -280,7 +276,7 @@ static std::string jit_source(const ah_primer_set_ *ps) {
     s += "extern \"C\" __global__ void __launch_bounds__(256) ah_scan_jit(ScanArgs a) {\n"
          "  __shared__ DPat sPat[AH_JIT_LDS_PATS];\n"
          "  __shared__ TileCtx sCtx[4][AH_NCTX];\n"
-         "  __shared__ uint32_t sQ[4][AH_QCAP][3];\n"
+         "  __shared__ uint32_t sQ[4][AH_QCAP][AH_QW];\n"
          "  __shared__ uint32_t sW[4][AH_NCTX][2][AH_TW];\n"
          "  ah_stage_patterns(a, sPat, AH_JIT_LDS_PATS);\n"
          "  JitFilter f;\n"

@@ -4,20 +4,19 @@
 // kernel and compiled by hipRTC, with constant pattern codes, for kernels
 // specialised to one primer set.
 //
-// Work layout.  A tile is 64 blocks (4096 bases) of one sequence; a wave owns
-// a contiguous run of tiles and walks it in order, prefetching the next
-// tile's blocks while it works on the current one (lane i owns block i and
-// reads it with one 128-bit load).  For its 64 clamp sites q a lane builds
-// bit-vectors "base q+i is in IUPAC set m" from funnel shifts of the two bit
-// planes and ANDs them over the first W clamp positions of each oriented
-// pattern -- a window that fails this pre-filter can never be a hit.  A lane
-// whose candidate mask for a pattern is non-zero appends (mask, pattern,
-// lane, tile) to a per-wave LDS queue -- one ballot per pattern gives the
-// slots, no prefix sums.  The queue spans several tiles and is verified in
-// full-wave rounds: each entry's windows are read back from the (L2-resident)
-// store and checked exactly against the pattern's per-base masks, the full
-// clamp, N bases and the substitution count.  Hits are rare and appended
-// with one atomic each.
+// Work layout.  A tile is 64 x AH_BPL blocks of one sequence (64 bases each);
+// a wave owns a contiguous run of tiles and walks it in order, prefetching
+// the next tile's blocks while it works on the current one (lane i owns
+// blocks AH_BPL*i .. AH_BPL*i + AH_BPL-1, read with 128-bit loads).  For its
+// clamp sites q a lane builds bit-vectors "base q+i is in IUPAC set m" from
+// funnel shifts of the two bit planes and ANDs them over the filter
+// positions of each oriented pattern -- a window that fails this pre-filter
+// can never be a hit.  A lane whose candidate mask for a pattern is non-zero
+// appends (mask, pattern, lane, tile) to a per-wave LDS queue -- one ballot
+// per pattern gives the slots, no prefix sums.  The queue spans several
+// tiles and is verified in full-wave rounds against the tiles' words kept in
+// LDS: the full clamp, N bases and the substitution count.  Hits are rare
+// and appended with one atomic each.
 #pragma once
 
 #include "ah_dev.h"
@@ -52,37 +51,39 @@ __device__ __forceinline__ uint32_t ah_and_set(uint32_t acc, uint32_t h, uint32_
     return acc & ((h & high) | (~h & low));
 }
 
-// The lane's 64 positions of both planes with their neighbours: p = the 32
-// positions before them (previous lane, or the block before the tile), x0/x1
-// = their two words, n = the 32 positions after them.
+// The lane's positions of both planes with their neighbours: word 0 = the
+// 32 positions before them (previous lane, or the block before the tile),
+// words 1..AH_NW = the lane's own, word AH_NW+1 = the 32 positions after.
 struct AhBase {
-    uint32_t ph, h0, h1, nh;
-    uint32_t pl, l0, l1, nl;
+    uint32_t h[AH_NW + 2];
+    uint32_t l[AH_NW + 2];
 };
 
-// Word Wd (0: positions 0-31, 1: 32-63) of a plane shifted by D positions
-// (bit q = base q + D), -31 <= D <= 31: one funnel shift, none for D = 0.
+// Word Wd (positions 32*Wd .. 32*Wd+31 of the lane) of a plane shifted by D
+// positions (bit q = base q + D), -31 <= D <= 31: one funnel shift, none for D = 0.
 template <int D, int Wd>
-__device__ __forceinline__ uint32_t ah_shw(uint32_t p, uint32_t x0, uint32_t x1, uint32_t n) {
+__device__ __forceinline__ uint32_t ah_shw(const uint32_t (&x)[AH_NW + 2]) {
     static_assert(D > -32 && D < 32, "shift out of range");
-    if constexpr (D == 0) return Wd == 0 ? x0 : x1;
-    else if constexpr (D > 0) return Wd == 0 ? ah_funnel(x1, x0, D) : ah_funnel(n, x1, D);
-    else return Wd == 0 ? ah_funnel(x0, p, 32 + D) : ah_funnel(x1, x0, 32 + D);
+    if constexpr (D == 0) return x[Wd + 1];
+    else if constexpr (D > 0) return ah_funnel(x[Wd + 2], x[Wd + 1], D);
+    else return ah_funnel(x[Wd + 1], x[Wd], 32 + D);
 }
 
 // acc AND (bit q: base q + D is in IUPAC set M), from the base words
 template <uint32_t M, int D, int Wd>
 __device__ __forceinline__ uint32_t ah_and_at(uint32_t acc, const AhBase &b) {
-    return ah_and_set<M>(acc, ah_shw<D, Wd>(b.ph, b.h0, b.h1, b.nh), ah_shw<D, Wd>(b.pl, b.l0, b.l1, b.nl));
+    return ah_and_set<M>(acc, ah_shw<D, Wd>(b.h), ah_shw<D, Wd>(b.l));
 }
 
 // Per-tile context kept for deferred verification.
 struct TileCtx {
     uint64_t gbase;  // store position (block index * 64) of the tile's first base
     uint32_t seq;
-    uint32_t len;
+    int32_t lo;      // lowest tile-relative window start: -min(pos0, 32)
+    int32_t room;    // bases from the tile start to the sequence end (capped at 2^20)
     uint32_t pos0;   // sequence position of the tile's first base
     uint32_t has_n;
+    uint32_t pad;
 };
 
 #ifndef AH_QCAP
@@ -92,6 +93,9 @@ struct TileCtx {
 #define AH_NCTX 2                         // tiles whose candidates may wait in the queue (<= 4)
 #endif
 #define AH_TW (2 * AH_TILE_BLOCKS + 2)    // words per plane of a tile (+ one word each side)
+#define AH_QW (AH_NW + 1)                 // queue entry: the lane's candidate words + tag
+// N-bitmap words covering the tile's blocks and one block on each side
+#define AH_NBW ((AH_TILE_BLOCKS + 2 + 31) / 32 + 1)
 
 __device__ __forceinline__ uint32_t ah_uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ uint64_t ah_uni64(uint64_t x) {
@@ -140,9 +144,9 @@ struct SeqCursor {
 // are unconditional (addresses clamped into the sequence) so they stay in
 // flight until the next iteration uses them.
 struct TileLoad {
-    uint4 blk;       // this lane's block (lanes past the end repeat the last one)
+    uint4 blk[AH_BPL];  // this lane's blocks (lanes past the end repeat the last one)
     uint4 hal;       // lane 0: the block before the tile; lane 63: the block after it
-    uint32_t nbw;    // lanes 0-3: the N-bitmap words around the tile (others repeat word 3)
+    uint32_t nbw;    // lanes 0..AH_NBW-1: the N-bitmap words around the tile
     uint32_t nb;     // blocks in the tile (uniform)
     uint32_t rel0;   // first block of the tile within its sequence (uniform)
     uint64_t gb0;    // store block of the tile's first block (uniform)
@@ -157,23 +161,28 @@ __device__ __forceinline__ void tile_issue(const ScanArgs &a, const SeqCursor &c
     // Addresses are a uniform base plus a 32-bit per-lane byte offset (one
     // vector op per load).  The base is the block before the tile (its
     // address is formed but only read when that block is in the sequence):
-    // lane l reads block 1 + own, lane 0's halo is block 0 when the tile has
-    // a predecessor, lane 63's halo is block 65 when it has a successor.
+    // block j of the tile is at offset 1 + j, lane 0's halo is block 0 when
+    // the tile has a predecessor, lane 63's halo the block after the tile.
     const uint64_t base = (uint64_t)a.st.d_blocks + 16u * (uint64_t)L.gb0 - 16u;
-    const uint32_t own = lane < L.nb ? lane : L.nb - 1;
-    uint32_t o_hal = own + 1;
+#pragma unroll
+    for (int b = 0; b < AH_BPL; b++) {
+        uint32_t own = AH_BPL * lane + b;
+        own = own < L.nb ? own : L.nb - 1;
+        L.blk[b] = *(const uint4 *)(base + 16u * (own + 1));
+    }
+    uint32_t o_hal = (AH_BPL * lane < L.nb ? AH_BPL * lane : L.nb - 1) + 1;
     if (lane == 0 && L.rel0 != 0) o_hal = 0;
     if (lane == 63 && L.rel0 + AH_TILE_BLOCKS < c.nblk) o_hal = AH_TILE_BLOCKS + 1;
-    L.blk = *(const uint4 *)(base + 16u * (own + 1));
     L.hal = *(const uint4 *)(base + 16u * o_hal);
-    // N-bitmap words: the four words from wb = max(gb0/32, 1) - 1 cover
-    // blocks gb0-1 .. gb0+64.  A nonzero word means the tile may touch an N
-    // -- a superset, which only costs exact per-block lookups in verification.
+    // N-bitmap words from wb = max(gb0/32, 1) - 1 cover blocks gb0-1 ..
+    // gb0+AH_TILE_BLOCKS.  A nonzero word means the tile may touch an N -- a
+    // superset, which only costs exact per-block lookups in verification.
     const uint64_t q = L.gb0 >> 5;
     const uint64_t wb = (q > 1 ? q : 1) - 1;
     const uint64_t nw = (a.st.n_blocks + 31) >> 5;
     const uint32_t room = (uint32_t)(nw - 1 - wb);  // words after wb
-    const uint32_t wi = lane < 3 ? (lane < room ? lane : room) : (3u < room ? 3u : room);
+    uint32_t wi = lane < AH_NBW - 1 ? lane : AH_NBW - 1;
+    wi = wi < room ? wi : room;
     L.nbw = *(const uint32_t *)((uint64_t)a.st.d_nbits + 4u * (uint64_t)wb + 4u * wi);
 }
 
@@ -196,16 +205,19 @@ __device__ __forceinline__ void ah_pattern_record(const ScanArgs &a, const DPat 
 }
 
 // Verify queued entries [e0, e1) (at most 64: one per lane).  Entry =
-// {candidate mask bits 0-31, bits 32-63, X << 8 | ctx << 6 | lane}; windows
-// are read from the tile words kept in LDS (sW[ctx][plane][word]).
+// {candidate words 0..AH_NW-1 (bit q of word w: clamp site 32w+q of the
+// lane), X << 8 | ctx << 6 | lane}; windows are read from the tile words
+// kept in LDS (sW[ctx][plane][word]).
 template <bool kLdsOnly>
 __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
-                                const uint32_t (*sQ)[3], uint32_t e0, uint32_t e1,
+                                const uint32_t (*sQ)[AH_QW], uint32_t e0, uint32_t e1,
                                 const uint32_t (*sW)[2][AH_TW]) {
     const uint32_t e = e0 + ah_lane();
     if (e >= e1) return;
-    uint64_t m = ((uint64_t)sQ[e][1] << 32) | sQ[e][0];
-    const uint32_t tag = sQ[e][2];
+    uint64_t m[AH_BPL];
+#pragma unroll
+    for (int b = 0; b < AH_BPL; b++) m[b] = ((uint64_t)sQ[e][2 * b + 1] << 32) | sQ[e][2 * b];
+    const uint32_t tag = sQ[e][AH_NW];
     const uint32_t X = tag >> 8, ci = (tag >> 6) & 3u, ln = tag & 63u;
     const TileCtx c = sCtx[ci];
     uint4 p0, p1;
@@ -213,38 +225,42 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
     const uint32_t L = p1.z & 0xFFu, k = (p1.z >> 8) & 0xFFu, shift = p1.z >> 24;
     const uint32_t *Wh = sW[ci][0], *Wl = sW[ci][1];
     // window starts (tile-relative) allowed by the sequence bounds
-    const int32_t lo_ok = -(int32_t)(c.pos0 < 32u ? c.pos0 : 32u);
-    const int64_t room = (int64_t)c.len - (int64_t)c.pos0 - (int64_t)L;
-    const int32_t hi_ok = (int32_t)(room < (1 << 20) ? room : (1 << 20));
-    while (m) {
-        const uint32_t b = (uint32_t)__ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        const int32_t pl = (int32_t)(64 * ln + b) - (int32_t)shift;  // window start, tile-relative
-        if (pl < lo_ok || pl > hi_ok) continue;
-        const uint32_t idx = (uint32_t)(pl + 32);
-        const uint32_t w = idx >> 5, off = idx & 31u;
-        const uint32_t hW = ah_funnel(Wh[w + 1], Wh[w], off);
-        const uint32_t lW = ah_funnel(Wl[w + 1], Wl[w], off);
-        uint32_t nW = 0;
-        if (c.has_n) {
-            const uint64_t gp = c.gbase + (uint64_t)(int64_t)pl;
-            const uint64_t ba = gp >> 6, bb = (gp + L - 1) >> 6;
-            const uint32_t o = (uint32_t)(gp & 63);
-            uint64_t nm = ah_block_nmask(a.st, ba) >> o;
-            if (bb != ba && o) nm |= ah_block_nmask(a.st, bb) << (64 - o);
-            nW = (uint32_t)nm;
-        }
-        const uint32_t lo = (lW & p0.y) | (~lW & p0.x);  // C : A
-        const uint32_t hi = (lW & p0.w) | (~lW & p0.z);  // T : G
-        const uint32_t matched = ((hW & hi) | (~hW & lo)) & ~nW & p1.y;
-        const uint32_t mm = __popc(p1.y & ~matched);
-        if ((matched & p1.x) == p1.x && mm <= k) {
-            const uint64_t h = atomicAdd((unsigned long long *)a.n_hits, 1ull);
-            if (h < a.hit_cap) {
-                uint32_t *r = a.hits + 3 * h;
-                r[0] = c.seq;
-                r[1] = (uint32_t)((int64_t)c.pos0 + pl);
-                r[2] = p1.w | (mm << 24);
+    const int32_t lo_ok = c.lo;
+    const int32_t hi_ok = c.room - (int32_t)L;
+    const int32_t lane0 = (int32_t)(64 * AH_BPL * ln) - (int32_t)shift;
+#pragma unroll
+    for (int hb = 0; hb < AH_BPL; hb++) {
+        uint64_t mm64 = m[hb];
+        while (mm64) {
+            const uint32_t bit = (uint32_t)__ffsll((unsigned long long)mm64) - 1;
+            mm64 &= mm64 - 1;
+            const int32_t pl = lane0 + 64 * hb + (int32_t)bit;  // window start, tile-relative
+            if (pl < lo_ok || pl > hi_ok) continue;
+            const uint32_t idx = (uint32_t)(pl + 32);
+            const uint32_t w = idx >> 5, off = idx & 31u;
+            const uint32_t hW = ah_funnel(Wh[w + 1], Wh[w], off);
+            const uint32_t lW = ah_funnel(Wl[w + 1], Wl[w], off);
+            uint32_t nW = 0;
+            if (c.has_n) {
+                const uint64_t gp = c.gbase + (uint64_t)(int64_t)pl;
+                const uint64_t ba = gp >> 6, bb = (gp + L - 1) >> 6;
+                const uint32_t o = (uint32_t)(gp & 63);
+                uint64_t nm = ah_block_nmask(a.st, ba) >> o;
+                if (bb != ba && o) nm |= ah_block_nmask(a.st, bb) << (64 - o);
+                nW = (uint32_t)nm;
+            }
+            const uint32_t lo = (lW & p0.y) | (~lW & p0.x);  // C : A
+            const uint32_t hi = (lW & p0.w) | (~lW & p0.z);  // T : G
+            const uint32_t matched = ((hW & hi) | (~hW & lo)) & ~nW & p1.y;
+            const uint32_t nmm = __popc(p1.y & ~matched);
+            if ((matched & p1.x) == p1.x && nmm <= k) {
+                const uint64_t h = atomicAdd((unsigned long long *)a.n_hits, 1ull);
+                if (h < a.hit_cap) {
+                    uint32_t *r = a.hits + 3 * h;
+                    r[0] = c.seq;
+                    r[1] = (uint32_t)((int64_t)c.pos0 + pl);
+                    r[2] = p1.w | (nmm << 24);
+                }
             }
         }
     }
@@ -254,7 +270,7 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
 // Entries left over move to the front of the queue.
 template <bool kLdsOnly>
 __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
-                                         uint32_t (*sQ)[3], uint32_t &qn, const uint32_t (*sW)[2][AH_TW],
+                                         uint32_t (*sQ)[AH_QW], uint32_t &qn, const uint32_t (*sW)[2][AH_TW],
                                          bool drain) {
     ah_wave_sync();
     uint32_t e0 = 0;
@@ -265,17 +281,15 @@ __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, ui
     } else if (e0 > 0) {
         const uint32_t rest = qn - e0;  // < 64
         const uint32_t lane = ah_lane();
-        uint32_t v0 = 0, v1 = 0, v2 = 0;
+        uint32_t v[AH_QW];
         if (lane < rest) {
-            v0 = sQ[e0 + lane][0];
-            v1 = sQ[e0 + lane][1];
-            v2 = sQ[e0 + lane][2];
+#pragma unroll
+            for (int j = 0; j < AH_QW; j++) v[j] = sQ[e0 + lane][j];
         }
         ah_wave_sync();
         if (lane < rest) {
-            sQ[lane][0] = v0;
-            sQ[lane][1] = v1;
-            sQ[lane][2] = v2;
+#pragma unroll
+            for (int j = 0; j < AH_QW; j++) sQ[lane][j] = v[j];
         }
         qn = ah_uni(rest);
     }
@@ -287,7 +301,7 @@ __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, ui
 // and verify full rounds of queued candidates.
 template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds, TileCtx *sCtx,
-                                        uint32_t (*sQ)[3], uint32_t (*sW)[2][AH_TW], const TileLoad &L,
+                                        uint32_t (*sQ)[AH_QW], uint32_t (*sW)[2][AH_TW], const TileLoad &L,
                                         const SeqCursor &cur, uint32_t groups, uint32_t &qn, uint32_t &nctx) {
     const uint32_t lane = ah_lane();
     if (nctx == AH_NCTX) {  // every context slot is referenced: verify all
@@ -301,54 +315,67 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
         TileCtx c;
         c.gbase = L.gb0 * 64;
         c.seq = cur.seq;
-        c.len = cur.len;
         c.pos0 = L.rel0 * 64;
+        c.lo = -(int32_t)(c.pos0 < 32u ? c.pos0 : 32u);
+        const uint32_t rest = cur.len - c.pos0;
+        c.room = (int32_t)(rest < (1u << 20) ? rest : (1u << 20));
         c.has_n = has_n;
+        c.pad = 0;
         sCtx[ci] = c;
     }
-    const uint32_t h0 = L.blk.x, l0 = L.blk.y, h1 = L.blk.z, l1 = L.blk.w;
-    uint32_t nh0 = __shfl_down(h0, 1, 64), nl0 = __shfl_down(l0, 1, 64);
-    if (lane == 63) {
-        nh0 = L.hal.x;
-        nl0 = L.hal.y;
+    // base words: [0] previous 32 positions, [1..AH_NW] the lane's, [AH_NW+1] next 32
+    AhBase B;
+#pragma unroll
+    for (int b = 0; b < AH_BPL; b++) {
+        B.h[1 + 2 * b] = L.blk[b].x;
+        B.l[1 + 2 * b] = L.blk[b].y;
+        B.h[2 + 2 * b] = L.blk[b].z;
+        B.l[2 + 2 * b] = L.blk[b].w;
     }
-    AhBase B = {};
+    B.h[AH_NW + 1] = __shfl_down(B.h[1], 1, 64);
+    B.l[AH_NW + 1] = __shfl_down(B.l[1], 1, 64);
+    if (lane == 63) {
+        B.h[AH_NW + 1] = L.hal.x;
+        B.l[AH_NW + 1] = L.hal.y;
+    }
+    B.h[0] = B.l[0] = 0u;
     if (F::kUsesBase) {
         // the previous 32 positions (lane 0: the block before the tile; at a
         // sequence start they are another sequence's or padding, which only
         // windows that verification rejects can see)
-        uint32_t ph1 = __shfl_up(h1, 1, 64), pl1 = __shfl_up(l1, 1, 64);
+        B.h[0] = __shfl_up(B.h[AH_NW], 1, 64);
+        B.l[0] = __shfl_up(B.l[AH_NW], 1, 64);
         if (lane == 0) {
-            ph1 = L.hal.z;
-            pl1 = L.hal.w;
+            B.h[0] = L.hal.z;
+            B.l[0] = L.hal.w;
         }
-        B = AhBase{ph1, h0, h1, nh0, pl1, l0, l1, nl0};
     }
     uint32_t *Wh = sW[ci][0], *Wl = sW[ci][1];
-    Wh[1 + 2 * lane] = h0;
-    Wh[2 + 2 * lane] = h1;
-    Wl[1 + 2 * lane] = l0;
-    Wl[2 + 2 * lane] = l1;
+#pragma unroll
+    for (int w = 0; w < AH_NW; w++) {
+        Wh[1 + AH_NW * lane + w] = B.h[1 + w];
+        Wl[1 + AH_NW * lane + w] = B.l[1 + w];
+    }
     if (lane == 0) {
         Wh[0] = L.hal.z;
         Wl[0] = L.hal.w;
     }
     if (lane == 63) {
-        Wh[AH_TW - 1] = nh0;
-        Wl[AH_TW - 1] = nl0;
+        Wh[AH_TW - 1] = B.h[AH_NW + 1];
+        Wl[AH_TW - 1] = B.l[AH_NW + 1];
     }
-    // Lanes past the sequence end hold a repeated block; their candidates are
+    // Lanes past the sequence end hold repeated blocks; their candidates are
     // windows past the end, which verification rejects, so no lane mask.
-    const uint32_t v = 0xFFFFFFFFu;
-    // bit q of S*[i][w]: plane bit of base q + i (w selects bases 0-31 / 32-63);
-    // only the F::kW offsets the filter reads are formed
-    uint32_t Sh[AH_WMAX][2], Sl[AH_WMAX][2];
+    // bit q of S*[i][w]: plane bit of base 32w + q + i of the lane; only the
+    // F::kW offsets the filter reads are formed
+    uint32_t Sh[AH_WMAX][AH_NW], Sl[AH_WMAX][AH_NW];
 #pragma unroll
     for (int i = 0; i < F::kW; i++) {
-        Sh[i][0] = ah_funnel(h1, h0, i);
-        Sh[i][1] = ah_funnel(nh0, h1, i);
-        Sl[i][0] = ah_funnel(l1, l0, i);
-        Sl[i][1] = ah_funnel(nl0, l1, i);
+#pragma unroll
+        for (int w = 0; w < AH_NW; w++) {
+            Sh[i][w] = ah_funnel(B.h[w + 2], B.h[w + 1], i);
+            Sl[i][w] = ah_funnel(B.l[w + 2], B.l[w + 1], i);
+        }
     }
     for (uint32_t g = 0; g < groups; g++) {
         if (g < 64 && !((cur.gm >> g) & 1ull)) continue;  // group not asked for on this sequence
@@ -359,29 +386,36 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
         if (F::kHoistGuard) {
 #pragma unroll
             for (int i = 0; i < F::kW; i++)
-                asm volatile("" : "+v"(Sh[i][0]), "+v"(Sh[i][1]), "+v"(Sl[i][0]), "+v"(Sl[i][1]));
+#pragma unroll
+                for (int w = 0; w < AH_NW; w++) asm volatile("" : "+v"(Sh[i][w]), "+v"(Sl[i][w]));
+            if (F::kUsesBase) {
+#pragma unroll
+                for (int w = 0; w < AH_NW + 2; w++) asm volatile("" : "+v"(B.h[w]), "+v"(B.l[w]));
+            }
         }
-        if (F::kUsesBase && F::kHoistGuard)
-            asm volatile("" : "+v"(B.ph), "+v"(B.h0), "+v"(B.h1), "+v"(B.nh), "+v"(B.pl), "+v"(B.l0), "+v"(B.l1),
-                         "+v"(B.nl));
-        uint32_t C[8];
-        f.filter(g, B, Sh, Sl, v, v, C);
+        uint32_t C[4 * AH_NW];  // C[AH_NW * x + w]: clamp sites of word w, pattern x
+        f.filter(g, B, Sh, Sl, C);
         if (F::kSkipEmpty) {  // many groups: most have no candidate in a tile
-            const uint32_t any = (C[0] | C[1] | C[2] | C[3]) | (C[4] | C[5] | C[6] | C[7]);
+            uint32_t any = 0;
+#pragma unroll
+            for (int j = 0; j < 4 * AH_NW; j++) any |= C[j];
             if (__ballot(any != 0) == 0) continue;
         }
-        // room for this group's candidates (at most 4 x 64 entries); a
-        // non-draining flush leaves fewer than 64
+        // room for this group's entries (at most 4 x 64); a non-draining
+        // flush leaves fewer than 64
         if (qn > AH_QCAP - 256) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, false);
 #pragma unroll
         for (int x = 0; x < 4; x++) {
-            const bool nz = (C[2 * x] | C[2 * x + 1]) != 0;
+            uint32_t nzw = 0;
+#pragma unroll
+            for (int w = 0; w < AH_NW; w++) nzw |= C[AH_NW * x + w];
+            const bool nz = nzw != 0;
             const uint64_t bal = __ballot(nz);
             if (nz) {
                 const uint32_t slot = qn + ah_mbcnt(bal);
-                sQ[slot][0] = C[2 * x];
-                sQ[slot][1] = C[2 * x + 1];
-                sQ[slot][2] = ((4 * g + (uint32_t)x) << 8) | (ci << 6) | lane;
+#pragma unroll
+                for (int w = 0; w < AH_NW; w++) sQ[slot][w] = C[AH_NW * x + w];
+                sQ[slot][AH_NW] = ((4 * g + (uint32_t)x) << 8) | (ci << 6) | lane;
             }
             qn = ah_uni(qn + (uint32_t)__popcll(bal));  // keeps the queue count in a scalar register
         }
@@ -391,8 +425,8 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
 
 // The kernel body.  Filter F provides
 //   f.groups(a)                         number of pattern groups (primer pairs),
-//   f.filter(g, B, Sh, Sl, v0, v1, C)   candidate words of group g (C[2x], C[2x+1]:
-//                                       clamp sites 0-31 / 32-63 of pattern x); a
+//   f.filter(g, B, Sh, Sl, C)           candidate words of group g (C[AH_NW*x + w]:
+//                                       clamp sites 32w..32w+31 of pattern x); a
 //                                       candidate must pass a necessary condition
 //                                       of a hit; verification decides.
 //   F::kUsesBase                        whether filter reads the base words B,
@@ -403,13 +437,13 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
 // n_lds: pattern records staged in sPat; kLdsOnly: n_lds covers every record.
 template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds,
-                                             TileCtx (*sCtx_all)[AH_NCTX], uint32_t (*sQ_all)[AH_QCAP][3],
+                                             TileCtx (*sCtx_all)[AH_NCTX], uint32_t (*sQ_all)[AH_QCAP][AH_QW],
                                              uint32_t (*sW_all)[AH_NCTX][2][AH_TW]) {
     // the wave index is uniform across the wave; saying so keeps the tile
     // walk, the cursor and the queue bookkeeping in scalar registers
     const uint32_t wv = ah_uni(threadIdx.x >> 6);
     TileCtx *sCtx = sCtx_all[wv];
-    uint32_t(*sQ)[3] = sQ_all[wv];
+    uint32_t(*sQ)[AH_QW] = sQ_all[wv];
     uint32_t(*sW)[2][AH_TW] = sW_all[wv];
     const uint64_t total = ah_uni64(a.tile_pref[a.n_list]);
     // XCD-aware numbering: workgroup i runs on XCD i % 8, so give each XCD a
