@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--len-scale", type=float, default=1.0, help="shrink the workload (testing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-bases", type=float, default=None,
-                    help="oracle sample size (default 1e9 bases for one pair, 3e7 for many)")
+                    help="oracle sample size (default 8e9 bases for one pair, 1e8 for many)")
     ap.add_argument("--stages", default="scan,pair,tm,extract")
     ap.add_argument("--generic", action="store_true", help="use the generic scan kernel (no primer-set JIT)")
     ap.add_argument("--plain-reps", type=int, default=1, help="timed repetitions of the plain per-pair loop (batch)")
@@ -77,17 +77,33 @@ def traffic_from_profiles(kernel_src_hash):
     return d.get("hbm_bytes_per_launch")
 
 
+def cpu_threads():
+    """Host threads for the oracle: the CPUs this process may run on, capped by
+    the OpenMP thread setting (the host's share for one GPU)."""
+    n = len(os.sched_getaffinity(0))
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS") or n))
+    except ValueError:
+        pass
+    return max(1, n)
+
+
 def cpu_baseline(wl, sample, ex, what):
-    if sample is None:
+    """The oracle, unmodified, timed on the leading sequences of the workload
+    (whole chunks of sequences, each run as one call; the time is their sum)."""
+    if not sample:
         return None
     import oracle
-    buf, off, m = sample
-    nt = os.cpu_count() or 1
-    tc = time.perf_counter()
-    o = oracle.run(buf, off, wl.pairs, wl.orient_mask, wl.tm, ex, n_threads=nt)
-    dt = time.perf_counter() - tc
-    sb = int(off[-1])
-    log("oracle sample: %d amplicons in %.1f s" % (len(o.amps), dt))
+    nt = cpu_threads()
+    dt, sb, m, n_amps = 0.0, 0, 0, 0
+    for buf, off in sample:
+        tc = time.perf_counter()
+        o = oracle.run(buf, off, wl.pairs, wl.orient_mask, wl.tm, ex, n_threads=nt)
+        dt += time.perf_counter() - tc
+        sb += int(off[-1])
+        m += len(off) - 1
+        n_amps += len(o.amps)
+    log("oracle sample: %d amplicons in %.1f s" % (n_amps, dt))
     return {"value": round(len(wl.pairs) * sb / dt / 1e9, 4), "unit": what, "cores": nt, "kind": "oracle",
             "sample": "first %d sequences (%.4f Gbases) of the workload, %d pairs, scan+pair+Tm+extract, %.1f s"
                       % (m, sb / 1e9, len(wl.pairs), dt)}
@@ -338,17 +354,20 @@ def main():
     wl = synth.gen_config(args.config, n_seqs=args.n_seqs, len_scale=args.len_scale)
     total = wl.total_bases
     log("workload %s: %d sequences, %.3f Gbases" % (wl.name, wl.n_seqs, total / 1e9))
-    sample = None
-    sample_goal = args.cpu_sample_bases or (1.0e9 if len(wl.pairs) == 1 else 3.0e7)
+    sample = []
+    # about 10 s of oracle work: ~8 Gbases for one pair, less for many
+    sample_goal = args.cpu_sample_bases or (8.0e9 if len(wl.pairs) == 1 else 1.0e8)
+    taken = 0
 
     def chunks():
-        nonlocal sample
+        nonlocal taken
         for first, buf, off in wl.chunks(1 << 30):
-            if sample is None and not args.no_cpu_baseline:
-                # bounded oracle sample: the leading sequences of the first chunk
-                m = int(np.searchsorted(off, sample_goal, side="right"))
+            if taken < sample_goal and not args.no_cpu_baseline:
+                # bounded oracle sample: the leading sequences of the workload
+                m = int(np.searchsorted(off, sample_goal - taken, side="right"))
                 m = max(1, min(m, len(off) - 1))
-                sample = (buf[:int(off[m])].copy(), off[:m + 1].copy(), m)
+                sample.append((buf[:int(off[m])].copy(), off[:m + 1].copy()))
+                taken += int(off[m])
             yield first, buf, off
 
     store = ah.Store(wl.lengths)
