@@ -10,7 +10,8 @@
  *  - Plain C.  `d_` pointers are device memory owned by the caller; `h_`
  *    pointers are host memory.  No entry point allocates device memory except
  *    ah_primers_compile (a one-time set-up call) and none synchronises the
- *    host, so the calls can be captured into a HIP graph.
+ *    host except ah_fasta_ingest (file input, which also allocates its pinned
+ *    host staging buffers), so the others can be captured into a HIP graph.
  *  - `stream` is a hipStream_t (NULL = the null stream); work is enqueued
  *    asynchronously on it.
  *  - Argument errors are returned synchronously and leave outputs untouched.
@@ -38,6 +39,9 @@ typedef int32_t ah_status;
 #define AH_E_LIMIT 3     /* primer length outside 1..32, clamp > length, too many pairs, key too wide */
 #define AH_E_HIP 4       /* a HIP runtime call failed */
 #define AH_E_WORKSPACE 5 /* workspace smaller than the matching *_ws_size() */
+#define AH_E_IO 6        /* a file could not be opened or read */
+#define AH_E_FORMAT 7    /* not FASTA: data before the first header, a record of 2^32 or more bases,
+                            2^32 or more records */
 
 /* Human-readable name of a status code (static string). */
 const char *ah_status_str(ah_status s);
@@ -92,6 +96,26 @@ ah_status ah_pack(const ah_store *st, const uint8_t *d_ascii, const uint64_t *d_
  * If more blocks were flagged than nlist_cap / nmask_cap allow, the count in
  * st->d_counters[0] says so and the pack must be redone with larger caps. */
 ah_status ah_pack_finish(const ah_store *st, const uint64_t *d_nlist, uint64_t nlist_cap, void *stream);
+
+/* One piece of a sequence for ah_pack_pieces. */
+typedef struct {
+    uint64_t src;      /* offset of the piece's first base in d_ascii */
+    uint64_t block;    /* store block that receives that base */
+    uint32_t n;        /* bases in the piece */
+    uint32_t reserved; /* 0 */
+} ah_pack_piece;
+
+/* Pack pieces of sequences whose layout the caller has fixed: piece i's n
+ * bases at d_ascii + src go to blocks [block, block + ceil(n / 64)).  Each
+ * piece starts on a 64-base boundary of its sequence; only the last piece of
+ * a sequence may end inside a block (the rest of that block is stored as A).
+ * Blocks at or past blocks_cap are not written, which is not an error.  N
+ * blocks are flagged in d_nbits and appended to d_nlist as by ah_pack (count
+ * in d_counters[0]); clear d_nbits and d_counters first (ah_pack_begin does).
+ * d_pieces is device memory. */
+ah_status ah_pack_pieces(uint32_t *d_blocks, uint64_t blocks_cap, uint32_t *d_nbits, uint64_t *d_counters,
+                         const uint8_t *d_ascii, const ah_pack_piece *d_pieces, uint32_t n_pieces, uint64_t *d_nlist,
+                         uint64_t nlist_cap, void *stream);
 
 /* Decode bases [start, start + n) of sequence `seq` to ASCII (A/C/G/T/N). */
 ah_status ah_unpack(const ah_store *st, uint32_t seq, uint64_t start, uint64_t n, uint8_t *d_out, void *stream);
@@ -324,6 +348,89 @@ ah_status ah_extract(const ah_store *st, ah_primer_set ps, const ah_amp *d_amps,
                      uint64_t amp_cap, const uint8_t *d_pass, const ah_extract_opts *o, char *d_seq, uint64_t seq_cap,
                      uint64_t *d_seq_off, char *d_fb, char *d_rb, uint8_t *d_bc_len, char *d_fprimer,
                      char *d_rprimer, uint64_t *d_n_bytes, void *d_ws, uint64_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * FASTA ingest (Implementations: AHv2 reads FASTA into 2-bit batches of
+ * headers, lengths and bases; Discussion: headers kept apart from the bases).
+ *
+ * A record is a line starting with '>' and the lines up to the next such line
+ * or the end of its file; records never span files.  Its identifier is the
+ * first white-space-separated word of the header (may be empty), its
+ * sequence the bytes of its other lines with ASCII white space (space, tab,
+ * LF, VT, FF, CR) removed; bytes other than A/C/G/T (either case) become N in
+ * the store.  Only white space may precede a file's first header.
+ *
+ * ah_fasta_ingest reads the files once.  The host keeps each record's
+ * identifier, source file, length and first block (the layout of
+ * ah_pack_layout) and streams the bases through two pinned staging buffers:
+ * while the GPU copies and packs one chunk, the host fills the other.  With
+ * d_blocks == NULL it only builds the record table (no GPU calls; stream and
+ * workspace unused).  The call returns when its GPU work has finished.
+ *
+ * Store arrays (caller-owned device memory, cleared by the call): d_blocks
+ * [blocks_cap][4] u32, d_nbits [ceil(blocks_cap / 32)] u32, d_counters
+ * [AH_STORE_SCRATCH] u64, d_nlist [nlist_cap][2] u64.  Blocks past
+ * blocks_cap and N blocks past nlist_cap are not written; the record table
+ * still counts them (ah_fasta_info's n_blocks, d_counters[0]), so the caller
+ * can run again with larger arrays.  To finish a store: copy the record
+ * table's lengths and first blocks to d_seq_len / d_seq_block0, fill an
+ * ah_store with n_blocks from ah_fasta_info, and call ah_pack_finish.
+ * Errors: AH_E_ARG (null paths, chunk_bytes outside [4096, 2^30]), AH_E_IO,
+ * AH_E_FORMAT, AH_E_WORKSPACE, AH_E_HIP; *out is set only on success.
+ * ---------------------------------------------------------------------- */
+typedef struct ah_fasta ah_fasta;  /* record table (host memory, owned by the library) */
+
+/* Device workspace bytes ah_fasta_ingest needs for staging chunks of chunk_bytes. */
+ah_status ah_fasta_ws_size(uint64_t chunk_bytes, uint64_t *bytes);
+
+ah_status ah_fasta_ingest(const char *const *paths, uint32_t n_files, uint32_t *d_blocks, uint64_t blocks_cap,
+                          uint32_t *d_nbits, uint64_t *d_counters, uint64_t *d_nlist, uint64_t nlist_cap,
+                          uint64_t chunk_bytes, void *d_ws, uint64_t ws_bytes, void *stream, ah_fasta **out);
+
+/* Totals of the record table. */
+ah_status ah_fasta_info(const ah_fasta *f, uint32_t *n_records, uint64_t *n_bases, uint64_t *n_blocks,
+                        uint32_t *max_len);
+
+/* Per-record lengths and first blocks ([n_records] each, host arrays). */
+ah_status ah_fasta_table(const ah_fasta *f, uint32_t *h_len, uint64_t *h_block0);
+
+/* Record identifiers and sources as the FASTA writer takes them; the pointers
+ * stay owned by f and valid until ah_fasta_free. */
+typedef struct {
+    const char *ids;          /* NUL-terminated identifiers, back to back */
+    const uint64_t *id_off;   /* [n_seqs] offset of sequence i's identifier in ids */
+    const uint32_t *seq_file; /* [n_seqs] index of sequence i's source file */
+    const char *const *files; /* [n_files] source file names (path without directories) */
+    uint32_t n_seqs;
+    uint32_t n_files;
+} ah_fasta_names;
+
+ah_status ah_fasta_names_of(const ah_fasta *f, ah_fasta_names *out);
+
+void ah_fasta_free(ah_fasta *f);
+
+/* ------------------------------------------------------------------------
+ * FASTA output (Supplementary, "Headers and outputs"): one record per
+ * amplicon, in amplicon order, skipping those with h_pass[i] == 0 (h_pass may
+ * be NULL: all).  Header fields in the paper's order:
+ *   >ID.source=FILE.coordinates=S-E.Tm=T.orientation=O.fprimer=P.rprimer=Q[.fb=B][.rb=C]
+ * ID and FILE from the names of the amplicon's sequence; S-E the amplicon
+ * (primer sites included, also when trimmed) as 1-based inclusive
+ * coordinates, start + 1 to end; T the Tm with two decimals (correctly
+ * rounded), NA when not finite; O one of FR RF FF RR; P/Q the primer
+ * snippets (NUL-padded [32] rows); .fb/.rb only when fb_len / rb_len > 0,
+ * their text h_bc_len[i][0] / [1] bytes of the [fb_len] / [rb_len] rows.  The
+ * amplicon's bytes follow on one line.  The inputs are the host copies of
+ * ah_extract's outputs (all host memory).  *h_n_bytes = the text's length;
+ * bytes past out_cap are not written.  AH_E_ARG for a sequence index outside
+ * the names, an orientation above 3, barcode lengths above the widths, or
+ * decreasing sequence offsets.
+ * ---------------------------------------------------------------------- */
+ah_status ah_fasta_format(const ah_fasta_names *names, uint32_t fb_len, uint32_t rb_len, const ah_amp *h_amps,
+                          uint64_t n_amps, const double *h_tm, const uint8_t *h_pass, const char *h_seq,
+                          const uint64_t *h_seq_off, const char *h_fb, const char *h_rb, const uint8_t *h_bc_len,
+                          const char *h_fprimer, const char *h_rprimer, char *h_out, uint64_t out_cap,
+                          uint64_t *h_n_bytes);
 
 #ifdef __cplusplus
 }

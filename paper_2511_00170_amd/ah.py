@@ -22,7 +22,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = C.CDLL(LIB_PATH)
 
-AH_OK, AH_E_ARG, AH_E_ALPHABET, AH_E_LIMIT, AH_E_HIP, AH_E_WORKSPACE = 0, 1, 2, 3, 4, 5
+AH_OK, AH_E_ARG, AH_E_ALPHABET, AH_E_LIMIT, AH_E_HIP, AH_E_WORKSPACE, AH_E_IO, AH_E_FORMAT = 0, 1, 2, 3, 4, 5, 6, 7
 AH_STORE_SCRATCH = 2048
 ORIENT_ALL = 0xF
 
@@ -59,6 +59,14 @@ class ah_extract_opts(C.Structure):
     _fields_ = [("trim", U32), ("fb_len", U32), ("rb_len", U32)]
 
 
+class ah_pack_piece(C.Structure):
+    _fields_ = [("src", U64), ("block", U64), ("n", U32), ("reserved", U32)]
+
+
+class ah_fasta_names(C.Structure):
+    _fields_ = [("ids", VP), ("id_off", VP), ("seq_file", VP), ("files", VP), ("n_seqs", U32), ("n_files", U32)]
+
+
 def _sig(name, restype, *args):
     f = getattr(_lib, name)
     f.restype = restype
@@ -74,6 +82,15 @@ _sig("ah_pack_begin", I32, C.POINTER(ah_store), VP)
 _sig("ah_pack", I32, C.POINTER(ah_store), VP, VP, U32, U32, VP, U64, VP)
 _sig("ah_pack_finish", I32, C.POINTER(ah_store), VP, U64, VP)
 _sig("ah_unpack", I32, C.POINTER(ah_store), U32, U64, U64, VP, VP)
+_sig("ah_pack_pieces", I32, VP, U64, VP, VP, VP, VP, U32, VP, U64, VP)
+_sig("ah_fasta_ws_size", I32, U64, C.POINTER(U64))
+_sig("ah_fasta_ingest", I32, C.POINTER(C.c_char_p), U32, VP, U64, VP, VP, VP, U64, U64, VP, U64, VP, C.POINTER(VP))
+_sig("ah_fasta_info", I32, VP, C.POINTER(U32), C.POINTER(U64), C.POINTER(U64), C.POINTER(U32))
+_sig("ah_fasta_table", I32, VP, VP, VP)
+_sig("ah_fasta_names_of", I32, VP, C.POINTER(ah_fasta_names))
+_sig("ah_fasta_free", None, VP)
+_sig("ah_fasta_format", I32, C.POINTER(ah_fasta_names), U32, U32, VP, U64, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP,
+     U64, C.POINTER(U64))
 _sig("ah_primers_compile", I32, C.POINTER(ah_pair_spec), U32, C.POINTER(VP))
 _sig("ah_primers_free", None, VP)
 _sig("ah_primers_compile_into", I32, C.POINTER(ah_pair_spec), U32, VP, U64, VP, C.POINTER(VP))
@@ -99,7 +116,8 @@ EXPORTED = ["ah_status_str", "ah_version", "ah_pack_layout", "ah_pack_begin", "a
             "ah_unpack", "ah_primers_compile", "ah_primers_compile_into", "ah_primers_table_bytes", "ah_primers_free", "ah_primers_count", "ah_primers_jit", "ah_primers_jit_check", "ah_primers_use_jit",
             "ah_primers_launch_shape", "ah_scan_ws_size",
             "ah_scan_primers", "ah_scan_primers_masked", "ah_route_hits", "ah_pair_ws_size", "ah_pair_amplicons", "ah_tm_nn", "ah_tm_duplex",
-            "ah_extract_ws_size", "ah_extract"]
+            "ah_extract_ws_size", "ah_extract", "ah_pack_pieces", "ah_fasta_ws_size", "ah_fasta_ingest",
+            "ah_fasta_info", "ah_fasta_table", "ah_fasta_names_of", "ah_fasta_free", "ah_fasta_format"]
 
 HIT_DTYPE = np.dtype([("seq", "<u4"), ("pos", "<u4"), ("pair", "<u2"), ("kind", "u1"), ("mm", "u1")])
 AMP_DTYPE = np.dtype([("seq", "<u4"), ("start", "<u4"), ("end", "<u4"), ("pair", "<u2"), ("orient", "u1"),
@@ -138,22 +156,33 @@ class Store:
         b0 = np.zeros(max(n, 1), np.uint64)
         nb = U64(0)
         check(_lib.ah_pack_layout(lens.ctypes.data_as(VP), n, b0.ctypes.data_as(VP), C.byref(nb)), "ah_pack_layout")
+        n_blocks = int(nb.value)
+        nw = (n_blocks + 31) // 32
+        blocks = torch.empty((max(n_blocks, 1), 4), dtype=torch.int32, device=dev)
+        nbits = torch.zeros(max(nw, 1), dtype=torch.int32, device=dev)
+        counters = torch.zeros(AH_STORE_SCRATCH, dtype=torch.int64, device=dev)
+        self._bind(lens, b0[:n].copy(), n_blocks, blocks, nbits, counters, nmask_cap, dev)
+
+    def _bind(self, lens, b0, n_blocks, blocks, nbits, counters, nmask_cap, dev):
+        """Per-sequence tables, the N side table and the C struct over the
+        given block, N-bit and counter arrays (which may be larger than
+        needed)."""
+        n = len(lens)
         self.n_seqs = n
-        self.n_blocks = int(nb.value)
-        self.lengths = lens
-        self.seq_block0_host = b0[:n].copy()
-        nw = (self.n_blocks + 31) // 32
-        self.blocks = torch.empty((max(self.n_blocks, 1), 4), dtype=torch.int32, device=dev)
-        self.seq_block0 = torch.from_numpy(b0[:n].astype(np.int64)).to(dev) if n else torch.zeros(1, dtype=torch.int64,
-                                                                                                    device=dev)
-        self.seq_len = torch.from_numpy(lens.astype(np.uint32).view(np.int32)).to(dev) if n else torch.zeros(
-            1, dtype=torch.int32, device=dev)
-        self.nbits = torch.zeros(max(nw, 1), dtype=torch.int32, device=dev)
-        self.nrank = torch.zeros(max(nw, 1), dtype=torch.int32, device=dev)
+        self.n_blocks = int(n_blocks)
+        self.lengths = np.asarray(lens, np.uint64)
+        self.seq_block0_host = np.asarray(b0, np.uint64)
+        self.blocks = blocks
+        self.seq_block0 = torch.from_numpy(self.seq_block0_host.astype(np.int64)).to(dev) if n else torch.zeros(
+            1, dtype=torch.int64, device=dev)
+        self.seq_len = torch.from_numpy(self.lengths.astype(np.uint32).view(np.int32)).to(dev) if n else \
+            torch.zeros(1, dtype=torch.int32, device=dev)
+        self.nbits = nbits
+        self.nrank = torch.zeros(nbits.numel(), dtype=torch.int32, device=dev)
         self.nmask = torch.zeros(max(nmask_cap, 1), dtype=torch.int64, device=dev)
         self.nmask_cap = nmask_cap
-        self.counters = torch.zeros(AH_STORE_SCRATCH, dtype=torch.int64, device=dev)
-        self.c = ah_store(n, int(lens.max()) if n else 0, self.n_blocks, self.blocks.data_ptr(),
+        self.counters = counters
+        self.c = ah_store(n, int(self.lengths.max()) if n else 0, self.n_blocks, self.blocks.data_ptr(),
                           self.seq_block0.data_ptr(), self.seq_len.data_ptr(), self.nbits.data_ptr(),
                           self.nrank.data_ptr(), self.nmask.data_ptr(), nmask_cap, self.counters.data_ptr())
 
@@ -206,12 +235,166 @@ class Store:
             buf = np.zeros(1, np.uint8)
         return st.pack_chunks([(0, buf, off)])
 
+    @classmethod
+    def from_fasta(cls, paths: Sequence[str], chunk_bytes: int = 64 << 20, nmask_cap: int = 1 << 16,
+                   blocks_cap: Optional[int] = None, stream=None):
+        """Read FASTA files into a new store in one pass (ah_fasta_ingest);
+        the record table (identifiers, sources, lengths) is ``store.fasta``.
+        Arrays too small for the files are grown and the files read again."""
+        paths = [os.fspath(p) for p in paths]
+        size = sum(os.path.getsize(p) for p in paths)
+        cap = int(blocks_cap) if blocks_cap is not None else size // 64 + size // 4096 + 64 * len(paths) + 64
+        dev = _dev()
+        ws_n = U64(0)
+        check(_lib.ah_fasta_ws_size(chunk_bytes, C.byref(ws_n)), "ah_fasta_ws_size")
+        ws = torch.empty(int(ws_n.value), dtype=torch.uint8, device=dev)
+        arr = (C.c_char_p * max(1, len(paths)))(*[os.fsencode(p) for p in paths])
+        s = _stream(stream)
+        while True:
+            blocks = torch.empty((max(cap, 1), 4), dtype=torch.int32, device=dev)
+            nbits = torch.empty(max((cap + 31) // 32, 1), dtype=torch.int32, device=dev)
+            counters = torch.empty(AH_STORE_SCRATCH, dtype=torch.int64, device=dev)
+            nlist = torch.empty((max(nmask_cap, 1), 2), dtype=torch.int64, device=dev)
+            h = VP()
+            check(_lib.ah_fasta_ingest(arr, len(paths), _p(blocks), cap, _p(nbits), _p(counters), _p(nlist),
+                                       nmask_cap, chunk_bytes, _p(ws), int(ws_n.value), s, C.byref(h)),
+                  "ah_fasta_ingest")
+            tab = FastaTable(h)
+            n_flag = int(counters[0].item())
+            if tab.n_blocks > cap:
+                cap = tab.n_blocks
+            elif n_flag > nmask_cap:
+                nmask_cap = n_flag
+            else:
+                break
+        del ws
+        lens = tab.lengths.astype(np.uint64)
+        b0 = np.zeros(max(len(lens), 1), np.uint64)
+        nb = U64(0)
+        check(_lib.ah_pack_layout(lens.ctypes.data_as(VP), len(lens), b0.ctypes.data_as(VP), C.byref(nb)),
+              "ah_pack_layout")
+        if int(nb.value) != tab.n_blocks or not np.array_equal(b0[:len(lens)], tab.block0):
+            raise AhError(AH_E_ARG, "ah_fasta_ingest: record layout differs from ah_pack_layout")
+        st = cls.__new__(cls)
+        st._bind(lens, tab.block0, tab.n_blocks, blocks, nbits, counters, nmask_cap, dev)
+        check(_lib.ah_pack_finish(C.byref(st.c), _p(nlist), nmask_cap, s), "ah_pack_finish")
+        torch.cuda.synchronize()
+        st.n_nblocks = n_flag
+        st.fasta = tab
+        return st
+
     def unpack(self, seq: int, start: int = 0, n: Optional[int] = None) -> bytes:
         n = int(self.lengths[seq]) - start if n is None else n
         out = torch.zeros(max(n, 1), dtype=torch.uint8, device=self.blocks.device)
         check(_lib.ah_unpack(C.byref(self.c), seq, start, n, _p(out), _stream()), "ah_unpack")
         torch.cuda.synchronize()
         return out[:n].cpu().numpy().tobytes()
+
+
+# ---------------------------------------------------------------------------
+# FASTA record tables and output
+# ---------------------------------------------------------------------------
+class FastaTable:
+    """Record table of ingested FASTA files (host memory owned by libah.so)."""
+
+    def __init__(self, handle: VP):
+        self._h = handle
+        n, nbase, nblk, ml = U32(0), U64(0), U64(0), U32(0)
+        check(_lib.ah_fasta_info(handle, C.byref(n), C.byref(nbase), C.byref(nblk), C.byref(ml)), "ah_fasta_info")
+        self.n_records, self.n_bases, self.n_blocks, self.max_len = int(n.value), int(nbase.value), \
+            int(nblk.value), int(ml.value)
+        self.lengths = np.zeros(max(self.n_records, 1), np.uint32)
+        self.block0 = np.zeros(max(self.n_records, 1), np.uint64)
+        check(_lib.ah_fasta_table(handle, self.lengths.ctypes.data_as(VP), self.block0.ctypes.data_as(VP)),
+              "ah_fasta_table")
+        self.lengths = self.lengths[:self.n_records]
+        self.block0 = self.block0[:self.n_records]
+        self.names = ah_fasta_names()
+        check(_lib.ah_fasta_names_of(handle, C.byref(self.names)), "ah_fasta_names_of")
+
+    @property
+    def ids(self) -> List[bytes]:
+        nm = self.names
+        if not self.n_records:
+            return []
+        off = np.ctypeslib.as_array(C.cast(nm.id_off, C.POINTER(U64)), (self.n_records,))
+        end = int(off[-1])
+        blob = C.string_at(nm.ids, end + len(C.string_at(nm.ids + end)) + 1)
+        return [blob[o:blob.index(b"\0", o)] for o in off.tolist()]
+
+    @property
+    def seq_file(self) -> np.ndarray:
+        if not self.n_records:
+            return np.zeros(0, np.uint32)
+        return np.ctypeslib.as_array(C.cast(self.names.seq_file, C.POINTER(U32)), (self.n_records,)).copy()
+
+    @property
+    def files(self) -> List[bytes]:
+        arr = C.cast(self.names.files, C.POINTER(C.c_char_p))
+        return [arr[i] for i in range(self.names.n_files)]
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.ah_fasta_free(self._h)
+            self._h = None
+
+
+def fasta_index(paths: Sequence[str]) -> FastaTable:
+    """Record table of FASTA files without reading them into a store (no GPU)."""
+    paths = [os.fspath(p) for p in paths]
+    arr = (C.c_char_p * max(1, len(paths)))(*[os.fsencode(p) for p in paths])
+    h = VP()
+    check(_lib.ah_fasta_ingest(arr, len(paths), None, 0, None, None, None, 0, 0, None, 0, None, C.byref(h)),
+          "ah_fasta_ingest")
+    return FastaTable(h)
+
+
+class FastaNames:
+    """Identifiers and source names of a store's sequences for ah_fasta_format,
+    from Python lists (for stores not read from FASTA files)."""
+
+    def __init__(self, ids: Sequence[bytes], seq_file: Sequence[int], files: Sequence[bytes]):
+        ids = [bytes(x) for x in ids]
+        self._blob = b"".join(x + b"\0" for x in ids) or b"\0"
+        self._id_off = np.zeros(max(len(ids), 1), np.uint64)
+        if ids:
+            self._id_off[1:len(ids)] = np.cumsum([len(x) + 1 for x in ids])[:-1]
+        self._seq_file = np.ascontiguousarray(np.asarray(seq_file, np.uint32).reshape(-1))
+        if len(self._seq_file) == 0:
+            self._seq_file = np.zeros(1, np.uint32)
+        self._files = (C.c_char_p * max(1, len(files)))(*[bytes(f) for f in files])
+        self._blob_buf = C.create_string_buffer(self._blob, len(self._blob))
+        self.names = ah_fasta_names(C.cast(self._blob_buf, VP), self._id_off.ctypes.data, self._seq_file.ctypes.data,
+                                    C.cast(self._files, VP), len(ids), len(files))
+
+
+def format_fasta(names, res: dict, fb_len: int, rb_len: int, tm_filter: bool = True) -> bytes:
+    """AHv2 FASTA text of a run's host results (``Pipeline.results()``):
+    names = a FastaTable or FastaNames; with tm_filter only amplicons that
+    passed the Tm threshold are written."""
+    amps = np.ascontiguousarray(res["amps"])
+    n = len(amps)
+    tm = np.ascontiguousarray(res["tm"], np.float64)
+    pas = np.ascontiguousarray(res["pass"], np.uint8) if tm_filter else None
+    seq = res["seq"]
+    seq_buf = np.frombuffer(seq, np.uint8) if len(seq) else np.zeros(1, np.uint8)
+    so = np.ascontiguousarray(res["seq_off"], np.uint64)
+    fb = np.ascontiguousarray(res["fb"], np.uint8) if fb_len else np.zeros(1, np.uint8)
+    rb = np.ascontiguousarray(res["rb"], np.uint8) if rb_len else np.zeros(1, np.uint8)
+    bc = np.ascontiguousarray(res["bc_len"], np.uint8)
+    fp = np.ascontiguousarray(res["fprimer"], np.uint8)
+    rp = np.ascontiguousarray(res["rprimer"], np.uint8)
+
+    def ptr(a):
+        return a.ctypes.data_as(VP)
+    args = (C.byref(names.names), fb_len, rb_len, ptr(amps) if n else None, n, ptr(tm) if n else None,
+            ptr(pas) if pas is not None and n else None, ptr(seq_buf), ptr(so), ptr(fb), ptr(rb),
+            ptr(bc) if n else None, ptr(fp) if n else None, ptr(rp) if n else None)
+    need = U64(0)
+    check(_lib.ah_fasta_format(*args, None, 0, C.byref(need)), "ah_fasta_format")
+    out = C.create_string_buffer(max(int(need.value), 1))
+    check(_lib.ah_fasta_format(*args, out, int(need.value), C.byref(need)), "ah_fasta_format")
+    return out.raw[:int(need.value)]
 
 
 # ---------------------------------------------------------------------------

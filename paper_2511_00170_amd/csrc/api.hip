@@ -15,6 +15,8 @@ extern "C" const char *ah_status_str(ah_status s) {
     case AH_E_LIMIT: return "size limit exceeded (primer length 1..32, clamp <= length, pairs, key width)";
     case AH_E_HIP: return "HIP runtime error";
     case AH_E_WORKSPACE: return "workspace too small";
+    case AH_E_IO: return "file could not be opened or read";
+    case AH_E_FORMAT: return "not FASTA (data before the first header, record or record count too large)";
     default: return "unknown status";
     }
 }

@@ -18,6 +18,36 @@ __device__ __forceinline__ uint32_t base_code(uint8_t c, bool &is_n) {
     }
 }
 
+// One wavefront packs one block: lane i codes src[i] when i < use (else A),
+// and lane 0 stores the two planes and flags an N block.
+__device__ __forceinline__ void pack_block(const uint8_t *src, uint64_t use, uint64_t gb, uint32_t *blocks,
+                                           uint32_t *nbits, uint64_t *counters, uint64_t *nlist,
+                                           uint64_t nlist_cap) {
+    const uint32_t lane = threadIdx.x & 63;
+    bool is_n = false;
+    uint32_t code = 0;
+    if (lane < use) code = base_code(src[lane], is_n);
+    const uint64_t hi = __ballot(code >> 1);
+    const uint64_t lo = __ballot(code & 1);
+    const uint64_t nm = __ballot(is_n);
+    if (lane == 0) {
+        uint4 w;
+        w.x = (uint32_t)hi;
+        w.y = (uint32_t)lo;
+        w.z = (uint32_t)(hi >> 32);
+        w.w = (uint32_t)(lo >> 32);
+        ((uint4 *)blocks)[gb] = w;
+        if (nm) {
+            atomicOr(&nbits[gb >> 5], 1u << (gb & 31));
+            unsigned long long k = atomicAdd((unsigned long long *)&counters[0], 1ull);
+            if (k < nlist_cap) {
+                nlist[2 * k] = gb;
+                nlist[2 * k + 1] = nm;
+            }
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) ah_pack_kernel(ah_store st, const uint8_t *ascii, const uint64_t *off,
                                                       uint32_t first, uint32_t n, uint64_t *nlist,
                                                       uint64_t nlist_cap) {
@@ -30,34 +60,28 @@ __global__ void __launch_bounds__(256) ah_pack_kernel(ah_store st, const uint8_t
     const uint64_t nblk = (len + 63) / 64;
     const uint64_t b0 = st.d_seq_block0[s];
     const uint8_t *src = ascii + off[si];
-    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t b = wave; b < nblk; b += nwaves)
+        pack_block(src + b * 64, use > b * 64 ? use - b * 64 : 0, b0 + b, st.d_blocks, st.d_nbits, st.d_counters,
+                   nlist, nlist_cap);
+}
+
+// blockIdx.y = piece; the waves of the row stride over its blocks.
+__global__ void __launch_bounds__(256) ah_pack_pieces_kernel(uint32_t *blocks, uint64_t blocks_cap, uint32_t *nbits,
+                                                             uint64_t *counters, const uint8_t *ascii,
+                                                             const ah_pack_piece *pieces, uint32_t n,
+                                                             uint64_t *nlist, uint64_t nlist_cap) {
+    const uint32_t pi = blockIdx.y;
+    if (pi >= n) return;
+    const ah_pack_piece pc = pieces[pi];
+    const uint64_t nblk = ((uint64_t)pc.n + 63) / 64;
     const uint64_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     for (uint64_t b = wave; b < nblk; b += nwaves) {
-        const uint64_t pos = b * 64 + lane;
-        bool is_n = false;
-        uint32_t code = 0;
-        if (pos < use) code = base_code(src[pos], is_n);
-        const uint64_t hi = __ballot(code >> 1);
-        const uint64_t lo = __ballot(code & 1);
-        const uint64_t nm = __ballot(is_n);
-        if (lane == 0) {
-            uint4 w;
-            w.x = (uint32_t)hi;
-            w.y = (uint32_t)lo;
-            w.z = (uint32_t)(hi >> 32);
-            w.w = (uint32_t)(lo >> 32);
-            ((uint4 *)st.d_blocks)[b0 + b] = w;
-            if (nm) {
-                const uint64_t gb = b0 + b;
-                atomicOr(&st.d_nbits[gb >> 5], 1u << (gb & 31));
-                unsigned long long k = atomicAdd((unsigned long long *)&st.d_counters[0], 1ull);
-                if (k < nlist_cap) {
-                    nlist[2 * k] = gb;
-                    nlist[2 * k + 1] = nm;
-                }
-            }
-        }
+        const uint64_t gb = pc.block + b;
+        if (gb >= blocks_cap) break;  // wave-uniform
+        pack_block(ascii + pc.src + b * 64, (uint64_t)pc.n - b * 64, gb, blocks, nbits, counters, nlist, nlist_cap);
     }
 }
 
@@ -107,6 +131,22 @@ extern "C" ah_status ah_pack(const ah_store *st, const uint8_t *d_ascii, const u
         uint32_t cn = n - c0 < 65535 ? n - c0 : 65535;
         hipLaunchKernelGGL(ah_pack_kernel, dim3(64, cn), dim3(256), 0, s, *st, d_ascii, d_ascii_off + c0,
                            first_seq + c0, cn, d_nlist, nlist_cap);
+    }
+    return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
+}
+
+extern "C" ah_status ah_pack_pieces(uint32_t *d_blocks, uint64_t blocks_cap, uint32_t *d_nbits, uint64_t *d_counters,
+                                    const uint8_t *d_ascii, const ah_pack_piece *d_pieces, uint32_t n_pieces,
+                                    uint64_t *d_nlist, uint64_t nlist_cap, void *stream) {
+    if (!n_pieces) return AH_OK;
+    if (!d_blocks || !d_nbits || !d_counters || !d_ascii || !d_pieces || (nlist_cap && !d_nlist)) return AH_E_ARG;
+    hipStream_t s = ah_stream(stream);
+    // workgroups per piece: many pieces in one chunk are short ones
+    const uint32_t gx = n_pieces <= 256 ? 64 : (n_pieces <= 4096 ? 16 : 4);
+    for (uint32_t c0 = 0; c0 < n_pieces; c0 += 65535) {
+        const uint32_t cn = n_pieces - c0 < 65535 ? n_pieces - c0 : 65535;
+        hipLaunchKernelGGL(ah_pack_pieces_kernel, dim3(gx, cn), dim3(256), 0, s, d_blocks, blocks_cap, d_nbits,
+                           d_counters, d_ascii, d_pieces + c0, cn, d_nlist, nlist_cap);
     }
     return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
 }
