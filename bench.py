@@ -32,6 +32,8 @@ def parse():
     ap.add_argument("--n-seqs", type=int, default=None, help="shrink the workload (testing)")
     ap.add_argument("--len-scale", type=float, default=1.0, help="shrink the workload (testing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fasta-gbases", type=float, default=2.0,
+                    help="size of the FASTA file the I/O extra writes and reads back, Gbases")
     ap.add_argument("--cpu-sample-bases", type=float, default=None,
                     help="oracle sample size (default 8e9 bases for one pair, 1e8 for many)")
     ap.add_argument("--stages", default="scan,pair,tm,extract")
@@ -107,6 +109,81 @@ def cpu_baseline(wl, sample, ex, what):
     return {"value": round(len(wl.pairs) * sb / dt / 1e9, 4), "unit": what, "cores": nt, "kind": "oracle",
             "sample": "first %d sequences (%.4f Gbases) of the workload, %d pairs, scan+pair+Tm+extract, %.1f s"
                       % (m, sb / 1e9, len(wl.pairs), dt)}
+
+
+def _fasta_lines(s, width=80):
+    """One sequence's FASTA lines (width bases each)."""
+    import numpy as np
+    full = len(s) // width
+    body = np.empty((full, width + 1), np.uint8)
+    body[:, :width] = s[:full * width].reshape(full, width)
+    body[:, width] = 10
+    tail = s[full * width:]
+    return body.tobytes() + (tail.tobytes() + b"\n" if len(tail) else b"")
+
+
+def extra_fasta(wl, store, res, ex, gbases):
+    """FASTA I/O: the leading ~gbases of the workload written as a FASTA file
+    (80 bases a line), read into a new store by ah_fasta_ingest (one pass,
+    pinned double-buffered chunks) and by the record-table pass alone (host
+    parse, no GPU); the new store must equal the resident one block for
+    block.  The AHv2 writer is timed on the run's amplicons."""
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    from paper_2511_00170_amd import ah
+    d = tempfile.mkdtemp(prefix="ah_fasta_")
+    path = os.path.join(d, "genomes.fa")
+    goal, n_bases, n_seqs = gbases * 1e9, 0, 0
+    try:
+        with open(path, "wb") as fh:
+            for first, buf, off in wl.chunks(1 << 30):
+                for i in range(len(off) - 1):
+                    if n_bases >= goal:
+                        break
+                    fh.write(b">seq%d source genome\n" % (first + i))
+                    fh.write(_fasta_lines(buf[int(off[i]):int(off[i + 1])]))
+                    n_bases += int(off[i + 1] - off[i])
+                    n_seqs += 1
+                if n_bases >= goal:
+                    break
+        fbytes = os.path.getsize(path)
+        t0 = time.perf_counter()
+        tab = ah.fasta_index([path])
+        t_index = time.perf_counter() - t0
+        del tab
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ah.Store.from_fasta([path])
+        torch.cuda.synchronize()
+        t_ingest = time.perf_counter() - t0
+        nb = st.n_blocks
+        same = st.n_seqs == n_seqs and torch.equal(st.blocks[:nb], store.blocks[:nb])
+        nw = nb // 32
+        same = same and torch.equal(st.nbits[:nw], store.nbits[:nw])
+        same = same and torch.equal(st.nmask[:st.n_nblocks], store.nmask[:st.n_nblocks])
+        del st
+    finally:
+        if os.path.exists(path):
+            os.remove(path)
+        os.rmdir(d)
+    names = ah.FastaNames([b"seq%d" % i for i in range(store.n_seqs)], np.zeros(store.n_seqs, np.uint32),
+                          [b"genomes.fa"])
+    t0 = time.perf_counter()
+    text = ah.format_fasta(names, res, ex.fb_len, ex.rb_len, tm_filter=wl.tm.filter)
+    t_write = time.perf_counter() - t0
+    out = {"fasta_bytes": fbytes, "sequences": n_seqs, "bases": n_bases,
+           "ingest_s": round(t_ingest, 3), "ingest_GB_s": round(fbytes / t_ingest / 1e9, 3),
+           "ingest_Gbases_s": round(n_bases / t_ingest / 1e9, 3),
+           "host_parse_only_GB_s": round(fbytes / t_index / 1e9, 3),
+           "store_identical_to_resident": bool(same),
+           "writer_records": text.count(b"\n>") + (1 if text else 0), "writer_MB": round(len(text) / 1e6, 2),
+           "writer_MB_s": round(len(text) / max(t_write, 1e-9) / 1e6, 1),
+           "note": "file in the page cache (just written): host parse + H2D + pack, not disk reads"}
+    log("fasta io: %s" % json.dumps(out))
+    return out
 
 
 def bench_batch(args, wl, store, sample):
@@ -443,6 +520,7 @@ def main():
         "cpu_baseline": cpu,
     }
     if not args.no_extras:
+        out["fasta_io"] = extra_fasta(wl, store, pipe.results(), ex, args.fasta_gbases)
         # the other two parts of the metric, on their own workloads
         del pipe, ps
         store = None

@@ -182,3 +182,15 @@ def test_writer_rejects_bad_records():
     res["amps"]["orient"][2] = 4
     with pytest.raises(ah.AhError):
         ah.format_fasta(names, res, 0, 0)
+
+
+def test_cli_flags(tmp_path):
+    from paper_2511_00170_amd import cli
+    lst = tmp_path / "inputs.txt"
+    lst.write_text("a.fa\n\nb.fa\n")
+    a = cli.parse_args(["--input", "x.fa", "--input-list", str(lst), "--forward", "ACGT", "--reverse", "TTGG",
+                        "--include-offtarget", "--trim-primers", "--fb-len", "4"])
+    assert a.input == ["x.fa", "a.fa", "b.fa"] and a.include_offtarget and a.trim_primers and a.fb_len == 4
+    assert a.tm_threshold is None and a.mismatches == 0
+    with pytest.raises(SystemExit):
+        cli.parse_args(["--forward", "ACGT", "--reverse", "TTGG"])

@@ -122,3 +122,29 @@ def test_fasta_in_fasta_out_matches_oracle(ah, tmp_path, ex):
                            o.tm.passed if wl.tm.filter else None, o.ext, ex.fb_len, ex.rb_len)
     assert len(o.amps) > 0 and want.count(b">") > 0
     assert got == want
+
+
+def test_cli_writes_the_oracle_fasta(ah, tmp_path):
+    from paper_2511_00170_amd import cli
+    wl = synth.gen_config(1, n_seqs=40)
+    buf, off = wl.concat()
+    recs = [(b"s%d" % i, b"", bytes(buf[int(off[i]):int(off[i + 1])])) for i in range(wl.n_seqs)]
+    p = str(tmp_path / "genomes.fa")
+    of.write_fasta(p, recs, width=60)
+    q = wl.pairs[0]
+    out = str(tmp_path / "amplicons.fa")
+    _say("cli")
+    rc = cli.main(["--input", p, "--forward", q.fwd, "--reverse", q.rev, "--mismatches", str(q.k), "--clamp",
+                   str(q.clamp), "--min-length", str(q.min_len), "--max-length", str(q.max_len),
+                   "--include-offtarget", "--trim-primers", "--fb-len", "6", "--rb-len", "6", "--tm-threshold",
+                   "50", "--output", out, "--chunk-mb", "1", "--quiet"])
+    assert rc == 0
+    tm = synth.TmSpec(threshold_C=50.0, filter=True)
+    ex = synth.ExtractSpec(trim=True, fb_len=6, rb_len=6)
+    orecs = of.read_fasta([p])
+    obuf, ooff = of.concat(orecs)
+    o = oracle.run(obuf, ooff, [q], 0b1111, tm, ex)
+    want = of.format_fasta([r for r, _, _ in orecs], [b"genomes.fa"] * len(orecs), o.amps, o.tm.tm, o.tm.passed,
+                           o.ext, 6, 6)
+    assert int(o.tm.passed.sum()) > 0
+    assert open(out, "rb").read() == want
