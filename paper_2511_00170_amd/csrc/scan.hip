@@ -87,10 +87,12 @@ __global__ void __launch_bounds__(256) ah_scan_kernel(ScanArgs a) {
     __shared__ TileCtx sCtx[4][AH_NCTX];
     __shared__ uint32_t sQ[4][AH_QCAP][AH_QW];
     __shared__ uint32_t sW[4][AH_NCTX][2][AH_TW];
+    __shared__ uint32_t sH[4][AH_HCAP][3];
+    __shared__ uint32_t sHn[4];
     ah_stage_patterns(a, sPat, AH_LDS_PATS);
     const uint32_t n_lds = a.n_pats < AH_LDS_PATS ? a.n_pats : AH_LDS_PATS;
     GenericFilter f{sPat, a.pats, n_lds};
-    ah_scan_body<kLdsOnly>(a, f, sPat, n_lds, sCtx, sQ, sW);
+    ah_scan_body<kLdsOnly>(a, f, sPat, n_lds, sCtx, sQ, sW, sH, sHn);
 }
 
 // ---------------------------------------------------------------- tile table
@@ -278,9 +280,11 @@ static std::string jit_source(const ah_primer_set_ *ps) {
          "  __shared__ TileCtx sCtx[4][AH_NCTX];\n"
          "  __shared__ uint32_t sQ[4][AH_QCAP][AH_QW];\n"
          "  __shared__ uint32_t sW[4][AH_NCTX][2][AH_TW];\n"
+         "  __shared__ uint32_t sH[4][AH_HCAP][3];\n"
+         "  __shared__ uint32_t sHn[4];\n"
          "  ah_stage_patterns(a, sPat, AH_JIT_LDS_PATS);\n"
          "  JitFilter f;\n"
-         "  ah_scan_body<AH_JIT_LDS_ONLY>(a, f, sPat, AH_JIT_LDS_PATS, sCtx, sQ, sW);\n"
+         "  ah_scan_body<AH_JIT_LDS_ONLY>(a, f, sPat, AH_JIT_LDS_PATS, sCtx, sQ, sW, sH, sHn);\n"
          "}\n";
     return s;
 }

@@ -15,8 +15,11 @@
 // appends (mask, pattern, lane, tile) to a per-wave LDS queue -- one ballot
 // per pattern gives the slots, no prefix sums.  The queue spans several
 // tiles and is verified in full-wave rounds against the tiles' words kept in
-// LDS: the full clamp, N bases and the substitution count.  Hits are rare
-// and appended with one atomic each.
+// LDS: the full clamp, N bases and the substitution count.  Hits go to a
+// small per-wave LDS buffer (an LDS atomic each) that is written out with
+// one device atomic per batch: a device atomic whose result is needed waits
+// for every earlier vector memory operation of the wave, including the next
+// tile's prefetch, so one per hit would stall hit-dense scans.
 #pragma once
 
 #include "ah_dev.h"
@@ -91,6 +94,9 @@ struct TileCtx {
 #endif
 #ifndef AH_NCTX
 #define AH_NCTX 2                         // tiles whose candidates may wait in the queue (<= 4)
+#endif
+#ifndef AH_HCAP
+#define AH_HCAP 48                        // hits buffered per wave (LDS) before one atomic reserves their room
 #endif
 #define AH_TW (2 * AH_TILE_BLOCKS + 2)    // words per plane of a tile (+ one word each side)
 #define AH_QW (AH_NW + 1)                 // queue entry: the lane's candidate words + tag
@@ -186,6 +192,37 @@ __device__ __forceinline__ void tile_issue(const ScanArgs &a, const SeqCursor &c
     L.nbw = *(const uint32_t *)((uint64_t)a.st.d_nbits + 4u * (uint64_t)wb + 4u * wi);
 }
 
+// A wave's hit buffer in LDS: records and the count of hits accepted since
+// the last write-out (those past AH_HCAP went to global memory directly).
+struct HitBuf {
+    uint32_t (*rec)[3];
+    uint32_t *n;
+};
+
+// Append the buffered records to the hit array: one atomic reserves their
+// room, the lanes copy them (consecutive records, coalesced).  Wave-wide.
+__device__ __forceinline__ void ah_hits_out(const ScanArgs &a, const HitBuf &hb) {
+    ah_wave_sync();
+    const uint32_t cnt = ah_uni(*hb.n);
+    const uint32_t n = cnt < AH_HCAP ? cnt : AH_HCAP;
+    if (n) {
+        uint64_t base = 0;
+        if (ah_lane() == 0) base = atomicAdd((unsigned long long *)a.n_hits, (unsigned long long)n);
+        base = ah_uni64(base);
+        for (uint32_t i = ah_lane(); i < n; i += 64) {
+            if (base + i < a.hit_cap) {
+                uint32_t *r = a.hits + 3 * (base + i);
+                r[0] = hb.rec[i][0];
+                r[1] = hb.rec[i][1];
+                r[2] = hb.rec[i][2];
+            }
+        }
+        ah_wave_sync();
+        if (ah_lane() == 0) *hb.n = 0u;
+        ah_wave_sync();
+    }
+}
+
 // Any N in the tile's blocks or its halo blocks (wave-uniform, conservative).
 __device__ __forceinline__ bool tile_has_n(const TileLoad &L) { return __ballot(L.nbw != 0) != 0; }
 
@@ -211,7 +248,7 @@ __device__ __forceinline__ void ah_pattern_record(const ScanArgs &a, const DPat 
 template <bool kLdsOnly>
 __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
                                 const uint32_t (*sQ)[AH_QW], uint32_t e0, uint32_t e1,
-                                const uint32_t (*sW)[2][AH_TW]) {
+                                const uint32_t (*sW)[2][AH_TW], const HitBuf &hb) {
     const uint32_t e = e0 + ah_lane();
     if (e >= e1) return;
     uint64_t m[AH_BPL];
@@ -229,12 +266,12 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
     const int32_t hi_ok = c.room - (int32_t)L;
     const int32_t lane0 = (int32_t)(64 * AH_BPL * ln) - (int32_t)shift;
 #pragma unroll
-    for (int hb = 0; hb < AH_BPL; hb++) {
-        uint64_t mm64 = m[hb];
+    for (int bk = 0; bk < AH_BPL; bk++) {
+        uint64_t mm64 = m[bk];
         while (mm64) {
             const uint32_t bit = (uint32_t)__ffsll((unsigned long long)mm64) - 1;
             mm64 &= mm64 - 1;
-            const int32_t pl = lane0 + 64 * hb + (int32_t)bit;  // window start, tile-relative
+            const int32_t pl = lane0 + 64 * bk + (int32_t)bit;  // window start, tile-relative
             if (pl < lo_ok || pl > hi_ok) continue;
             const uint32_t idx = (uint32_t)(pl + 32);
             const uint32_t w = idx >> 5, off = idx & 31u;
@@ -254,12 +291,20 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
             const uint32_t matched = ((hW & hi) | (~hW & lo)) & ~nW & p1.y;
             const uint32_t nmm = __popc(p1.y & ~matched);
             if ((matched & p1.x) == p1.x && nmm <= k) {
-                const uint64_t h = atomicAdd((unsigned long long *)a.n_hits, 1ull);
-                if (h < a.hit_cap) {
-                    uint32_t *r = a.hits + 3 * h;
-                    r[0] = c.seq;
-                    r[1] = (uint32_t)((int64_t)c.pos0 + pl);
-                    r[2] = p1.w | (nmm << 24);
+                const uint32_t pos = (uint32_t)((int64_t)c.pos0 + pl), w2 = p1.w | (nmm << 24);
+                const uint32_t slot = atomicAdd(hb.n, 1u);  // LDS
+                if (slot < AH_HCAP) {
+                    hb.rec[slot][0] = c.seq;
+                    hb.rec[slot][1] = pos;
+                    hb.rec[slot][2] = w2;
+                } else {  // buffer full: straight to the hit array
+                    const uint64_t h = atomicAdd((unsigned long long *)a.n_hits, 1ull);
+                    if (h < a.hit_cap) {
+                        uint32_t *r = a.hits + 3 * h;
+                        r[0] = c.seq;
+                        r[1] = pos;
+                        r[2] = w2;
+                    }
                 }
             }
         }
@@ -271,12 +316,12 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
 template <bool kLdsOnly>
 __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
                                          uint32_t (*sQ)[AH_QW], uint32_t &qn, const uint32_t (*sW)[2][AH_TW],
-                                         bool drain) {
+                                         const HitBuf &hb, bool drain) {
     ah_wave_sync();
     uint32_t e0 = 0;
-    for (; e0 + 64 <= qn; e0 += 64) ah_verify_round<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, e0, e0 + 64, sW);
+    for (; e0 + 64 <= qn; e0 += 64) ah_verify_round<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, e0, e0 + 64, sW, hb);
     if (drain) {
-        if (e0 < qn) ah_verify_round<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, e0, qn, sW);
+        if (e0 < qn) ah_verify_round<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, e0, qn, sW, hb);
         qn = 0u;
     } else if (e0 > 0) {
         const uint32_t rest = qn - e0;  // < 64
@@ -294,6 +339,8 @@ __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, ui
         qn = ah_uni(rest);
     }
     ah_wave_sync();
+    // half full: write out, so the next flush's hits fit
+    if (ah_uni(*hb.n) >= AH_HCAP / 2) ah_hits_out(a, hb);
 }
 
 // One tile, its blocks already loaded into L: record its context and words
@@ -301,11 +348,12 @@ __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, ui
 // and verify full rounds of queued candidates.
 template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds, TileCtx *sCtx,
-                                        uint32_t (*sQ)[AH_QW], uint32_t (*sW)[2][AH_TW], const TileLoad &L,
-                                        const SeqCursor &cur, uint32_t groups, uint32_t &qn, uint32_t &nctx) {
+                                        uint32_t (*sQ)[AH_QW], uint32_t (*sW)[2][AH_TW], const HitBuf &hb,
+                                        const TileLoad &L, const SeqCursor &cur, uint32_t groups, uint32_t &qn,
+                                        uint32_t &nctx) {
     const uint32_t lane = ah_lane();
     if (nctx == AH_NCTX) {  // every context slot is referenced: verify all
-        ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, true);
+        ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, hb, true);
         nctx = 0;
     }
     const uint32_t ci = nctx;
@@ -403,7 +451,7 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
         }
         // room for this group's entries (at most 4 x 64); a non-draining
         // flush leaves fewer than 64
-        if (qn > AH_QCAP - 256) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, false);
+        if (qn > AH_QCAP - 256) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, hb, false);
 #pragma unroll
         for (int x = 0; x < 4; x++) {
             uint32_t nzw = 0;
@@ -420,7 +468,7 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
             qn = ah_uni(qn + (uint32_t)__popcll(bal));  // keeps the queue count in a scalar register
         }
     }
-    if (qn >= 64) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, false);
+    if (qn >= 64) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, hb, false);
 }
 
 // The kernel body.  Filter F provides
@@ -438,13 +486,17 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
 template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds,
                                              TileCtx (*sCtx_all)[AH_NCTX], uint32_t (*sQ_all)[AH_QCAP][AH_QW],
-                                             uint32_t (*sW_all)[AH_NCTX][2][AH_TW]) {
+                                             uint32_t (*sW_all)[AH_NCTX][2][AH_TW],
+                                             uint32_t (*sH_all)[AH_HCAP][3], uint32_t *sHn_all) {
     // the wave index is uniform across the wave; saying so keeps the tile
     // walk, the cursor and the queue bookkeeping in scalar registers
     const uint32_t wv = ah_uni(threadIdx.x >> 6);
     TileCtx *sCtx = sCtx_all[wv];
     uint32_t(*sQ)[AH_QW] = sQ_all[wv];
     uint32_t(*sW)[2][AH_TW] = sW_all[wv];
+    const HitBuf hb{sH_all[wv], sHn_all + wv};
+    if (ah_lane() == 0) *hb.n = 0u;
+    ah_wave_sync();
     const uint64_t total = ah_uni64(a.tile_pref[a.n_list]);
     // XCD-aware numbering: workgroup i runs on XCD i % 8, so give each XCD a
     // contiguous share of the tiles.
@@ -470,18 +522,19 @@ __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat
         SeqCursor nc = cur;
         nc.advance(a, tn);
         tile_issue(a, nc, tn, B);
-        ah_tile<kLdsOnly>(a, f, sPat, n_lds, sCtx, sQ, sW, A, cur, groups, qn, nctx);
+        ah_tile<kLdsOnly>(a, f, sPat, n_lds, sCtx, sQ, sW, hb, A, cur, groups, qn, nctx);
         cur = nc;
         if (++t >= tend) break;
         tn = t + 1 < tend ? t + 1 : t;
         nc = cur;
         nc.advance(a, tn);
         tile_issue(a, nc, tn, A);
-        ah_tile<kLdsOnly>(a, f, sPat, n_lds, sCtx, sQ, sW, B, cur, groups, qn, nctx);
+        ah_tile<kLdsOnly>(a, f, sPat, n_lds, sCtx, sQ, sW, hb, B, cur, groups, qn, nctx);
         cur = nc;
         if (++t >= tend) break;
     }
-    if (qn) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, true);
+    if (qn) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, hb, true);
+    ah_hits_out(a, hb);
 }
 
 // Stage the first n pattern records in LDS (all threads of the block).

@@ -351,6 +351,24 @@ def _segment_plants(rng, length: int, n_copies: int, pair_choices) -> list:
     return plants
 
 
+# Sweeps shaped like the paper's (Results, "Primer degeneracy and mismatch
+# tolerance"): N bases added two at a time, one per primer, at the 5' ends
+# (the 3' clamp is untouched); and the substitutions allowed, 0 to 6.
+SWEEP_N = (0, 2, 4, 6)
+SWEEP_K = (0, 1, 2, 3, 4, 5, 6)
+
+
+def sweep_pairs(base: PairSpec, kind: str) -> List[tuple]:
+    """(x, PairSpec) for each point of a sweep: kind "degeneracy" (x = N bases
+    added over both primers) or "mismatch" (x = k)."""
+    if kind == "degeneracy":
+        return [(n, dataclasses.replace(base, fwd="N" * (n // 2) + base.fwd, rev="N" * (n // 2) + base.rev))
+                for n in SWEEP_N]
+    if kind == "mismatch":
+        return [(k, dataclasses.replace(base, k=k)) for k in SWEEP_K]
+    raise ValueError(kind)
+
+
 def gen_config(cfg: int, n_seqs: Optional[int] = None, len_scale: float = 1.0) -> Workload:
     """Build workload ``cfg`` (1..5).  ``n_seqs``/``len_scale`` shrink it for
     tests (same recipe, fewer/shorter sequences)."""

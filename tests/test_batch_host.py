@@ -66,3 +66,15 @@ def test_merge_results_orders_by_sequence_then_pair():
     got = [(int(x["seq"]), int(x["pair"]), int(x["start"])) for x in m["amps"]]
     assert got == [(0, 0, 5), (0, 0, 50), (0, 1, 1), (1, 1, 7), (2, 0, 1)]
     assert list(m["tm"]) == [0.0, 1.0, 0.0, 1.0, 2.0]
+
+
+def test_sweep_pair_constructions():
+    from paper_2511_00170_amd import synth
+    base = synth.PairSpec("ACGTRYACGT", "TTGGCCAANN", k=3, clamp=4, min_len=100, max_len=900)
+    deg = synth.sweep_pairs(base, "degeneracy")
+    assert [n for n, _ in deg] == [0, 2, 4, 6]
+    for n, p in deg:
+        assert p.fwd == "N" * (n // 2) + base.fwd and p.rev == "N" * (n // 2) + base.rev
+        assert p.fwd.endswith(base.fwd) and (p.k, p.clamp, p.min_len, p.max_len) == (3, 4, 100, 900)
+    mm = synth.sweep_pairs(base, "mismatch")
+    assert [k for k, _ in mm] == list(range(7)) and all(p.k == k and p.fwd == base.fwd for k, p in mm)
