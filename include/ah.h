@@ -164,12 +164,24 @@ uint64_t ah_primers_table_bytes(uint32_t n_pairs);
  * AH_E_HIP if hipRTC or module loading fails (the generic kernel stays). */
 ah_status ah_primers_jit(ah_primer_set ps);
 
-/* Generate and compile (without loading) the specialised scan kernel of the
- * primer pairs h_pairs[n_pairs] for the GPU architecture `arch` (e.g.
- * "gfx950"); touches no device.  AH_OK when it compiles; the primer errors
- * of ah_primers_compile; AH_E_HIP when hipRTC fails (its log goes to
- * stderr).  For build checks on machines without a GPU. */
-ah_status ah_primers_jit_check(const ah_pair_spec *h_pairs, uint32_t n_pairs, const char *arch);
+/* Select the specialised kernel variant with blocks_per_lane 64-base blocks
+ * per lane (1 or 2: a wave's tile, the positions one wave scans per step, is
+ * 4096 x blocks_per_lane bases) and an LDS buffer of hit_buffer hit records
+ * per wave (2..256), compiling it on first use (variants stay cached with
+ * the set).  Every variant finds the same hits; registers, LDS and hence
+ * occupancy and speed differ -- the batch autotuner times them.
+ * ah_primers_jit selects (1, 48) unless a variant is already selected.
+ * Errors: AH_E_ARG (null set, values out of range), AH_E_HIP. */
+ah_status ah_primers_jit_variant(ah_primer_set ps, uint32_t blocks_per_lane, uint32_t hit_buffer);
+
+/* Generate and compile (without loading) the specialised scan kernel variant
+ * (blocks_per_lane, hit_buffer as in ah_primers_jit_variant) of the primer
+ * pairs h_pairs[n_pairs] for the GPU architecture `arch` (e.g. "gfx950");
+ * touches no device.  AH_OK when it compiles; AH_E_ARG for a bad variant;
+ * the primer errors of ah_primers_compile; AH_E_HIP when hipRTC fails (its
+ * log goes to stderr).  For build checks on machines without a GPU. */
+ah_status ah_primers_jit_check(const ah_pair_spec *h_pairs, uint32_t n_pairs, const char *arch,
+                               uint32_t blocks_per_lane, uint32_t hit_buffer);
 
 /* Switch between the specialised (on != 0, needs ah_primers_jit first) and
  * the generic scan kernel for this set. */

@@ -97,7 +97,8 @@ _sig("ah_primers_compile_into", I32, C.POINTER(ah_pair_spec), U32, VP, U64, VP, 
 _sig("ah_primers_table_bytes", U64, U32)
 _sig("ah_primers_count", U32, VP)
 _sig("ah_primers_jit", I32, VP)
-_sig("ah_primers_jit_check", I32, C.POINTER(ah_pair_spec), U32, C.c_char_p)
+_sig("ah_primers_jit_check", I32, C.POINTER(ah_pair_spec), U32, C.c_char_p, U32, U32)
+_sig("ah_primers_jit_variant", I32, VP, U32, U32)
 _sig("ah_primers_use_jit", I32, VP, I32)
 _sig("ah_primers_launch_shape", I32, VP, I32, C.POINTER(I32))
 _sig("ah_scan_ws_size", I32, C.POINTER(ah_store), U32, C.POINTER(U64))
@@ -113,7 +114,7 @@ _sig("ah_extract", I32, C.POINTER(ah_store), VP, VP, VP, U64, VP, C.POINTER(ah_e
      VP, VP, VP, VP, VP, U64, VP)
 
 EXPORTED = ["ah_status_str", "ah_version", "ah_pack_layout", "ah_pack_begin", "ah_pack", "ah_pack_finish",
-            "ah_unpack", "ah_primers_compile", "ah_primers_compile_into", "ah_primers_table_bytes", "ah_primers_free", "ah_primers_count", "ah_primers_jit", "ah_primers_jit_check", "ah_primers_use_jit",
+            "ah_unpack", "ah_primers_compile", "ah_primers_compile_into", "ah_primers_table_bytes", "ah_primers_free", "ah_primers_count", "ah_primers_jit", "ah_primers_jit_check", "ah_primers_jit_variant", "ah_primers_use_jit",
             "ah_primers_launch_shape", "ah_scan_ws_size",
             "ah_scan_primers", "ah_scan_primers_masked", "ah_route_hits", "ah_pair_ws_size", "ah_pair_amplicons", "ah_tm_nn", "ah_tm_duplex",
             "ah_extract_ws_size", "ah_extract", "ah_pack_pieces", "ah_fasta_ws_size", "ah_fasta_ingest",
@@ -424,12 +425,23 @@ class PrimerSet:
         self.h = h
         self.jit = False       # specialised kernel selected
         self.has_jit = False   # specialised kernel compiled
+        self.variant = None    # (blocks per lane, LDS hit buffer) of the selected specialised kernel
         if jit:
             self.enable_jit()
 
     def enable_jit(self):
         check(_lib.ah_primers_jit(self.h), "ah_primers_jit")
         self.jit = self.has_jit = True
+        if self.variant is None:
+            self.variant = JIT_DEFAULT_VARIANT
+
+    def jit_variant(self, blocks_per_lane: int, hit_buffer: int):
+        """Select (compiling on first use) the specialised kernel with this
+        tile size (blocks per lane: a wave scans 4096 x blocks_per_lane
+        positions per step) and LDS hit buffer per wave."""
+        check(_lib.ah_primers_jit_variant(self.h, int(blocks_per_lane), int(hit_buffer)), "ah_primers_jit_variant")
+        self.jit = self.has_jit = True
+        self.variant = (int(blocks_per_lane), int(hit_buffer))
 
     def use_jit(self, on: bool):
         check(_lib.ah_primers_use_jit(self.h, int(bool(on))), "ah_primers_use_jit")
@@ -461,16 +473,20 @@ def table_bytes(n_pairs: int) -> int:
     return int(_lib.ah_primers_table_bytes(n_pairs))
 
 
-def jit_check(pairs, arch: str = "gfx950") -> int:
-    """Generate and compile the specialised scan kernel of `pairs` for `arch`
-    without loading it (no GPU needed); returns the ah_status."""
+JIT_DEFAULT_VARIANT = (1, 48)
+JIT_VARIANTS = ((1, 48), (1, 16), (2, 48), (2, 16))   # (blocks per lane, LDS hit buffer per wave)
+
+
+def jit_check(pairs, arch: str = "gfx950", variant=JIT_DEFAULT_VARIANT) -> int:
+    """Generate and compile the specialised scan kernel variant of `pairs` for
+    `arch` without loading it (no GPU needed); returns the ah_status."""
     arr = (ah_pair_spec * max(len(pairs), 1))()
     keep = []
     for i, p in enumerate(pairs):
         f, r = p.fwd.encode(), p.rev.encode()
         keep += [f, r]
         arr[i] = ah_pair_spec(f, r, int(p.k), int(p.clamp), int(p.min_len), int(p.max_len))
-    return int(_lib.ah_primers_jit_check(arr, len(pairs), arch.encode()))
+    return int(_lib.ah_primers_jit_check(arr, len(pairs), arch.encode(), int(variant[0]), int(variant[1])))
 
 
 def tm_params(tm) -> ah_tm_params:

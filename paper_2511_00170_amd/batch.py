@@ -64,6 +64,7 @@ class TuneResult:
     wg_per_cu: int
     ms: float
     table: list = field(default_factory=list)
+    variant: Optional[tuple] = None   # (blocks per lane, LDS hit buffer) of the specialised kernel
 
 
 class BatchRunner:
@@ -88,10 +89,12 @@ class BatchRunner:
         self.tuned: Optional[TuneResult] = None
 
     # ------------------------------------------------------------- autotune
-    def tune(self, sample_bases: float = 1e9, wg_options=None, reps: int = 3) -> TuneResult:
+    def tune(self, sample_bases: float = 1e9, wg_options=None, reps: int = 3, variants=None) -> TuneResult:
         """Time the scan of a leading sample of the store (about sample_bases)
-        under each kernel variant (specialised / generic x workgroups per CU)
-        and keep the fastest.  Every variant must give the same hit set."""
+        under each kernel variant -- the specialised kernel at every (tile
+        size = blocks per lane, LDS hit buffer) of `variants`, the generic
+        kernel -- and each persistent grid (workgroups per CU), and keep the
+        fastest.  Every variant must give the same hit set."""
         lens = self.store.lengths.astype(np.int64)
         m = int(np.searchsorted(np.cumsum(lens), sample_bases, side="left")) + 1
         m = max(1, min(m, self.store.n_seqs))
@@ -99,11 +102,14 @@ class BatchRunner:
         cap = hit_capacity(self.pairs, int(lens[:m].sum()))
         probe = ah.Pipeline(self.store, self.ps, self.orient_mask, self.tm, None,
                             caps=ah.Caps(cap, 1, 1), subset=sub)
-        kernels = ([True] if self.ps.has_jit else []) + [False]
+        kinds = [("jit", v) for v in (variants or ah.JIT_VARIANTS)] if self.ps.has_jit else []
+        kinds.append(("generic", None))
         ref, best, table = None, None, []
-        for jit in kernels:
-            if self.ps.has_jit:
-                self.ps.use_jit(jit)
+        for kind, v in kinds:
+            if kind == "jit":
+                self.ps.jit_variant(*v)
+            elif self.ps.has_jit:
+                self.ps.use_jit(False)
             max_wg = self.ps.launch_shape(0)
             opts = wg_options or sorted({1, 2, max(1, max_wg // 2), max_wg})
             for wg in opts:
@@ -130,14 +136,18 @@ class BatchRunner:
                 if ref is None:
                     ref = hits
                 elif not np.array_equal(ref, hits):
-                    raise RuntimeError("scan variant jit=%s wg_per_cu=%d changed the hits" % (jit, wg))
+                    raise RuntimeError("scan variant %s %s wg_per_cu=%d changed the hits" % (kind, v, wg))
                 ms = float(np.median(ts))
-                table.append({"kernel": "jit" if jit else "generic", "wg_per_cu": wg, "ms": round(ms, 4)})
+                bpl, hb = v if v else (1, 48)
+                table.append({"kernel": kind, "tile_bases": 4096 * bpl, "blocks_per_lane": bpl, "hit_buffer": hb,
+                              "wg_per_cu": wg, "ms": round(ms, 4)})
                 if best is None or ms < best.ms:
-                    best = TuneResult(jit, wg, ms)
+                    best = TuneResult(kind == "jit", wg, ms, variant=v)
         best.table = table
-        if self.ps.has_jit:
-            self.ps.use_jit(best.jit)
+        if best.jit:
+            self.ps.jit_variant(*best.variant)
+        elif self.ps.has_jit:
+            self.ps.use_jit(False)
         self.ps.launch_shape(best.wg_per_cu)
         self.tuned = best
         self.graph = None

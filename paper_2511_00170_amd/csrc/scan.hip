@@ -96,12 +96,13 @@ __global__ void __launch_bounds__(256) ah_scan_kernel(ScanArgs a) {
 }
 
 // ---------------------------------------------------------------- tile table
-__global__ void ah_tile_count_kernel(ah_store st, const uint32_t *list, uint32_t n, uint64_t *out) {
+__global__ void ah_tile_count_kernel(ah_store st, const uint32_t *list, uint32_t n, uint32_t tile_blocks,
+                                     uint64_t *out) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint32_t s = list ? list[i] : i;
         // an index outside the store contributes no tiles
         const uint64_t nblk = s < st.n_seqs ? ((uint64_t)st.d_seq_len[s] + 63) / 64 : 0;
-        out[i] = (nblk + AH_TILE_BLOCKS - 1) / AH_TILE_BLOCKS;
+        out[i] = (nblk + tile_blocks - 1) / tile_blocks;
     }
 }
 
@@ -135,7 +136,18 @@ struct AhJit {
     hipFunction_t fn = nullptr;
     int per_cu = 0;  // resident workgroups per CU
     int device = -1;
+    uint32_t bpl = 1;   // 64-base blocks per lane (a wave's tile: 64 x bpl blocks)
+    uint32_t hcap = 0;  // LDS hit buffer records per wave
 };
+
+// Every compiled variant of a primer set's specialised kernel; one is active.
+struct AhJitSet {
+    std::vector<AhJit *> v;
+    AhJit *active = nullptr;
+};
+
+#define AH_JIT_DEFAULT_BPL 1u
+#define AH_JIT_DEFAULT_HCAP 48u
 
 // ---------------------------------------------------------------- filter plan
 // The clamp positions alone let through about prod(|set|/4) of all windows;
@@ -225,14 +237,17 @@ static std::string set_test_chain(std::string acc, const std::vector<FiltPos> &p
 
 // Kernel source specialised to a primer set: the codes of every oriented
 // pattern's filter positions become template constants of the set tests.
-static std::string jit_source(const ah_primer_set_ *ps) {
+static std::string jit_source(const ah_primer_set_ *ps, uint32_t bpl, uint32_t hcap) {
     std::string s;
+    const int nw = 2 * (int)bpl;  // words per lane and plane in the variant
     std::vector<FiltPlan> plans(ps->n_pats);
     bool any_groups = false;
     for (uint32_t X = 0; X < ps->n_pats; X++) {
         plans[X] = plan_filter(ps->h_pats[X]);
         any_groups = any_groups || plans[X].n_groups > 0;
     }
+    s += "#define AH_BPL " + std::to_string(bpl) + "\n";
+    s += "#define AH_HCAP " + std::to_string(hcap) + "\n";
     s += "#include \"scan_core.h\"\n";
     s += std::string("#define AH_JIT_USES_BASE ") + (any_groups ? "true" : "false") + "\n";
     s += "struct JitFilter {\n";
@@ -250,7 +265,7 @@ static std::string jit_source(const ah_primer_set_ *ps) {
             const DPat &P = ps->h_pats[4 * g + x];
             const uint32_t W = (P.meta >> 16) & 0xFFu;
             const FiltPlan &plan = plans[4 * g + x];
-            for (int w = 0; w < AH_NW; w++) {
+            for (int w = 0; w < nw; w++) {
                 const std::string Ws = std::to_string(w);
                 std::string c = "0xFFFFFFFFu";
                 for (uint32_t i = 0; i < W; i++) {
@@ -265,7 +280,7 @@ static std::string jit_source(const ah_primer_set_ *ps) {
                         any += (q ? " | " : "") + set_test_chain("0xFFFFFFFFu", plan.groups[q], w);
                     c = "(" + c + ") & (" + any + ")";
                 }
-                s += "      C[" + std::to_string(AH_NW * x + w) + "] = " + c + ";\n";
+                s += "      C[" + std::to_string(nw * x + w) + "] = " + c + ";\n";
             }
         }
         s += "      break; }\n";
@@ -296,8 +311,11 @@ static int device_cus(int dev) {
 }
 
 // Compile the specialised kernel for `arch` (e.g. "gfx950"); code object in *code.
-static ah_status jit_compile(const ah_primer_set_ *ps, const std::string &arch, std::vector<char> *code) {
-    const std::string src = jit_source(ps);
+static bool jit_variant_ok(uint32_t bpl, uint32_t hcap) { return (bpl == 1 || bpl == 2) && hcap >= 2 && hcap <= 256; }
+
+static ah_status jit_compile(const ah_primer_set_ *ps, const std::string &arch, uint32_t bpl, uint32_t hcap,
+                             std::vector<char> *code) {
+    const std::string src = jit_source(ps, bpl, hcap);
     // AH_JIT_DUMP=<path>: also write the generated source there (inspection)
     if (const char *dump = getenv("AH_JIT_DUMP")) {
         if (FILE *f = fopen(dump, "w")) {
@@ -328,31 +346,39 @@ static ah_status jit_compile(const ah_primer_set_ *ps, const std::string &arch, 
     return AH_OK;
 }
 
-extern "C" ah_status ah_primers_jit_check(const ah_pair_spec *h_pairs, uint32_t n_pairs, const char *arch) {
-    if (!arch || !*arch) return AH_E_ARG;
+extern "C" ah_status ah_primers_jit_check(const ah_pair_spec *h_pairs, uint32_t n_pairs, const char *arch,
+                                          uint32_t blocks_per_lane, uint32_t hit_buffer) {
+    if (!arch || !*arch || !jit_variant_ok(blocks_per_lane, hit_buffer)) return AH_E_ARG;
     ah_primer_set ps = nullptr;
     ah_status st = ah_build_primer_set(h_pairs, n_pairs, true, &ps);
     if (st != AH_OK) return st;
     std::vector<char> code;
-    st = jit_compile(ps, arch, &code);
+    st = jit_compile(ps, arch, blocks_per_lane, hit_buffer, &code);
     ah_primers_free(ps);
     return st;
 }
 
-extern "C" ah_status ah_primers_jit(ah_primer_set ps) {
-    if (!ps) return AH_E_ARG;
-    if (ps->jit) {
-        ps->use_jit = 1;
-        return AH_OK;
-    }
+extern "C" ah_status ah_primers_jit_variant(ah_primer_set ps, uint32_t blocks_per_lane, uint32_t hit_buffer) {
+    if (!ps || !jit_variant_ok(blocks_per_lane, hit_buffer)) return AH_E_ARG;
     int dev = 0;
     hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return AH_E_HIP;
+    if (hipGetDevice(&dev) != hipSuccess) return AH_E_HIP;
+    AhJitSet *set = (AhJitSet *)ps->jit;
+    if (set) {
+        for (AhJit *j : set->v) {
+            if (j->device == dev && j->bpl == blocks_per_lane && j->hcap == hit_buffer) {
+                set->active = j;
+                ps->use_jit = 1;
+                return AH_OK;
+            }
+        }
+    }
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return AH_E_HIP;
     std::string arch = prop.gcnArchName;
     const size_t colon = arch.find(':');  // drop feature suffixes such as ":sramecc+:xnack-"
     if (colon != std::string::npos) arch = arch.substr(0, colon);
     std::vector<char> code;
-    const ah_status st = jit_compile(ps, arch, &code);
+    const ah_status st = jit_compile(ps, arch, blocks_per_lane, hit_buffer, &code);
     if (st != AH_OK) return st;
     AhJit *j = new AhJit();
     if (hipModuleLoadData(&j->mod, code.data()) != hipSuccess ||
@@ -366,23 +392,43 @@ extern "C" ah_status ah_primers_jit(ah_primer_set ps) {
         per_cu = 1;
     j->per_cu = per_cu;
     j->device = dev;
-    ps->jit = j;
+    j->bpl = blocks_per_lane;
+    j->hcap = hit_buffer;
+    if (!set) {
+        set = new AhJitSet();
+        ps->jit = set;
+    }
+    set->v.push_back(j);
+    set->active = j;
     ps->use_jit = 1;
     return AH_OK;
 }
 
+extern "C" ah_status ah_primers_jit(ah_primer_set ps) {
+    if (!ps) return AH_E_ARG;
+    const AhJitSet *set = (const AhJitSet *)ps->jit;
+    if (set && set->active) {
+        ps->use_jit = 1;
+        return AH_OK;
+    }
+    return ah_primers_jit_variant(ps, AH_JIT_DEFAULT_BPL, AH_JIT_DEFAULT_HCAP);
+}
+
 extern "C" ah_status ah_primers_use_jit(ah_primer_set ps, int32_t on) {
     if (!ps) return AH_E_ARG;
-    if (on && !ps->jit) return AH_E_ARG;
+    if (on && !(ps->jit && ((const AhJitSet *)ps->jit)->active)) return AH_E_ARG;
     ps->use_jit = on ? 1 : 0;
     return AH_OK;
 }
 
 void ah_jit_free(void *jit) {
-    AhJit *j = (AhJit *)jit;
-    if (!j) return;
-    if (j->mod) (void)hipModuleUnload(j->mod);
-    delete j;
+    AhJitSet *set = (AhJitSet *)jit;
+    if (!set) return;
+    for (AhJit *j : set->v) {
+        if (j->mod) (void)hipModuleUnload(j->mod);
+        delete j;
+    }
+    delete set;
 }
 
 // Resident workgroups per CU of the generic kernel (same on every gfx950 device).
@@ -397,9 +443,11 @@ static int generic_per_cu() {
     return per_cu;
 }
 
-static bool jit_active(ah_primer_set ps, int dev) {
-    const AhJit *j = (const AhJit *)ps->jit;
-    return j && ps->use_jit && j->device == dev;
+// The active specialised variant if it is in use on this device, else null.
+static const AhJit *jit_active(ah_primer_set ps, int dev) {
+    const AhJitSet *set = (const AhJitSet *)ps->jit;
+    const AhJit *j = set ? set->active : nullptr;
+    return j && ps->use_jit && j->device == dev ? j : nullptr;
 }
 
 extern "C" ah_status ah_primers_launch_shape(ah_primer_set ps, int32_t wg_per_cu, int32_t *max_wg_per_cu) {
@@ -407,7 +455,8 @@ extern "C" ah_status ah_primers_launch_shape(ah_primer_set ps, int32_t wg_per_cu
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return AH_E_HIP;
     ps->wg_per_cu = wg_per_cu;
-    if (max_wg_per_cu) *max_wg_per_cu = jit_active(ps, dev) ? ((const AhJit *)ps->jit)->per_cu : generic_per_cu();
+    const AhJit *j = jit_active(ps, dev);
+    if (max_wg_per_cu) *max_wg_per_cu = j ? j->per_cu : generic_per_cu();
     return AH_OK;
 }
 
@@ -428,7 +477,13 @@ static ah_status scan_launch(const ah_store *st, ah_primer_set ps, const uint32_
     uint64_t *pref = (uint64_t *)((char *)d_ws + ah_align_up(8ull * n_list, 256));
     ah_fill<uint64_t>(d_n_hits, 0ull, 1, s);
     if (!n_list) return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
-    hipLaunchKernelGGL(ah_tile_count_kernel, dim3(256), dim3(256), 0, s, *st, d_seq_subset, n_list, cnt);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const AhJit *jk = jit_active(ps, dev);
+    // tiles of the kernel that will run (a specialised variant may use larger ones)
+    const uint32_t tile_blocks = jk ? 64u * jk->bpl : (uint32_t)AH_TILE_BLOCKS;
+    hipLaunchKernelGGL(ah_tile_count_kernel, dim3(256), dim3(256), 0, s, *st, d_seq_subset, n_list, tile_blocks,
+                       cnt);
     ah_scan_small_u64(cnt, pref, n_list, s);
     ScanArgs a;
     a.st = *st;
@@ -442,16 +497,13 @@ static ah_status scan_launch(const ah_store *st, ah_primer_set ps, const uint32_
     a.hits = (uint32_t *)d_hits;
     a.hit_cap = hit_cap;
     a.n_hits = d_n_hits;
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    const bool use_j = jit_active(ps, dev);
     // persistent grid: the workgroups that can be resident at once (or fewer, as set)
-    int per_cu = use_j ? ((const AhJit *)ps->jit)->per_cu : generic_per_cu();
+    int per_cu = jk ? jk->per_cu : generic_per_cu();
     if (ps->wg_per_cu > 0 && ps->wg_per_cu < per_cu) per_cu = ps->wg_per_cu;
     const unsigned grid = (unsigned)(device_cus(dev) * per_cu);
-    if (use_j) {
+    if (jk) {
         void *args[] = {&a};
-        if (hipModuleLaunchKernel(((AhJit *)ps->jit)->fn, grid, 1, 1, 256, 1, 1, 0, s, args, nullptr) != hipSuccess)
+        if (hipModuleLaunchKernel(jk->fn, grid, 1, 1, 256, 1, 1, 0, s, args, nullptr) != hipSuccess)
             return AH_E_HIP;
         return AH_OK;
     }

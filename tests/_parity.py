@@ -9,10 +9,12 @@ import oracle
 TM_TOL = 1e-9  # degrees C, FP64 (same operation order on both sides)
 
 
-def gpu_run(store, pairs, orient_mask, tm, ex=None, subset=None, caps=None, jit=False):
+def gpu_run(store, pairs, orient_mask, tm, ex=None, subset=None, caps=None, jit=False, variant=None):
     from paper_2511_00170_amd import ah
     import torch
-    ps = ah.PrimerSet(pairs, jit=jit)
+    ps = ah.PrimerSet(pairs, jit=jit and variant is None)
+    if variant is not None:
+        ps.jit_variant(*variant)
     sub = None
     if subset is not None:
         sub = torch.from_numpy(np.asarray(subset, np.uint32).view(np.int32)).cuda()
@@ -67,9 +69,15 @@ def compare_extract(r, e):
     assert (r["rprimer"] == e.rprimer).all()
 
 
-def full_parity(store, ascii_buf, off, pairs, orient_mask, tm, ex=None, n_threads=None, jit=False):
+# scan kernels: the generic one and the specialised one in every variant
+# (blocks per lane, LDS hit buffer) the autotuner may pick
+KERNELS = {"generic": (False, None), "jit": (True, None), "jit-1x16": (True, (1, 16)),
+           "jit-2x48": (True, (2, 48)), "jit-2x16": (True, (2, 16))}
+
+
+def full_parity(store, ascii_buf, off, pairs, orient_mask, tm, ex=None, n_threads=None, jit=False, variant=None):
     """Run both sides on the same input; assert every output agrees."""
-    r = gpu_run(store, pairs, orient_mask, tm, ex, jit=jit)
+    r = gpu_run(store, pairs, orient_mask, tm, ex, jit=jit, variant=variant)
     o = oracle.run(ascii_buf, off, pairs, orient_mask, tm, ex, n_threads=n_threads)
     compare_hits(r["hits"], o.hits, o.mm)
     compare_amps(r["amps"], o.amps)

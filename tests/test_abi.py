@@ -66,9 +66,14 @@ def test_primer_compile_rejects_bad_input_without_gpu():
 @pytest.mark.parametrize("cfg", [1, 2, 3, 5])
 def test_specialised_scan_kernel_compiles_without_gpu(cfg):
     """The hipRTC source generated for a primer set compiles for gfx950 (the
-    same headers and options the library uses at run time)."""
+    same headers and options the library uses at run time), in every variant
+    the autotuner may pick."""
     if not os.path.exists(LIB):
         pytest.fail("libah.so is not built")
     from paper_2511_00170_amd import ah, synth
     wl = synth.gen_config(cfg, n_seqs=2, len_scale=1e-4)
-    assert ah.jit_check(wl.pairs, "gfx950") == ah.AH_OK
+    variants = ah.JIT_VARIANTS if cfg in (2, 3) else (ah.JIT_DEFAULT_VARIANT,)
+    for v in variants:
+        assert ah.jit_check(wl.pairs, "gfx950", v) == ah.AH_OK, v
+    assert ah.jit_check(wl.pairs, "gfx950", (3, 48)) == ah.AH_E_ARG
+    assert ah.jit_check(wl.pairs, "gfx950", (1, 1)) == ah.AH_E_ARG

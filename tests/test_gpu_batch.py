@@ -112,8 +112,12 @@ def test_autotuner_variants_agree_and_choice_is_applied(mods, batch_wl):
     best = br.tune(sample_bases=3e5, wg_options=[1, 2, 4], reps=2)  # raises if any variant differs
     kinds = {r["kernel"] for r in best.table}
     assert kinds == {"jit", "generic"}
+    tried = {(r["blocks_per_lane"], r["hit_buffer"]) for r in best.table if r["kernel"] == "jit"}
+    assert tried == set(ah.JIT_VARIANTS)              # tile sizes 4096 and 8192, two hit buffers
     assert round(best.ms, 4) == min(r["ms"] for r in best.table)
     assert br.ps.jit == best.jit
+    if best.jit:
+        assert br.ps.variant == best.variant
     res = br.run()
     ref = ah.Pipeline(st, ah.PrimerSet(wl.pairs), wl.orient_mask, wl.tm, wl.extract).run().results()
     _same(res, ref, True)

@@ -66,7 +66,7 @@ ADVERSARIAL_PAIRS = [
 ]
 
 
-KERNELS = ["generic", "jit"]
+KERNELS = list(P.KERNELS)
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
@@ -98,8 +98,9 @@ def test_scan_pair_tm_adversarial(ah, pi, kernel):
     _say("adversarial pair", pi, kernel)
     st = ah.Store.from_ascii(seqs)
     tm = TmSpec(threshold_C=40.0)
+    jit, variant = P.KERNELS[kernel]
     r, o = P.full_parity(st, buf, off, [pair], 0xF, tm, ExtractSpec(trim=True, fb_len=7, rb_len=9),
-                         jit=kernel == "jit")
+                         jit=jit, variant=variant)
     assert len(o.hits) > 0
 
 
@@ -119,7 +120,7 @@ def test_genome_config_reduced_full_path(ah, kernel):
     _say("config genome reduced", wl.total_bases, kernel)
     st = ah.Store.from_workload(wl)
     r, o = P.full_parity(st, buf, off, wl.pairs, wl.orient_mask, wl.tm, ExtractSpec(trim=True, fb_len=16, rb_len=16),
-                         jit=kernel == "jit")
+                         jit=P.KERNELS[kernel][0], variant=P.KERNELS[kernel][1])
     assert len(o.amps) > 20
 
 
@@ -139,7 +140,8 @@ def test_many_pairs_batch_reduced(ah, kernel):
     buf, off = wl.concat()
     _say("config batch reduced", wl.total_bases, wl.n_seqs, kernel)
     st = ah.Store.from_workload(wl)
-    P.full_parity(st, buf, off, wl.pairs, wl.orient_mask, wl.tm, ExtractSpec(), jit=kernel == "jit")
+    jit, variant = P.KERNELS[kernel]
+    P.full_parity(st, buf, off, wl.pairs, wl.orient_mask, wl.tm, ExtractSpec(), jit=jit, variant=variant)
 
 
 def test_overflow_rerun_is_exact(ah):
