@@ -21,6 +21,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 BYTES_PER_BASE = 0.25   # 2-bit store
+# int32 / bitwise vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64
+# instruction occupies a SIMD for 4 clocks), in tera lane-ops per second
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def parse():
@@ -68,17 +71,56 @@ def scan_source_hash():
     return h.hexdigest()
 
 
-def traffic_from_profiles(kernel_src_hash):
-    """HBM bytes per scan launch from committed rocprofv3 counter runs, if they
-    were taken on the current scan kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", "scan_genome_counters.json")
+def counters_from_profiles(name, kernel_src_hash):
+    """Committed rocprofv3 counter summary profiles/<name>_counters.json, if it
+    was taken on the current scan kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "%s_counters.json" % name)
     try:
         d = json.load(open(p))
     except Exception:
         return None
-    if d.get("scan_src_sha256") != kernel_src_hash:
+    return d if d.get("scan_src_sha256") == kernel_src_hash else None
+
+
+def traffic_from_profiles(kernel_src_hash):
+    """HBM bytes per genome scan launch from the committed counter runs."""
+    d = counters_from_profiles("scan_genome", kernel_src_hash)
+    return d.get("hbm_bytes_per_launch") if d else None
+
+
+def valu_roof(insts, kernel_ms):
+    """Vector ALU issue: wave instructions per launch x 64 lanes over the
+    launch time, against the int32 VALU peak."""
+    if not insts:
         return None
-    return d.get("hbm_bytes_per_launch")
+    tops = insts * 64 / (kernel_ms / 1e3) / 1e12
+    return {"insts_per_launch": int(insts), "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "Tlane-ops/s", "frac": round(tops / VALU_PEAK_TOPS, 4)}
+
+
+def stream_read_probe():
+    """A read-only stream over 4 GiB in HBM (ah_read_probe: 128-bit loads, a
+    persistent grid): the bandwidth a plain reading kernel reaches on this
+    GPU, in GB/s (median of 9)."""
+    import numpy as np
+    import torch
+
+    from paper_2511_00170_amd import ah
+    x = torch.ones(1 << 30, dtype=torch.int32, device="cuda")
+    out = torch.empty(8192, dtype=torch.int32, device="cuda")
+    ah.read_probe(x, out)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(9):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        ah.read_probe(x, out)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    del x, out
+    torch.cuda.empty_cache()
+    return round((4 << 30) / (float(np.median(ts)) / 1e3) / 1e9, 1)
 
 
 def cpu_threads():
@@ -295,14 +337,22 @@ def bench_batch(args, wl, store, sample):
     br.replay()
     res = br.pipe.results()
     log("graph %.3f ms/step, scan %.3f ms" % (ms_step, scan_ms))
-    plain, plain_ms = batch.plain_loop(store, wl.pairs, wl.orient_mask, wl.tm, ex, jit=not args.generic,
-                                       reps=args.plain_reps)
-    same = batch_outputs_equal(res, plain)
-    log("plain loop %.3f ms; identical output: %s" % (plain_ms, same))
+    if args.plain_reps > 0:
+        plain, plain_ms = batch.plain_loop(store, wl.pairs, wl.orient_mask, wl.tm, ex, jit=not args.generic,
+                                           reps=args.plain_reps)
+        same = batch_outputs_equal(res, plain)
+        log("plain loop %.3f ms; identical output: %s" % (plain_ms, same))
+    else:
+        plain_ms, same = None, None
     npairs = len(wl.pairs)
     alg_bytes = BYTES_PER_BASE * total + 12.0 * n_hits
     achieved = alg_bytes / (scan_ms / 1e3) / 1e9
     kern = "ah_scan_jit" if br.ps.jit else "ah_scan_kernel"
+    variant = list(br.ps.variant) if br.ps.jit else None
+    prof = counters_from_profiles("scan_batch", scan_source_hash()) if br.ps.jit else None
+    if prof and prof.get("variant") != variant:
+        prof = None      # counters of another tile / hit-buffer variant
+    valu = valu_roof(prof.get("valu_insts_per_launch") if prof else None, scan_ms)
     out = {
         "metric": "Gbases scanned/s per primer pair (k mm) + % HBM peak; batched vs plain; p50/p99 latency",
         "value": round(npairs * total / (ms_step / 1e3) / 1e9, 2),
@@ -315,13 +365,23 @@ def bench_batch(args, wl, store, sample):
                    "pairs": npairs, "bases": total, "hits": n_hits, "amplicons": n_amps,
                    "scan_kernel": "primer-set specialised (hipRTC)" if br.ps.jit else "generic",
                    "graph": True, "autotune": tuned.table if tuned else None,
-                   "wg_per_cu": tuned.wg_per_cu if tuned else 0},
-        "batched_vs_plain": {"batched_ms": round(ms_step, 3), "plain_loop_ms": round(plain_ms, 3),
-                             "speedup": round(plain_ms / ms_step, 3), "identical_output": same,
-                             "plain_pair_gbases_s": round(npairs * total / (plain_ms / 1e3) / 1e9, 2)},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kern,
-                     "kernel_ms": round(scan_ms, 4), "algorithmic_bytes_per_launch": int(alg_bytes)},
+                   "wg_per_cu": tuned.wg_per_cu if tuned else 0, "variant": variant},
+        "batched_vs_plain": {"batched_ms": round(ms_step, 3),
+                             "plain_loop_ms": round(plain_ms, 3) if plain_ms else None,
+                             "speedup": round(plain_ms / ms_step, 3) if plain_ms else None,
+                             "identical_output": same,
+                             "plain_pair_gbases_s": round(npairs * total / (plain_ms / 1e3) / 1e9, 2)
+                             if plain_ms else None},
+        # the scan of 256 patterns is bound by vector ALU issue: achieved =
+        # measured VALU lane-ops per second (committed counters), the HBM
+        # figures beside it
+        "roofline": {"bound": "alu", "achieved": valu["achieved"] if valu else None,
+                     "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tlane-ops/s",
+                     "frac": valu["frac"] if valu else None,
+                     "traffic": prof.get("hbm_bytes_per_launch") if prof else None, "kernel": kern,
+                     "kernel_ms": round(scan_ms, 4), "valu_insts_per_launch": valu["insts_per_launch"] if valu else None,
+                     "algorithmic_bytes_per_launch": int(alg_bytes), "hbm_achieved_GB_s": round(achieved, 1),
+                     "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)},
         "cpu_baseline": cpu_baseline(wl, sample, ex, "pair-Gbases/s"),
     }
     return out
@@ -428,7 +488,8 @@ def extra_batch(args):
     r = dict(o["batched_vs_plain"])
     r.update({"workload": o["config"]["workload"], "pairs": o["config"]["pairs"], "bases": o["config"]["bases"],
               "batched_pair_gbases_s": o["value"], "unit": "pair-Gbases/s", "scan_ms": o["roofline"]["kernel_ms"],
-              "scan_bound": "alu"})
+              "scan_bound": "alu", "scan_valu_frac": o["roofline"]["frac"], "scan_hbm_frac": o["roofline"]["hbm_frac"],
+              "variant": o["config"]["variant"], "wg_per_cu": o["config"]["wg_per_cu"]})
     return r
 
 
@@ -528,7 +589,7 @@ def main():
     if len(wl.pairs) > 1:
         out = bench_batch(args, wl, store, sample)
         print(json.dumps(out), flush=True)
-        if not out["batched_vs_plain"]["identical_output"]:
+        if out["batched_vs_plain"]["identical_output"] is False:
             sys.exit(1)
         return
 
@@ -561,11 +622,16 @@ def main():
     gbases_s = total / (ms_step / 1e3) / 1e9
     alg_bytes = BYTES_PER_BASE * total + 12.0 * n_hits
     achieved = alg_bytes / (scan_ms / 1e3) / 1e9
-    traffic = traffic_from_profiles(scan_source_hash())
+    prof = counters_from_profiles("scan_genome", scan_source_hash()) if ps.jit else None
+    traffic = prof.get("hbm_bytes_per_launch") if prof else None
+    stream_gbs = stream_read_probe()
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "ah_scan_jit" if ps.jit else "ah_scan_kernel", "kernel_ms": round(scan_ms, 4),
-            "algorithmic_bytes_per_launch": int(alg_bytes)}
+            "algorithmic_bytes_per_launch": int(alg_bytes),
+            "measured_hbm_frac": round(traffic / (scan_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+            "stream_read_GB_s": stream_gbs, "frac_of_stream_read": round(achieved / stream_gbs, 4),
+            "valu": valu_roof(prof.get("valu_insts_per_launch") if prof else None, scan_ms)}
 
     cpu = cpu_baseline(wl, sample, ex, "Gbases/s")
 
@@ -601,7 +667,7 @@ def main():
         torch.cuda.empty_cache()
         out["serving"] = extra_serve(args)
     print(json.dumps(out), flush=True)
-    if out.get("batched_vs_plain") and not out["batched_vs_plain"]["identical_output"]:
+    if out.get("batched_vs_plain") and out["batched_vs_plain"]["identical_output"] is False:
         sys.exit(1)
 
 

@@ -362,6 +362,15 @@ ah_status ah_extract(const ah_store *st, ah_primer_set ps, const ah_amp *d_amps,
                      char *d_rprimer, uint64_t *d_n_bytes, void *d_ws, uint64_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Measurement helper: read d_buf[0:bytes) once with 128-bit loads (a
+ * persistent grid of at most out_n workgroups, each writing one XOR fold to
+ * d_out) -- the HBM read bandwidth a plain streaming kernel reaches, the
+ * ceiling the scan's bandwidth is compared with.  bytes must be a multiple of
+ * 16; d_out holds out_n words.  Errors: AH_E_ARG, AH_E_HIP.
+ * ---------------------------------------------------------------------- */
+ah_status ah_read_probe(const void *d_buf, uint64_t bytes, uint32_t *d_out, uint32_t out_n, void *stream);
+
+/* ------------------------------------------------------------------------
  * FASTA ingest (Implementations: AHv2 reads FASTA into 2-bit batches of
  * headers, lengths and bases; Discussion: headers kept apart from the bases).
  *

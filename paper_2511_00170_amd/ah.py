@@ -83,6 +83,7 @@ _sig("ah_pack", I32, C.POINTER(ah_store), VP, VP, U32, U32, VP, U64, VP)
 _sig("ah_pack_finish", I32, C.POINTER(ah_store), VP, U64, VP)
 _sig("ah_unpack", I32, C.POINTER(ah_store), U32, U64, U64, VP, VP)
 _sig("ah_pack_pieces", I32, VP, U64, VP, VP, VP, VP, U32, VP, U64, VP)
+_sig("ah_read_probe", I32, VP, U64, VP, U32, VP)
 _sig("ah_fasta_ws_size", I32, U64, C.POINTER(U64))
 _sig("ah_fasta_ingest", I32, C.POINTER(C.c_char_p), U32, VP, U64, VP, VP, VP, U64, U64, VP, U64, VP, C.POINTER(VP))
 _sig("ah_fasta_info", I32, VP, C.POINTER(U32), C.POINTER(U64), C.POINTER(U64), C.POINTER(U32))
@@ -118,7 +119,8 @@ EXPORTED = ["ah_status_str", "ah_version", "ah_pack_layout", "ah_pack_begin", "a
             "ah_primers_launch_shape", "ah_scan_ws_size",
             "ah_scan_primers", "ah_scan_primers_masked", "ah_route_hits", "ah_pair_ws_size", "ah_pair_amplicons", "ah_tm_nn", "ah_tm_duplex",
             "ah_extract_ws_size", "ah_extract", "ah_pack_pieces", "ah_fasta_ws_size", "ah_fasta_ingest",
-            "ah_fasta_info", "ah_fasta_table", "ah_fasta_names_of", "ah_fasta_free", "ah_fasta_format"]
+            "ah_fasta_info", "ah_fasta_table", "ah_fasta_names_of", "ah_fasta_free", "ah_fasta_format",
+            "ah_read_probe"]
 
 HIT_DTYPE = np.dtype([("seq", "<u4"), ("pos", "<u4"), ("pair", "<u2"), ("kind", "u1"), ("mm", "u1")])
 AMP_DTYPE = np.dtype([("seq", "<u4"), ("start", "<u4"), ("end", "<u4"), ("pair", "<u2"), ("orient", "u1"),
@@ -475,6 +477,12 @@ def table_bytes(n_pairs: int) -> int:
 
 JIT_DEFAULT_VARIANT = (1, 48)
 JIT_VARIANTS = ((1, 48), (1, 16), (2, 48), (2, 16))   # (blocks per lane, LDS hit buffer per wave)
+
+
+def read_probe(buf: torch.Tensor, out: torch.Tensor, stream=None) -> None:
+    """One read-only stream over buf (see ah_read_probe); out: int32 scratch."""
+    check(_lib.ah_read_probe(_p(buf), buf.numel() * buf.element_size() // 16 * 16, _p(out), out.numel(),
+                             _stream(stream)), "ah_read_probe")
 
 
 def jit_check(pairs, arch: str = "gfx950", variant=JIT_DEFAULT_VARIANT) -> int:

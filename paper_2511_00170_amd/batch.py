@@ -89,12 +89,15 @@ class BatchRunner:
         self.tuned: Optional[TuneResult] = None
 
     # ------------------------------------------------------------- autotune
-    def tune(self, sample_bases: float = 1e9, wg_options=None, reps: int = 3, variants=None) -> TuneResult:
+    def tune(self, sample_bases: float = 1e9, wg_options=None, reps: int = 3, variants=None,
+             tolerance: float = 0.02) -> TuneResult:
         """Time the scan of a leading sample of the store (about sample_bases)
         under each kernel variant -- the specialised kernel at every (tile
         size = blocks per lane, LDS hit buffer) of `variants`, the generic
-        kernel -- and each persistent grid (workgroups per CU), and keep the
-        fastest.  Every variant must give the same hit set."""
+        kernel -- and each persistent grid (workgroups per CU).  Keep the
+        first candidate (default variant first, larger grids first) within
+        `tolerance` of the fastest, so timing noise does not flip the choice
+        between runs.  Every variant must give the same hit set."""
         lens = self.store.lengths.astype(np.int64)
         m = int(np.searchsorted(np.cumsum(lens), sample_bases, side="left")) + 1
         m = max(1, min(m, self.store.n_seqs))
@@ -104,14 +107,14 @@ class BatchRunner:
                             caps=ah.Caps(cap, 1, 1), subset=sub)
         kinds = [("jit", v) for v in (variants or ah.JIT_VARIANTS)] if self.ps.has_jit else []
         kinds.append(("generic", None))
-        ref, best, table = None, None, []
+        ref, table, cands = None, [], []
         for kind, v in kinds:
             if kind == "jit":
                 self.ps.jit_variant(*v)
             elif self.ps.has_jit:
                 self.ps.use_jit(False)
             max_wg = self.ps.launch_shape(0)
-            opts = wg_options or sorted({1, 2, max(1, max_wg // 2), max_wg})
+            opts = wg_options or sorted({1, 2, max(1, max_wg // 2), max_wg}, reverse=True)
             for wg in opts:
                 if wg > max_wg:
                     continue
@@ -141,8 +144,9 @@ class BatchRunner:
                 bpl, hb = v if v else (1, 48)
                 table.append({"kernel": kind, "tile_bases": 4096 * bpl, "blocks_per_lane": bpl, "hit_buffer": hb,
                               "wg_per_cu": wg, "ms": round(ms, 4)})
-                if best is None or ms < best.ms:
-                    best = TuneResult(kind == "jit", wg, ms, variant=v)
+                cands.append(TuneResult(kind == "jit", wg, ms, variant=v))
+        fastest = min(c.ms for c in cands)
+        best = next(c for c in cands if c.ms <= fastest * (1.0 + tolerance))
         best.table = table
         if best.jit:
             self.ps.jit_variant(*best.variant)

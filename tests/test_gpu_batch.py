@@ -114,7 +114,7 @@ def test_autotuner_variants_agree_and_choice_is_applied(mods, batch_wl):
     assert kinds == {"jit", "generic"}
     tried = {(r["blocks_per_lane"], r["hit_buffer"]) for r in best.table if r["kernel"] == "jit"}
     assert tried == set(ah.JIT_VARIANTS)              # tile sizes 4096 and 8192, two hit buffers
-    assert round(best.ms, 4) == min(r["ms"] for r in best.table)
+    assert best.ms <= 1.02 * min(r["ms"] for r in best.table) + 1e-4
     assert br.ps.jit == best.jit
     if best.jit:
         assert br.ps.variant == best.variant

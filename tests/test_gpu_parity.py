@@ -264,3 +264,17 @@ def test_invalid_salt_method_is_rejected(ah):
         ah.tm_duplex(["ACGTACGT"], ["TGCATGCA"], TmSpec(saltcorr=8))
     with pytest.raises(ah.AhError):
         ah.tm_duplex(["ACGTACGT"], ["TGCATGCA"], TmSpec(na_mM=0, saltcorr=1))
+
+
+def test_read_probe_reads_every_word(ah):
+    """The bandwidth probe touches every 16-byte word once: the XOR of its
+    per-workgroup folds equals the XOR of the buffer (also with a ragged tail)."""
+    rng = np.random.default_rng(12)
+    for n in (1 << 22, (1 << 22) + 36):
+        x = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+        d = torch.from_numpy(x.view(np.int32)).cuda()
+        out = torch.zeros(8192, dtype=torch.int32, device="cuda")
+        ah.read_probe(d, out)
+        torch.cuda.synchronize()
+        got = np.bitwise_xor.reduce(out.cpu().numpy().view(np.uint32))
+        assert got == np.bitwise_xor.reduce(x[:n // 4 * 4])
