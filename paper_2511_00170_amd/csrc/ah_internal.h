@@ -37,6 +37,15 @@ ah_status ah_build_primer_set(const ah_pair_spec *h_pairs, uint32_t n_pairs, boo
 
 static inline hipStream_t ah_stream(void *s) { return (hipStream_t)s; }
 
+// Compute units of the current device (256 on MI355X if the query fails).
+static inline uint32_t ah_device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    return (uint32_t)cus;
+}
+
 static inline uint64_t ah_align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // Device table layout inside one buffer: patterns first, then pair records.
 static inline uint64_t ah_pat_bytes(uint32_t n_pairs) { return ah_align_up(4ull * n_pairs * sizeof(DPat), 256); }

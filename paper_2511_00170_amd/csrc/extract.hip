@@ -52,18 +52,87 @@ __device__ __forceinline__ char base_at(const ah_store &st, uint64_t b0, uint64_
     return "ACGT"[c];
 }
 
+// Bases [a0, a1) of a sequence (first block b0) to out[dst0 ..], forward or
+// (rc) reverse-complemented: out[j] = comp(s[a1 - 1 - j]).  Whole wave.  The
+// span's blocks and their N masks are staged in LDS 64 at a time (one block
+// per lane, all loads in flight together); every output byte is then decoded
+// from LDS, consecutive lanes writing consecutive bytes.
+__device__ __forceinline__ void copy_span(const ah_store &st, uint64_t b0, uint64_t a0, uint64_t a1, bool rc,
+                                          char *out, uint64_t dst0, uint64_t seq_cap, uint4 *sblk, uint64_t *snm) {
+    const uint32_t lane = ah_lane();
+    if (a1 <= a0) return;
+    const uint64_t bs = a0 >> 6, be = ((a1 - 1) >> 6) + 1;  // blocks of the span, sequence-relative
+    for (uint64_t cb = bs; cb < be; cb += 64) {
+        const uint64_t ce = cb + 64 < be ? cb + 64 : be;
+        ah_wave_sync();  // the previous chunk's bytes are written
+        if (cb + lane < ce) {
+            const uint64_t gb = b0 + cb + lane;
+            sblk[lane] = ((const uint4 *)st.d_blocks)[gb];
+            snm[lane] = ah_block_nmask(st, gb);
+        }
+        ah_wave_sync();
+        // the chunk's positions inside the span, and their output indices
+        const uint64_t p0 = cb * 64 > a0 ? cb * 64 : a0, p1 = ce * 64 < a1 ? ce * 64 : a1;
+        const uint64_t j0 = rc ? a1 - p1 : p0 - a0, j1 = rc ? a1 - p0 : p1 - a0;
+        for (uint64_t j = j0 + lane; j < j1; j += 64) {
+            const uint64_t p = rc ? a1 - 1 - j : a0 + j;
+            const uint32_t k = (uint32_t)((p >> 6) - cb), bit = (uint32_t)(p & 63);
+            const uint4 w = sblk[k];
+            const uint32_t h = bit < 32 ? w.x : w.z, l = bit < 32 ? w.y : w.w;
+            uint32_t c = (((h >> (bit & 31)) & 1u) << 1) | ((l >> (bit & 31)) & 1u);
+            if (rc) c ^= 3u;
+            if (dst0 + j < seq_cap) out[dst0 + j] = ((snm[k] >> bit) & 1ull) ? 'N' : "ACGT"[c];
+        }
+    }
+}
+
+// Output bytes of amplicon i (0 when it did not pass).
+__device__ __forceinline__ uint64_t amp_size(const uint32_t *amps, uint64_t i, const DPair *pairs,
+                                             const uint8_t *pass, uint32_t trim) {
+    if (pass && !pass[i]) return 0;
+    const AmpGeom g = amp_geom(amps, i, pairs);
+    uint64_t a0, a1;
+    amp_span(g, trim, &a0, &a1);
+    return a1 - a0;
+}
+
 __global__ void ah_extract_size_kernel(const uint32_t *amps, const uint64_t *d_n, uint64_t cap, const DPair *pairs,
                                        const uint8_t *pass, uint32_t trim, uint64_t *size) {
     const uint64_t n = *d_n < cap ? *d_n : cap;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t s = 0;
-        if (!pass || pass[i]) {
-            const AmpGeom g = amp_geom(amps, i, pairs);
-            uint64_t a0, a1;
-            amp_span(g, trim, &a0, &a1);
-            s = a1 - a0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        size[i] = amp_size(amps, i, pairs, pass, trim);
+}
+
+// Sizes and their exclusive prefix in one workgroup (for up to
+// AH_EXTRACT_ONE_WG amplicons): seq_off[i], seq_off[n] = *n_bytes = total.
+#define AH_EXTRACT_ONE_WG 65536u
+__global__ void __launch_bounds__(1024) ah_extract_offsets_kernel(const uint32_t *amps, const uint64_t *d_n,
+                                                                  uint64_t cap, const DPair *pairs,
+                                                                  const uint8_t *pass, uint32_t trim,
+                                                                  uint64_t *seq_off, uint64_t *n_bytes) {
+    __shared__ uint64_t lds[16];
+    const uint64_t n = *d_n < cap ? *d_n : cap;
+    uint64_t carry = 0;
+    for (uint64_t r0 = 0; r0 < n; r0 += 4 * 1024) {
+        const uint64_t i0 = r0 + 4 * threadIdx.x;
+        uint64_t sz[4], loc = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            sz[k] = i0 + k < n ? amp_size(amps, i0 + k, pairs, pass, trim) : 0;
+            loc += sz[k];
         }
-        size[i] = s;
+        uint64_t tot;
+        uint64_t o = carry + ah_block_excl_sum<uint64_t>(loc, lds, tot);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (i0 + k < n) seq_off[i0 + k] = o;
+            o += sz[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        seq_off[n] = carry;
+        *n_bytes = carry;
     }
 }
 
@@ -79,6 +148,8 @@ __global__ void __launch_bounds__(256) ah_extract_write_kernel(ah_store st, cons
                                                                ah_extract_opts o, const uint64_t *seq_off, char *out,
                                                                uint64_t seq_cap, char *fb, char *rb, uint8_t *bc_len,
                                                                char *fpr, char *rpr) {
+    __shared__ uint4 s_blk[4][64];
+    __shared__ uint64_t s_nm[4][64];
     const uint64_t n = *d_n < cap ? *d_n : cap;
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
@@ -127,11 +198,7 @@ __global__ void __launch_bounds__(256) ah_extract_write_kernel(ah_store st, cons
         if (!on) continue;
         uint64_t a0, a1;
         amp_span(g, o.trim, &a0, &a1);
-        const uint64_t dst0 = seq_off[i];
-        const uint64_t m = a1 - a0;
-        for (uint64_t j = lane; j < m; j += 64) {
-            if (dst0 + j < seq_cap) out[dst0 + j] = base_at(st, b0, rc ? a1 - 1 - j : a0 + j, rc);
-        }
+        copy_span(st, b0, a0, a1, rc, out, seq_off[i], seq_cap, s_blk[threadIdx.x >> 6], s_nm[threadIdx.x >> 6]);
     }
 }
 
@@ -175,12 +242,18 @@ extern "C" ah_status ah_extract(const ah_store *st, ah_primer_set ps, const ah_a
     ExtractWs w = extract_ws(d_ws, amp_cap ? amp_cap : 1);
     if (!d_ws || ws_bytes < w.bytes) return AH_E_WORKSPACE;
     hipStream_t s = ah_stream(stream);
-    hipLaunchKernelGGL(ah_extract_size_kernel, dim3(1024), dim3(256), 0, s, (const uint32_t *)d_amps, d_n_amps, amp_cap,
-                       (const DPair *)ps->d_pairs, d_pass, o->trim, w.size);
-    ah_status e = ah_exclusive_scan<uint64_t, uint64_t>(w.size, d_seq_off, d_n_amps, amp_cap, w.total, w.partials, s);
-    if (e) return e;
-    hipLaunchKernelGGL(ah_extract_tail_kernel, dim3(1), dim3(1), 0, s, d_n_amps, amp_cap, (const uint64_t *)w.total,
-                       d_seq_off, d_n_bytes);
+    if (amp_cap <= AH_EXTRACT_ONE_WG) {  // one launch for sizes and offsets
+        hipLaunchKernelGGL(ah_extract_offsets_kernel, dim3(1), dim3(1024), 0, s, (const uint32_t *)d_amps, d_n_amps,
+                           amp_cap, (const DPair *)ps->d_pairs, d_pass, o->trim, d_seq_off, d_n_bytes);
+    } else {
+        hipLaunchKernelGGL(ah_extract_size_kernel, dim3(1024), dim3(256), 0, s, (const uint32_t *)d_amps, d_n_amps,
+                           amp_cap, (const DPair *)ps->d_pairs, d_pass, o->trim, w.size);
+        ah_status e =
+            ah_exclusive_scan<uint64_t, uint64_t>(w.size, d_seq_off, d_n_amps, amp_cap, w.total, w.partials, s);
+        if (e) return e;
+        hipLaunchKernelGGL(ah_extract_tail_kernel, dim3(1), dim3(1), 0, s, d_n_amps, amp_cap,
+                           (const uint64_t *)w.total, d_seq_off, d_n_bytes);
+    }
     if (amp_cap) {
         uint64_t wgs = (amp_cap + 3) / 4;
         if (wgs > 16384) wgs = 16384;

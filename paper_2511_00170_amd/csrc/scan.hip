@@ -106,6 +106,39 @@ __global__ void ah_tile_count_kernel(ah_store st, const uint32_t *list, uint32_t
     }
 }
 
+// Tiles per listed sequence and their exclusive prefix in one workgroup (for
+// up to AH_TILE_PREF_ONE_WG sequences); also clears the hit counter.
+#define AH_TILE_PREF_ONE_WG 16384u
+__global__ void __launch_bounds__(1024) ah_tile_pref_kernel(ah_store st, const uint32_t *list, uint32_t n,
+                                                            uint32_t tile_blocks, uint64_t *pref, uint64_t *n_hits) {
+    __shared__ uint64_t lds[16];
+    if (threadIdx.x == 0) *n_hits = 0;
+    uint64_t carry = 0;
+    for (uint64_t r0 = 0; r0 < n; r0 += 4 * 1024) {
+        const uint64_t i0 = r0 + 4 * threadIdx.x;
+        uint64_t v[4], loc = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            v[k] = 0;
+            if (i0 + k < n) {
+                const uint32_t s = list ? list[i0 + k] : (uint32_t)(i0 + k);
+                const uint64_t nblk = s < st.n_seqs ? ((uint64_t)st.d_seq_len[s] + 63) / 64 : 0;
+                v[k] = (nblk + tile_blocks - 1) / tile_blocks;
+            }
+            loc += v[k];
+        }
+        uint64_t tot;
+        uint64_t o = carry + ah_block_excl_sum<uint64_t>(loc, lds, tot);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (i0 + k < n) pref[i0 + k] = o;
+            o += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) pref[n] = carry;
+}
+
 __global__ void __launch_bounds__(1024) ah_scan_small_u64_kernel(const uint64_t *in, uint64_t *out, uint64_t n) {
     __shared__ uint64_t lds[16];
     uint64_t carry = 0;
@@ -475,16 +508,21 @@ static ah_status scan_launch(const ah_store *st, ah_primer_set ps, const uint32_
     hipStream_t s = ah_stream(stream);
     uint64_t *cnt = (uint64_t *)d_ws;
     uint64_t *pref = (uint64_t *)((char *)d_ws + ah_align_up(8ull * n_list, 256));
-    ah_fill<uint64_t>(d_n_hits, 0ull, 1, s);
-    if (!n_list) return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
     int dev = 0;
     (void)hipGetDevice(&dev);
     const AhJit *jk = jit_active(ps, dev);
     // tiles of the kernel that will run (a specialised variant may use larger ones)
     const uint32_t tile_blocks = jk ? 64u * jk->bpl : (uint32_t)AH_TILE_BLOCKS;
-    hipLaunchKernelGGL(ah_tile_count_kernel, dim3(256), dim3(256), 0, s, *st, d_seq_subset, n_list, tile_blocks,
-                       cnt);
-    ah_scan_small_u64(cnt, pref, n_list, s);
+    if (n_list && n_list <= AH_TILE_PREF_ONE_WG) {  // counts, prefix and the cleared counter in one launch
+        hipLaunchKernelGGL(ah_tile_pref_kernel, dim3(1), dim3(1024), 0, s, *st, d_seq_subset, n_list, tile_blocks,
+                           pref, d_n_hits);
+    } else {
+        ah_fill<uint64_t>(d_n_hits, 0ull, 1, s);
+        if (!n_list) return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
+        hipLaunchKernelGGL(ah_tile_count_kernel, dim3(256), dim3(256), 0, s, *st, d_seq_subset, n_list, tile_blocks,
+                           cnt);
+        ah_scan_small_u64(cnt, pref, n_list, s);
+    }
     ScanArgs a;
     a.st = *st;
     a.pats = ps->d_pats;

@@ -421,8 +421,11 @@ extern "C" ah_status ah_tm_nn(const ah_store *st, ah_primer_set ps, const ah_amp
         if (!ps->h_pairs[q].prim[0].D || !ps->h_pairs[q].prim[1].D) return AH_E_LIMIT;
     if (!amp_cap) return AH_OK;
     hipStream_t s = ah_stream(stream);
+    // one wave per site over a persistent grid: every workgroup stages the NN
+    // tables in LDS once, so no more workgroups than can be resident
     uint64_t wgs = (2 * amp_cap + 3) / 4;
-    if (wgs > 16384) wgs = 16384;
+    const uint64_t resident = 8ull * ah_device_cus();
+    if (wgs > resident) wgs = resident;
     hipLaunchKernelGGL(ah_tm_site_kernel, dim3((unsigned)wgs), dim3(256), 0, s, *st, (const DPair *)ps->d_pairs,
                        (const uint32_t *)d_amps, d_n_amps, amp_cap, *p, d_tm_site);
     hipLaunchKernelGGL(ah_tm_finish_kernel, dim3(256), dim3(256), 0, s, (const double *)d_tm_site, d_amps, d_n_amps,
