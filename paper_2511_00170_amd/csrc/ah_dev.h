@@ -49,6 +49,7 @@ struct DPrimer {
     uint8_t n_deg;           // degenerate positions
     uint8_t pad[2];
     uint32_t D;              // number of concrete variants (<= AH_MAX_VARIANTS)
+    uint64_t base;           // code[j] at bits 2j: the first variant
     uint8_t code[AH_MAXL];   // 2-bit base of each concrete position
     uint8_t deg_pos[AH_MAXL];
     uint8_t deg_n[AH_MAXL];

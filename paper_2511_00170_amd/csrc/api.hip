@@ -101,6 +101,7 @@ static void make_primer(const int *m, int L, DPrimer *p) {
                 n++;
             }
         p->code[j] = (uint8_t)first;
+        p->base |= (uint64_t)first << (2 * j);
         if (n > 1) {
             int d = p->n_deg++;
             p->deg_pos[d] = (uint8_t)j;

@@ -335,15 +335,14 @@ __device__ __forceinline__ uint64_t primer_variant(const DPrimer &P, uint64_t ba
     return V;
 }
 
-__device__ __forceinline__ uint64_t primer_base_codes(const DPrimer &P) {
-    uint64_t V = 0;
-    for (int j = 0; j < P.L; j++) V |= (uint64_t)P.code[j] << (2 * j);
-    return V;
-}
+__device__ __forceinline__ uint64_t primer_base_codes(const DPrimer &P) { return P.base; }
 
+// Sites packed lps lanes apart (lps = the set's largest variant count rounded
+// up to a power of two, at most 64): a wave evaluates 64 / lps sites at once,
+// each lane a variant, and max-reduces within its site's lanes.
 __global__ void __launch_bounds__(256) ah_tm_site_kernel(ah_store st, const DPair *pairs, const uint32_t *amps,
                                                          const uint64_t *d_n, uint64_t cap, ah_tm_params prm,
-                                                         double *tm_site) {
+                                                         uint32_t lps, double *tm_site) {
     __shared__ double sdh[256], sds[256], tdh[256], tds[256];
     __shared__ uint32_t sok[8], tok[8];
     for (int i = threadIdx.x; i < 256; i += blockDim.x) {
@@ -360,9 +359,13 @@ __global__ void __launch_bounds__(256) ah_tm_site_kernel(ah_store st, const DPai
     const TmConst k = tm_const(prm);
     const uint64_t n = *d_n < cap ? *d_n : cap;
     const uint32_t lane = threadIdx.x & 63;
+    const uint32_t per_wave = 64u / lps, sub = lane / lps, vl = lane % lps;
     const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    for (uint64_t w = blockIdx.x * (uint64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); w < 2 * n; w += nw) {
-        const uint64_t a = w >> 1;
+    for (uint64_t w0 = (blockIdx.x * (uint64_t)(blockDim.x >> 6) + (threadIdx.x >> 6)) * per_wave; w0 < 2 * n;
+         w0 += nw * per_wave) {
+        const uint64_t w = w0 + sub;  // this lane's site
+        const bool live = w < 2 * n;
+        const uint64_t a = live ? w >> 1 : 0;
         const int side = (int)(w & 1);
         const uint32_t seq = amps[4 * a], start = amps[4 * a + 1], end = amps[4 * a + 2], meta = amps[4 * a + 3];
         const uint32_t pair = meta & 0xFFFFu, orient = (meta >> 16) & 0xFFu;
@@ -380,20 +383,19 @@ __global__ void __launch_bounds__(256) ah_tm_site_kernel(ah_store st, const DPai
         const uint64_t lm = L == 32 ? ~0ull : ((1ull << (2 * L)) - 1);
         const uint64_t Cc = side == 0 ? (G ^ (0xFFFFFFFFFFFFFFFFull & lm)) : reverse_codes(G, L);
         double best = -INFINITY;
-        if (!has_n && P.D) {
+        if (live && !has_n && P.D) {
             const uint64_t base = primer_base_codes(P);
-            for (uint32_t v = lane; v < P.D; v += 64) {
+            for (uint32_t v = vl; v < P.D; v += lps) {
                 double t;
                 if (duplex_tm(primer_variant(P, base, v), Cc, L, sdh, sds, sok, tdh, tds, tok, k, &t))
                     best = t > best ? t : best;
             }
         }
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-            const double o = __shfl_xor(best, d, 64);
+        for (uint32_t d = lps >> 1; d >= 1; d >>= 1) {  // within the site's lanes
+            const double o = __shfl_xor(best, (int)d, 64);
             best = o > best ? o : best;
         }
-        if (lane == 0) tm_site[2 * a + side] = best;
+        if (live && vl == 0) tm_site[2 * a + side] = best;
     }
 }
 
@@ -417,17 +419,22 @@ extern "C" ah_status ah_tm_nn(const ah_store *st, ah_primer_set ps, const ah_amp
         TmConst k;
         if (tm_salt_setup(*p, &k)) return AH_E_ARG;  // unknown method or a zero concentration under a logarithm
     }
-    for (uint32_t q = 0; q < ps->n_pairs; q++)
+    uint32_t maxD = 1;
+    for (uint32_t q = 0; q < ps->n_pairs; q++) {
         if (!ps->h_pairs[q].prim[0].D || !ps->h_pairs[q].prim[1].D) return AH_E_LIMIT;
+        for (int r = 0; r < 2; r++) maxD = ps->h_pairs[q].prim[r].D > maxD ? ps->h_pairs[q].prim[r].D : maxD;
+    }
+    uint32_t lps = 1;  // lanes per site: a power of two covering the largest variant count, at most 64
+    while (lps < maxD && lps < 64) lps <<= 1;
     if (!amp_cap) return AH_OK;
     hipStream_t s = ah_stream(stream);
     // one wave per site over a persistent grid: every workgroup stages the NN
     // tables in LDS once, so no more workgroups than can be resident
-    uint64_t wgs = (2 * amp_cap + 3) / 4;
+    uint64_t wgs = (2 * amp_cap + 4 * (64 / lps) - 1) / (4 * (64 / lps));
     const uint64_t resident = 8ull * ah_device_cus();
     if (wgs > resident) wgs = resident;
     hipLaunchKernelGGL(ah_tm_site_kernel, dim3((unsigned)wgs), dim3(256), 0, s, *st, (const DPair *)ps->d_pairs,
-                       (const uint32_t *)d_amps, d_n_amps, amp_cap, *p, d_tm_site);
+                       (const uint32_t *)d_amps, d_n_amps, amp_cap, *p, lps, d_tm_site);
     hipLaunchKernelGGL(ah_tm_finish_kernel, dim3(256), dim3(256), 0, s, (const double *)d_tm_site, d_amps, d_n_amps,
                        amp_cap, *p, d_tm, d_pass);
     return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
