@@ -103,30 +103,30 @@ __global__ void ah_extract_size_kernel(const uint32_t *amps, const uint64_t *d_n
         size[i] = amp_size(amps, i, pairs, pass, trim);
 }
 
-// Sizes and their exclusive prefix in one workgroup (for up to
-// AH_EXTRACT_ONE_WG amplicons): seq_off[i], seq_off[n] = *n_bytes = total.
+// Exclusive prefix of the sizes in one workgroup (for up to AH_EXTRACT_ONE_WG
+// amplicons), in coalesced rounds of 4 x 1024: seq_off[i], seq_off[n] =
+// *n_bytes = total.
 #define AH_EXTRACT_ONE_WG 65536u
-__global__ void __launch_bounds__(1024) ah_extract_offsets_kernel(const uint32_t *amps, const uint64_t *d_n,
-                                                                  uint64_t cap, const DPair *pairs,
-                                                                  const uint8_t *pass, uint32_t trim,
-                                                                  uint64_t *seq_off, uint64_t *n_bytes) {
+__global__ void __launch_bounds__(1024) ah_extract_offsets_kernel(const uint64_t *size, const uint64_t *d_n,
+                                                                  uint64_t cap, uint64_t *seq_off,
+                                                                  uint64_t *n_bytes) {
     __shared__ uint64_t lds[16];
     const uint64_t n = *d_n < cap ? *d_n : cap;
     uint64_t carry = 0;
     for (uint64_t r0 = 0; r0 < n; r0 += 4 * 1024) {
         const uint64_t i0 = r0 + 4 * threadIdx.x;
-        uint64_t sz[4], loc = 0;
+        uint64_t v[4], loc = 0;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            sz[k] = i0 + k < n ? amp_size(amps, i0 + k, pairs, pass, trim) : 0;
-            loc += sz[k];
+            v[k] = i0 + k < n ? size[i0 + k] : 0;
+            loc += v[k];
         }
         uint64_t tot;
         uint64_t o = carry + ah_block_excl_sum<uint64_t>(loc, lds, tot);
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             if (i0 + k < n) seq_off[i0 + k] = o;
-            o += sz[k];
+            o += v[k];
         }
         carry += tot;
     }
@@ -242,12 +242,12 @@ extern "C" ah_status ah_extract(const ah_store *st, ah_primer_set ps, const ah_a
     ExtractWs w = extract_ws(d_ws, amp_cap ? amp_cap : 1);
     if (!d_ws || ws_bytes < w.bytes) return AH_E_WORKSPACE;
     hipStream_t s = ah_stream(stream);
-    if (amp_cap <= AH_EXTRACT_ONE_WG) {  // one launch for sizes and offsets
-        hipLaunchKernelGGL(ah_extract_offsets_kernel, dim3(1), dim3(1024), 0, s, (const uint32_t *)d_amps, d_n_amps,
-                           amp_cap, (const DPair *)ps->d_pairs, d_pass, o->trim, d_seq_off, d_n_bytes);
+    hipLaunchKernelGGL(ah_extract_size_kernel, dim3(1024), dim3(256), 0, s, (const uint32_t *)d_amps, d_n_amps,
+                       amp_cap, (const DPair *)ps->d_pairs, d_pass, o->trim, w.size);
+    if (amp_cap <= AH_EXTRACT_ONE_WG) {  // one launch for the offsets
+        hipLaunchKernelGGL(ah_extract_offsets_kernel, dim3(1), dim3(1024), 0, s, (const uint64_t *)w.size, d_n_amps,
+                           amp_cap, d_seq_off, d_n_bytes);
     } else {
-        hipLaunchKernelGGL(ah_extract_size_kernel, dim3(1024), dim3(256), 0, s, (const uint32_t *)d_amps, d_n_amps,
-                           amp_cap, (const DPair *)ps->d_pairs, d_pass, o->trim, w.size);
         ah_status e =
             ah_exclusive_scan<uint64_t, uint64_t>(w.size, d_seq_off, d_n_amps, amp_cap, w.total, w.partials, s);
         if (e) return e;

@@ -107,50 +107,47 @@ __global__ void ah_tile_count_kernel(ah_store st, const uint32_t *list, uint32_t
 }
 
 // Tiles per listed sequence and their exclusive prefix in one workgroup (for
-// up to AH_TILE_PREF_ONE_WG sequences); also clears the hit counter.
+// up to AH_TILE_PREF_ONE_WG sequences, one contiguous chunk per thread); also
+// clears the hit counter.
 #define AH_TILE_PREF_ONE_WG 16384u
+__device__ __forceinline__ uint64_t tiles_of(const ah_store &st, const uint32_t *list, uint64_t i,
+                                             uint32_t tile_blocks) {
+    const uint32_t s = list ? list[i] : (uint32_t)i;
+    const uint64_t nblk = s < st.n_seqs ? ((uint64_t)st.d_seq_len[s] + 63) / 64 : 0;
+    return (nblk + tile_blocks - 1) / tile_blocks;
+}
+
 __global__ void __launch_bounds__(1024) ah_tile_pref_kernel(ah_store st, const uint32_t *list, uint32_t n,
                                                             uint32_t tile_blocks, uint64_t *pref, uint64_t *n_hits) {
     __shared__ uint64_t lds[16];
     if (threadIdx.x == 0) *n_hits = 0;
-    uint64_t carry = 0;
-    for (uint64_t r0 = 0; r0 < n; r0 += 4 * 1024) {
-        const uint64_t i0 = r0 + 4 * threadIdx.x;
-        uint64_t v[4], loc = 0;
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            v[k] = 0;
-            if (i0 + k < n) {
-                const uint32_t s = list ? list[i0 + k] : (uint32_t)(i0 + k);
-                const uint64_t nblk = s < st.n_seqs ? ((uint64_t)st.d_seq_len[s] + 63) / 64 : 0;
-                v[k] = (nblk + tile_blocks - 1) / tile_blocks;
-            }
-            loc += v[k];
-        }
-        uint64_t tot;
-        uint64_t o = carry + ah_block_excl_sum<uint64_t>(loc, lds, tot);
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            if (i0 + k < n) pref[i0 + k] = o;
-            o += v[k];
-        }
-        carry += tot;
+    const uint64_t per = ((uint64_t)n + blockDim.x - 1) / blockDim.x;
+    const uint64_t i0 = threadIdx.x * per, i1 = i0 + per < n ? i0 + per : n;
+    uint64_t loc = 0;
+    for (uint64_t i = i0; i < i1; i++) loc += tiles_of(st, list, i, tile_blocks);
+    uint64_t tot;
+    uint64_t o = ah_block_excl_sum<uint64_t>(loc, lds, tot);
+    for (uint64_t i = i0; i < i1; i++) {
+        pref[i] = o;
+        o += tiles_of(st, list, i, tile_blocks);
     }
-    if (threadIdx.x == 0) pref[n] = carry;
+    if (threadIdx.x == 0) pref[n] = tot;
 }
 
 __global__ void __launch_bounds__(1024) ah_scan_small_u64_kernel(const uint64_t *in, uint64_t *out, uint64_t n) {
     __shared__ uint64_t lds[16];
-    uint64_t carry = 0;
-    for (uint64_t t0 = 0; t0 < n; t0 += blockDim.x) {
-        const uint64_t i = t0 + threadIdx.x;
-        const uint64_t v = i < n ? in[i] : 0;
-        uint64_t tot;
-        const uint64_t ex = ah_block_excl_sum<uint64_t>(v, lds, tot);
-        if (i < n) out[i] = carry + ex;
-        carry += tot;
+    const uint64_t per = (n + blockDim.x - 1) / blockDim.x;  // one contiguous chunk per thread
+    const uint64_t i0 = threadIdx.x * per, i1 = i0 + per < n ? i0 + per : n;
+    uint64_t loc = 0;
+    for (uint64_t i = i0; i < i1; i++) loc += in[i];
+    uint64_t tot;
+    uint64_t o = ah_block_excl_sum<uint64_t>(loc, lds, tot);
+    for (uint64_t i = i0; i < i1; i++) {
+        const uint64_t v = in[i];
+        out[i] = o;
+        o += v;
     }
-    if (threadIdx.x == 0) out[n] = carry;
+    if (threadIdx.x == 0) out[n] = tot;
 }
 
 void ah_scan_small_u64(const uint64_t *d_in, uint64_t *d_out, uint64_t n, hipStream_t s) {
