@@ -218,7 +218,8 @@ typedef struct {
 /* Workspace bytes for ah_scan_primers over n_list sequences (all: n_seqs). */
 ah_status ah_scan_ws_size(const ah_store *st, uint32_t n_list, uint64_t *bytes);
 
-/* d_seq_subset: NULL for every sequence, else n_subset store indices.
+/* d_seq_subset: NULL for every sequence, else n_subset store indices
+ * (n_subset may be 0: nothing is scanned; the pointer must still be non-null).
  * Writes min(total, hit_cap) hits; *d_n_hits = total (the call resets it). */
 ah_status ah_scan_primers(const ah_store *st, ah_primer_set ps, const uint32_t *d_seq_subset, uint32_t n_subset,
                           ah_hit *d_hits, uint64_t hit_cap, uint64_t *d_n_hits, void *d_ws, uint64_t ws_bytes,

@@ -527,10 +527,21 @@ def ws_extract(amp_cap: int) -> int:
     return int(b.value)
 
 
+def _list_ptr(subset, stand_in):
+    """Device pointer of a sequence list: None for "every sequence"; for an
+    empty list a non-null stand-in (an empty tensor may have a null data
+    pointer, which the library would read as every sequence; with zero
+    entries the pointer is never read)."""
+    if subset is None:
+        return None
+    return _p(subset) if subset.numel() else _p(stand_in)
+
+
 def scan_primers(store, ps, hits, hit_cap, n_hits, ws, subset=None, stream=None):
     n_sub = 0 if subset is None else int(subset.numel())
-    check(_lib.ah_scan_primers(C.byref(store.c), ps.h, _p(subset), n_sub, _p(hits), hit_cap, _p(n_hits), _p(ws),
-                               ws.numel() * ws.element_size(), _stream(stream)), "ah_scan_primers")
+    check(_lib.ah_scan_primers(C.byref(store.c), ps.h, _list_ptr(subset, n_hits), n_sub, _p(hits), hit_cap,
+                               _p(n_hits), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
+          "ah_scan_primers")
 
 
 def scan_primers_masked(store, ps, subset, pair_mask, hits, hit_cap, n_hits, ws, stream=None):
@@ -538,7 +549,8 @@ def scan_primers_masked(store, ps, subset, pair_mask, hits, hit_cap, n_hits, ws,
     one word per subset entry)."""
     n_sub = int(subset.numel()) if subset is not None else store.n_seqs
     assert pair_mask.numel() >= n_sub and pair_mask.dtype == torch.int64
-    check(_lib.ah_scan_primers_masked(C.byref(store.c), ps.h, _p(subset), n_sub if subset is not None else 0,
+    check(_lib.ah_scan_primers_masked(C.byref(store.c), ps.h, _list_ptr(subset, n_hits),
+                                      n_sub if subset is not None else 0,
                                       _p(pair_mask), _p(hits), hit_cap, _p(n_hits), _p(ws),
                                       ws.numel() * ws.element_size(), _stream(stream)), "ah_scan_primers_masked")
 
