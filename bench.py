@@ -167,11 +167,11 @@ def _fasta_lines(s, width=80):
 
 
 def extra_fasta(wl, store, res, ex, gbases):
-    """FASTA I/O: the leading ~gbases of the workload written as a FASTA file
-    (80 bases a line), read into a new store by ah_fasta_ingest (one pass,
-    pinned double-buffered chunks) and by the record-table pass alone (host
-    parse, no GPU); the new store must equal the resident one block for
-    block.  The AHv2 writer is timed on the run's amplicons."""
+    """FASTA I/O: the leading ~gbases of the workload written as FASTA, one
+    file per genome (80 bases a line), read into a new store by
+    ah_fasta_ingest with 8 host workers and with one, and by the record-table
+    pass alone (host parse, no GPU); the new store must equal the resident one
+    block for block.  The AHv2 writer is timed on the run's amplicons."""
     import tempfile
 
     import numpy as np
@@ -179,119 +179,60 @@ def extra_fasta(wl, store, res, ex, gbases):
 
     from paper_2511_00170_amd import ah
     d = tempfile.mkdtemp(prefix="ah_fasta_")
-    path = os.path.join(d, "genomes.fa")
-    goal, n_bases, n_seqs = gbases * 1e9, 0, 0
+    goal, n_bases, paths = gbases * 1e9, 0, []
     try:
-        with open(path, "wb") as fh:
-            for first, buf, off in wl.chunks(1 << 30):
-                for i in range(len(off) - 1):
-                    if n_bases >= goal:
-                        break
-                    fh.write(b">seq%d source genome\n" % (first + i))
-                    fh.write(_fasta_lines(buf[int(off[i]):int(off[i + 1])]))
-                    n_bases += int(off[i + 1] - off[i])
-                    n_seqs += 1
+        for first, buf, off in wl.chunks(1 << 30):
+            for i in range(len(off) - 1):
                 if n_bases >= goal:
                     break
-        fbytes = os.path.getsize(path)
+                p = os.path.join(d, "g%05d.fa" % (first + i))
+                with open(p, "wb") as fh:
+                    fh.write(b">seq%d source genome\n" % (first + i))
+                    fh.write(_fasta_lines(buf[int(off[i]):int(off[i + 1])]))
+                paths.append(p)
+                n_bases += int(off[i + 1] - off[i])
+            if n_bases >= goal:
+                break
+        fbytes = sum(os.path.getsize(p) for p in paths)
         t0 = time.perf_counter()
-        tab = ah.fasta_index([path])
+        tab = ah.fasta_index(paths, n_threads=8)
         t_index = time.perf_counter() - t0
         del tab
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = ah.Store.from_fasta([path])
-        torch.cuda.synchronize()
-        t_ingest = time.perf_counter() - t0
-        nb = st.n_blocks
-        same = st.n_seqs == n_seqs and torch.equal(st.blocks[:nb], store.blocks[:nb])
-        nw = nb // 32
-        same = same and torch.equal(st.nbits[:nw], store.nbits[:nw])
-        same = same and torch.equal(st.nmask[:st.n_nblocks], store.nmask[:st.n_nblocks])
-        del st
+        rates = {}
+        same = True
+        for nt in (8, 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = ah.Store.from_fasta(paths, n_threads=nt)
+            torch.cuda.synchronize()
+            rates[nt] = time.perf_counter() - t0
+            nb = st.n_blocks
+            ok = st.n_seqs == len(paths) and torch.equal(st.blocks[:nb], store.blocks[:nb])
+            nw = nb // 32
+            ok = ok and torch.equal(st.nbits[:nw], store.nbits[:nw])
+            same = same and ok and torch.equal(st.nmask[:st.n_nblocks], store.nmask[:st.n_nblocks])
+            del st
     finally:
-        if os.path.exists(path):
-            os.remove(path)
+        for p in paths:
+            if os.path.exists(p):
+                os.remove(p)
         os.rmdir(d)
     names = ah.FastaNames([b"seq%d" % i for i in range(store.n_seqs)], np.zeros(store.n_seqs, np.uint32),
                           [b"genomes.fa"])
     t0 = time.perf_counter()
     text = ah.format_fasta(names, res, ex.fb_len, ex.rb_len, tm_filter=wl.tm.filter)
     t_write = time.perf_counter() - t0
-    out = {"fasta_bytes": fbytes, "sequences": n_seqs, "bases": n_bases,
-           "ingest_s": round(t_ingest, 3), "ingest_GB_s": round(fbytes / t_ingest / 1e9, 3),
-           "ingest_Gbases_s": round(n_bases / t_ingest / 1e9, 3),
-           "host_parse_only_GB_s": round(fbytes / t_index / 1e9, 3),
+    out = {"fasta_bytes": fbytes, "files": len(paths), "bases": n_bases,
+           "ingest_s": round(rates[8], 3), "ingest_GB_s": round(fbytes / rates[8] / 1e9, 3),
+           "ingest_Gbases_s": round(n_bases / rates[8] / 1e9, 3), "ingest_threads": 8,
+           "ingest_GB_s_one_thread": round(fbytes / rates[1] / 1e9, 3),
+           "host_index_only_GB_s": round(fbytes / t_index / 1e9, 3),
            "store_identical_to_resident": bool(same),
            "writer_records": text.count(b"\n>") + (1 if text else 0), "writer_MB": round(len(text) / 1e6, 2),
            "writer_MB_s": round(len(text) / max(t_write, 1e-9) / 1e6, 1),
-           "note": "file in the page cache (just written): host parse + H2D + pack, not disk reads"}
+           "note": "one file per genome, files in the page cache (just written): host parse + H2D + pack, "
+                   "not disk reads"}
     log("fasta io: %s" % json.dumps(out))
-    return out
-
-
-_IUPAC_FOLD = {c: n for n, cs in ((1, "ACGTU"), (2, "RYSWKM"), (3, "BDHV"), (4, "N")) for c in cs}
-
-
-def _variants(primer: str) -> int:
-    v = 1
-    for c in primer.upper():
-        v *= _IUPAC_FOLD[c]
-    return v
-
-
-def bench_sweep(args, wl, store):
-    """Runtime against primer degeneracy and mismatch tolerance on the genome
-    store (the shape of the paper's degeneracy and mismatch tests): per point
-    the whole path, timed per stage with HIP events on the stream."""
-    import torch
-
-    from paper_2511_00170_amd import ah, synth
-    ex = synth.ExtractSpec(trim=wl.extract.trim, fb_len=wl.extract.fb_len, rb_len=wl.extract.rb_len)
-    total = wl.total_bases
-    stages = ("scan", "pair", "tm", "extract")
-    out = {"metric": "sweep: whole-path time vs primer degeneracy (N bases added, one per primer) and "
-                     "substitutions allowed (k)",
-           "unit": "ms per step", "data": "synthetic", "n_gpus": 1, "steps": args.steps,
-           "workload": "genome: %d seqs x 3-6 Mb, %.2f Gbases, base pair %s / %s, k=%d, clamp %d, FR/RF/FF/RR"
-                       % (wl.n_seqs, total / 1e9, wl.pairs[0].fwd, wl.pairs[0].rev, wl.pairs[0].k,
-                          wl.pairs[0].clamp)}
-    stream = torch.cuda.Stream()
-    for kind in ("degeneracy", "mismatch"):
-        rows = []
-        for x, pair in synth.sweep_pairs(wl.pairs[0], kind):
-            tc = time.perf_counter()
-            ps = ah.PrimerSet([pair], jit=True)
-            t_compile = time.perf_counter() - tc
-            with torch.cuda.stream(stream):
-                pipe = ah.Pipeline(store, ps, wl.orient_mask, wl.tm, ex)
-                pipe.run(stream)
-                n_hits, n_amps, n_bytes = pipe.counts()
-                n_pass = int(pipe.passed[:n_amps].sum().item())
-                pipe.launch(stream)
-                torch.cuda.synchronize()
-                ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
-                      for _ in range(args.steps)]
-                t0 = time.perf_counter()
-                for i in range(args.steps):
-                    ev[i][0].record(stream)
-                    for j, stg in enumerate(stages):
-                        pipe.launch(stream, (stg,))
-                        ev[i][j + 1].record(stream)
-                torch.cuda.synchronize()
-                ms = (time.perf_counter() - t0) * 1e3 / args.steps
-            st_ms = {stg: round(sum(e[j].elapsed_time(e[j + 1]) for e in ev) / args.steps, 4)
-                     for j, stg in enumerate(stages)}
-            alg = BYTES_PER_BASE * total + 12.0 * n_hits
-            row = {("n_N" if kind == "degeneracy" else "k"): x, "fwd": pair.fwd, "rev": pair.rev,
-                   "variants": [_variants(pair.fwd), _variants(pair.rev)], "k": pair.k,
-                   "ms_per_step": round(ms, 4), "gbases_s": round(total / (ms / 1e3) / 1e9, 1), "stage_ms": st_ms,
-                   "scan_hbm_frac": round(alg / (st_ms["scan"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                   "hits": n_hits, "amplicons": n_amps, "passed": n_pass, "jit_compile_s": round(t_compile, 2)}
-            log("sweep %s %s: %s" % (kind, x, json.dumps(row)))
-            rows.append(row)
-            del pipe, ps
-        out[kind] = rows
     return out
 
 

@@ -382,10 +382,14 @@ ah_status ah_read_probe(const void *d_buf, uint64_t bytes, uint32_t *d_out, uint
  * LF, VT, FF, CR) removed; bytes other than A/C/G/T (either case) become N in
  * the store.  Only white space may precede a file's first header.
  *
- * ah_fasta_ingest reads the files once.  The host keeps each record's
- * identifier, source file, length and first block (the layout of
- * ah_pack_layout) and streams the bases through two pinned staging buffers:
- * while the GPU copies and packs one chunk, the host fills the other.  With
+ * ah_fasta_ingest keeps each record's identifier, source file, length and
+ * first block (the layout of ah_pack_layout) on the host and streams the
+ * bases through pinned staging buffers: while the GPU copies and packs one
+ * chunk, the host fills the next.  With one worker (n_threads <= 1, or one
+ * file) the files are read once, in order.  With more, up to n_threads host
+ * threads index the files in parallel, the layout is fixed in file order and
+ * the files are packed in parallel, each worker with its own two staging
+ * buffers and its own part of d_ws (so every file is read twice).  With
  * d_blocks == NULL it only builds the record table (no GPU calls; stream and
  * workspace unused).  The call returns when its GPU work has finished.
  *
@@ -397,17 +401,21 @@ ah_status ah_read_probe(const void *d_buf, uint64_t bytes, uint32_t *d_out, uint
  * can run again with larger arrays.  To finish a store: copy the record
  * table's lengths and first blocks to d_seq_len / d_seq_block0, fill an
  * ah_store with n_blocks from ah_fasta_info, and call ah_pack_finish.
- * Errors: AH_E_ARG (null paths, chunk_bytes outside [4096, 2^30]), AH_E_IO,
- * AH_E_FORMAT, AH_E_WORKSPACE, AH_E_HIP; *out is set only on success.
+ * Errors: AH_E_ARG (null paths, chunk_bytes outside [4096, 2^30]), AH_E_IO
+ * (also: a file changed between the two reads), AH_E_FORMAT, AH_E_WORKSPACE
+ * (smaller than one worker's share; a workspace for fewer workers than
+ * n_threads limits the workers), AH_E_HIP; *out is set only on success.
  * ---------------------------------------------------------------------- */
 typedef struct ah_fasta ah_fasta;  /* record table (host memory, owned by the library) */
 
-/* Device workspace bytes ah_fasta_ingest needs for staging chunks of chunk_bytes. */
+/* Device workspace bytes one ingest worker needs for staging chunks of
+ * chunk_bytes (ah_fasta_ingest with W workers needs W times this). */
 ah_status ah_fasta_ws_size(uint64_t chunk_bytes, uint64_t *bytes);
 
 ah_status ah_fasta_ingest(const char *const *paths, uint32_t n_files, uint32_t *d_blocks, uint64_t blocks_cap,
                           uint32_t *d_nbits, uint64_t *d_counters, uint64_t *d_nlist, uint64_t nlist_cap,
-                          uint64_t chunk_bytes, void *d_ws, uint64_t ws_bytes, void *stream, ah_fasta **out);
+                          uint64_t chunk_bytes, uint32_t n_threads, void *d_ws, uint64_t ws_bytes, void *stream,
+                          ah_fasta **out);
 
 /* Totals of the record table. */
 ah_status ah_fasta_info(const ah_fasta *f, uint32_t *n_records, uint64_t *n_bases, uint64_t *n_blocks,

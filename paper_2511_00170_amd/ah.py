@@ -85,7 +85,8 @@ _sig("ah_unpack", I32, C.POINTER(ah_store), U32, U64, U64, VP, VP)
 _sig("ah_pack_pieces", I32, VP, U64, VP, VP, VP, VP, U32, VP, U64, VP)
 _sig("ah_read_probe", I32, VP, U64, VP, U32, VP)
 _sig("ah_fasta_ws_size", I32, U64, C.POINTER(U64))
-_sig("ah_fasta_ingest", I32, C.POINTER(C.c_char_p), U32, VP, U64, VP, VP, VP, U64, U64, VP, U64, VP, C.POINTER(VP))
+_sig("ah_fasta_ingest", I32, C.POINTER(C.c_char_p), U32, VP, U64, VP, VP, VP, U64, U64, U32, VP, U64, VP,
+     C.POINTER(VP))
 _sig("ah_fasta_info", I32, VP, C.POINTER(U32), C.POINTER(U64), C.POINTER(U64), C.POINTER(U32))
 _sig("ah_fasta_table", I32, VP, VP, VP)
 _sig("ah_fasta_names_of", I32, VP, C.POINTER(ah_fasta_names))
@@ -239,18 +240,25 @@ class Store:
         return st.pack_chunks([(0, buf, off)])
 
     @classmethod
-    def from_fasta(cls, paths: Sequence[str], chunk_bytes: int = 64 << 20, nmask_cap: int = 1 << 16,
-                   blocks_cap: Optional[int] = None, stream=None):
-        """Read FASTA files into a new store in one pass (ah_fasta_ingest);
-        the record table (identifiers, sources, lengths) is ``store.fasta``.
-        Arrays too small for the files are grown and the files read again."""
+    def from_fasta(cls, paths: Sequence[str], chunk_bytes: Optional[int] = None, nmask_cap: int = 1 << 16,
+                   blocks_cap: Optional[int] = None, n_threads: Optional[int] = None, stream=None):
+        """Read FASTA files into a new store (ah_fasta_ingest): one file in one
+        pass, many files by up to n_threads host threads (default: the CPUs
+        this process may use, at most 8); the record table (identifiers,
+        sources, lengths) is ``store.fasta``.  Arrays too small for the files
+        are grown and the files read again."""
         paths = [os.fspath(p) for p in paths]
         size = sum(os.path.getsize(p) for p in paths)
         cap = int(blocks_cap) if blocks_cap is not None else size // 64 + size // 4096 + 64 * len(paths) + 64
+        if n_threads is None:
+            n_threads = min(8, len(os.sched_getaffinity(0)))
+        workers = max(1, min(int(n_threads), len(paths)))
+        if chunk_bytes is None:
+            chunk_bytes = (64 << 20) if workers == 1 else (16 << 20)
         dev = _dev()
         ws_n = U64(0)
         check(_lib.ah_fasta_ws_size(chunk_bytes, C.byref(ws_n)), "ah_fasta_ws_size")
-        ws = torch.empty(int(ws_n.value), dtype=torch.uint8, device=dev)
+        ws = torch.empty(int(ws_n.value) * workers, dtype=torch.uint8, device=dev)
         arr = (C.c_char_p * max(1, len(paths)))(*[os.fsencode(p) for p in paths])
         s = _stream(stream)
         while True:
@@ -260,7 +268,7 @@ class Store:
             nlist = torch.empty((max(nmask_cap, 1), 2), dtype=torch.int64, device=dev)
             h = VP()
             check(_lib.ah_fasta_ingest(arr, len(paths), _p(blocks), cap, _p(nbits), _p(counters), _p(nlist),
-                                       nmask_cap, chunk_bytes, _p(ws), int(ws_n.value), s, C.byref(h)),
+                                       nmask_cap, chunk_bytes, workers, _p(ws), ws.numel(), s, C.byref(h)),
                   "ah_fasta_ingest")
             tab = FastaTable(h)
             n_flag = int(counters[0].item())
@@ -342,13 +350,14 @@ class FastaTable:
             self._h = None
 
 
-def fasta_index(paths: Sequence[str]) -> FastaTable:
-    """Record table of FASTA files without reading them into a store (no GPU)."""
+def fasta_index(paths: Sequence[str], n_threads: int = 1) -> FastaTable:
+    """Record table of FASTA files without reading them into a store (no GPU);
+    many files are indexed by up to n_threads host threads."""
     paths = [os.fspath(p) for p in paths]
     arr = (C.c_char_p * max(1, len(paths)))(*[os.fsencode(p) for p in paths])
     h = VP()
-    check(_lib.ah_fasta_ingest(arr, len(paths), None, 0, None, None, None, 0, 0, None, 0, None, C.byref(h)),
-          "ah_fasta_ingest")
+    check(_lib.ah_fasta_ingest(arr, len(paths), None, 0, None, None, None, 0, 0, int(n_threads), None, 0, None,
+                               C.byref(h)), "ah_fasta_ingest")
     return FastaTable(h)
 
 

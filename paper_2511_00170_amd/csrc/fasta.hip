@@ -9,6 +9,12 @@
 // sequence that does not fit in the rest of a chunk is cut on a 64-base
 // boundary of the sequence, so every piece starts on a store block.
 //
+// Many files (one genome per file is the usual case) are read by several
+// host threads: each file is indexed in parallel, the store layout is fixed
+// in file order, and the files are packed in parallel, each worker with its
+// own staging buffers (pieces carry absolute store blocks, so the order in
+// which they land does not matter).
+//
 // Output follows Supplementary, "Headers and outputs".
 #include <errno.h>
 #include <fcntl.h>
@@ -17,8 +23,10 @@
 #include <sys/stat.h>
 #include <unistd.h>
 
+#include <atomic>
 #include <cmath>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ah.h"
@@ -347,67 +355,173 @@ extern "C" ah_status ah_fasta_ws_size(uint64_t chunk_bytes, uint64_t *bytes) {
     return AH_OK;
 }
 
+namespace {
+
+struct Target {  // where and how a worker packs
+    uint64_t chunk;
+    uint8_t *d_ws;   // this worker's device staging (ah_fasta_ws_size bytes)
+    hipStream_t s;
+    uint32_t *d_blocks;
+    uint64_t blocks_cap;
+    uint32_t *d_nbits;
+    uint64_t *d_counters;
+    uint64_t *d_nlist;
+    uint64_t nlist_cap;
+};
+
+// Set up g for packing into t (pinned staging allocated here).
+ah_status ingest_open(Ingest &g, const Target &t) {
+    g.device = true;
+    g.chunk = t.chunk;
+    g.pcap = (uint32_t)pieces_per_chunk(t.chunk);
+    g.s = t.s;
+    g.d_blocks = t.d_blocks;
+    g.blocks_cap = t.blocks_cap;
+    g.d_nbits = t.d_nbits;
+    g.d_counters = t.d_counters;
+    g.d_nlist = t.d_nlist;
+    g.nlist_cap = t.nlist_cap;
+    const uint64_t a = ah_align_up(g.chunk, 256), b = ah_align_up((uint64_t)g.pcap * sizeof(ah_pack_piece), 256);
+    for (int i = 0; i < 2; i++) {
+        Slot &S = g.slot[i];
+        S.d_buf = t.d_ws + i * (a + b);
+        S.d_pcs = (ah_pack_piece *)(t.d_ws + i * (a + b) + a);
+        if (hipHostMalloc((void **)&S.h_buf, g.chunk, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&S.h_pcs, (uint64_t)g.pcap * sizeof(ah_pack_piece), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipEventCreateWithFlags(&S.ev, hipEventDisableTiming) != hipSuccess)
+            return AH_E_HIP;
+    }
+    return AH_OK;
+}
+
+// Send what is staged, wait for both slots, free the staging.
+ah_status ingest_close(Ingest &g, ah_status ret) {
+    if (!ret) g.submit(g.cur);
+    g.wait(0);
+    g.wait(1);
+    if (!ret) ret = g.err;
+    for (int i = 0; i < 2; i++) {
+        Slot &S = g.slot[i];
+        if (S.h_buf && hipHostFree(S.h_buf) != hipSuccess && !ret) ret = AH_E_HIP;
+        if (S.h_pcs && hipHostFree(S.h_pcs) != hipSuccess && !ret) ret = AH_E_HIP;
+        if (S.ev && hipEventDestroy(S.ev) != hipSuccess && !ret) ret = AH_E_HIP;
+        S.h_buf = nullptr;
+        S.h_pcs = nullptr;
+        S.ev = nullptr;
+    }
+    return ret;
+}
+
+// Run fn(worker) on n host threads (inline when n == 1); first error wins.
+template <class Fn>
+ah_status run_workers(uint32_t n, Fn fn) {
+    std::vector<ah_status> st(n, AH_OK);
+    if (n == 1) {
+        st[0] = fn(0u);
+    } else {
+        std::vector<std::thread> th;
+        for (uint32_t w = 0; w < n; w++) th.emplace_back([&, w] { st[w] = fn(w); });
+        for (auto &t : th) t.join();
+    }
+    for (ah_status e : st)
+        if (e) return e;
+    return AH_OK;
+}
+
+// Append part's records (one file, blocks numbered from 0) to f.
+void append_part(ah_fasta *f, const ah_fasta &part) {
+    const uint64_t base = f->n_blocks, id0 = f->ids.size();
+    for (size_t r = 0; r < part.len.size(); r++) {
+        f->len.push_back(part.len[r]);
+        f->block0.push_back(base + part.block0[r]);
+        f->file.push_back(part.file[r]);
+        f->id_off.push_back(id0 + part.id_off[r]);
+    }
+    f->ids.append(part.ids);
+    f->n_blocks += part.n_blocks;
+    f->n_bases += part.n_bases;
+    if (part.max_len > f->max_len) f->max_len = part.max_len;
+}
+
+}  // namespace
+
 extern "C" ah_status ah_fasta_ingest(const char *const *paths, uint32_t n_files, uint32_t *d_blocks,
                                      uint64_t blocks_cap, uint32_t *d_nbits, uint64_t *d_counters, uint64_t *d_nlist,
-                                     uint64_t nlist_cap, uint64_t chunk_bytes, void *d_ws, uint64_t ws_bytes,
-                                     void *stream, ah_fasta **out) {
+                                     uint64_t nlist_cap, uint64_t chunk_bytes, uint32_t n_threads, void *d_ws,
+                                     uint64_t ws_bytes, void *stream, ah_fasta **out) {
     if (!out || (n_files && !paths)) return AH_E_ARG;
     for (uint32_t i = 0; i < n_files; i++)
         if (!paths[i]) return AH_E_ARG;
-    Ingest g;
-    g.device = d_blocks != nullptr;
-    if (g.device) {
-        uint64_t need = 0;
-        if (ah_fasta_ws_size(chunk_bytes, &need)) return AH_E_ARG;
+    const bool device = d_blocks != nullptr;
+    uint32_t workers = n_threads ? n_threads : 1;
+    if (workers > n_files) workers = n_files ? n_files : 1;
+    if (workers > 64) workers = 64;
+    uint64_t per_ws = 0;
+    if (device) {
+        if (ah_fasta_ws_size(chunk_bytes, &per_ws)) return AH_E_ARG;
         if (!d_nbits || !d_counters || (nlist_cap && !d_nlist) || !d_ws) return AH_E_ARG;
-        if (ws_bytes < need) return AH_E_WORKSPACE;
-        g.chunk = chunk_bytes;
-        g.pcap = (uint32_t)pieces_per_chunk(chunk_bytes);
-        g.s = ah_stream(stream);
-        g.d_blocks = d_blocks;
-        g.blocks_cap = blocks_cap;
-        g.d_nbits = d_nbits;
-        g.d_counters = d_counters;
-        g.d_nlist = d_nlist;
-        g.nlist_cap = nlist_cap;
+        if (ws_bytes < per_ws) return AH_E_WORKSPACE;
+        if (ws_bytes < per_ws * workers) workers = (uint32_t)(ws_bytes / per_ws);  // as many as the workspace holds
     }
+    Target t{chunk_bytes, (uint8_t *)d_ws, ah_stream(stream), d_blocks, blocks_cap, d_nbits, d_counters, d_nlist,
+             nlist_cap};
     ah_fasta *f = new ah_fasta();
-    g.f = f;
     for (uint32_t i = 0; i < n_files; i++) f->files.push_back(base_name(paths[i]));
-    std::vector<uint8_t> rb(kReadBytes);
     ah_status ret = AH_OK;
-    if (g.device) {
-        const uint64_t a = ah_align_up(g.chunk, 256), b = ah_align_up((uint64_t)g.pcap * sizeof(ah_pack_piece), 256);
-        for (int i = 0; i < 2 && !ret; i++) {
-            Slot &S = g.slot[i];
-            S.d_buf = (uint8_t *)d_ws + i * (a + b);
-            S.d_pcs = (ah_pack_piece *)((uint8_t *)d_ws + i * (a + b) + a);
-            if (hipHostMalloc((void **)&S.h_buf, g.chunk, hipHostMallocDefault) != hipSuccess ||
-                hipHostMalloc((void **)&S.h_pcs, (uint64_t)g.pcap * sizeof(ah_pack_piece), hipHostMallocDefault) !=
-                    hipSuccess ||
-                hipEventCreateWithFlags(&S.ev, hipEventDisableTiming) != hipSuccess)
-                ret = AH_E_HIP;
+    if (device) {
+        ah_fill<uint32_t>(d_nbits, 0u, (blocks_cap + 31) / 32, t.s);
+        ah_fill<uint64_t>(d_counters, 0ull, AH_STORE_SCRATCH, t.s);
+        if (hipGetLastError() != hipSuccess) ret = AH_E_HIP;
+    }
+    if (!ret && workers <= 1) {
+        // one pass: parse, stage and pack every file in order
+        Ingest g;
+        g.f = f;
+        std::vector<uint8_t> rb(kReadBytes);
+        if (device) ret = ingest_open(g, t);
+        for (uint32_t i = 0; i < n_files && !ret; i++) ret = g.file(paths[i], i, rb.data());
+        if (device) ret = ingest_close(g, ret);
+    } else if (!ret) {
+        // index every file in parallel, fix the layout in file order, pack in parallel
+        std::vector<ah_fasta> parts(n_files);
+        std::atomic<uint32_t> next{0};
+        ret = run_workers(workers, [&](uint32_t) -> ah_status {
+            std::vector<uint8_t> rb(kReadBytes);
+            for (uint32_t i; (i = next.fetch_add(1)) < n_files;) {
+                Ingest g;
+                g.f = &parts[i];
+                const ah_status e = g.file(paths[i], i, rb.data());
+                if (e) return e;
+            }
+            return AH_OK;
+        });
+        std::vector<uint64_t> base(n_files, 0);
+        for (uint32_t i = 0; i < n_files && !ret; i++) {
+            base[i] = f->n_blocks;
+            append_part(f, parts[i]);
+            if (f->len.size() >= 0xFFFFFFFFull) ret = AH_E_FORMAT;
         }
-        if (!ret) {
-            ah_fill<uint32_t>(d_nbits, 0u, (blocks_cap + 31) / 32, g.s);
-            ah_fill<uint64_t>(d_counters, 0ull, AH_STORE_SCRATCH, g.s);
-            if (hipGetLastError() != hipSuccess) ret = AH_E_HIP;
+        if (!ret && device) {
+            std::atomic<uint32_t> next2{0};
+            ret = run_workers(workers, [&](uint32_t w) -> ah_status {
+                Target tw = t;
+                tw.d_ws = t.d_ws + (uint64_t)w * per_ws;
+                Ingest g;
+                std::vector<uint8_t> rb(kReadBytes);
+                ah_status e = ingest_open(g, tw);
+                for (uint32_t i; !e && (i = next2.fetch_add(1)) < n_files;) {
+                    ah_fasta scratch;
+                    scratch.n_blocks = base[i];  // records numbered from the file's first block
+                    g.f = &scratch;
+                    e = g.file(paths[i], i, rb.data());
+                    if (!e && scratch.n_blocks - base[i] != parts[i].n_blocks) e = AH_E_IO;  // file changed
+                }
+                return ingest_close(g, e);
+            });
         }
     }
-    for (uint32_t i = 0; i < n_files && !ret; i++) ret = g.file(paths[i], i, rb.data());
-    if (g.device) {
-        if (!ret) g.submit(g.cur);
-        g.wait(0);
-        g.wait(1);
-        if (!ret) ret = g.err;
-        if (hipStreamSynchronize(g.s) != hipSuccess && !ret) ret = AH_E_HIP;
-        for (int i = 0; i < 2; i++) {
-            Slot &S = g.slot[i];
-            if (S.h_buf && hipHostFree(S.h_buf) != hipSuccess && !ret) ret = AH_E_HIP;
-            if (S.h_pcs && hipHostFree(S.h_pcs) != hipSuccess && !ret) ret = AH_E_HIP;
-            if (S.ev && hipEventDestroy(S.ev) != hipSuccess && !ret) ret = AH_E_HIP;
-        }
-    }
+    if (device && hipStreamSynchronize(t.s) != hipSuccess && !ret) ret = AH_E_HIP;
     if (ret) {
         delete f;
         return ret;

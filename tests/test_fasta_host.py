@@ -58,7 +58,8 @@ def _check_table(tab, paths):
     assert tab.max_len == max([len(s) for _, _, s in want], default=0)
 
 
-def test_record_table_matches_oracle(tmp_path):
+@pytest.mark.parametrize("n_threads", [1, 4])
+def test_record_table_matches_oracle(tmp_path, n_threads):
     rng = np.random.default_rng(7)
     paths = []
     for k in range(4):
@@ -68,7 +69,7 @@ def test_record_table_matches_oracle(tmp_path):
     empty = str(tmp_path / "empty.fa")
     open(empty, "wb").close()
     paths.insert(2, empty)
-    _check_table(ah.fasta_index(paths), paths)
+    _check_table(ah.fasta_index(paths, n_threads=n_threads), paths)
 
 
 def test_record_table_across_read_buffers(tmp_path):
@@ -91,6 +92,15 @@ def test_record_table_errors(tmp_path):
     with pytest.raises(ah.AhError) as e:
         ah.fasta_index([str(tmp_path / "missing.fa")])
     assert e.value.status == ah.AH_E_IO
+    good = tmp_path / "good.fa"
+    good.write_bytes(b">a\nACGT\n")
+    for n_threads in (1, 3):                     # an error in any file, any worker
+        with pytest.raises(ah.AhError) as e:
+            ah.fasta_index([str(good), str(tmp_path / "missing.fa"), str(good)], n_threads=n_threads)
+        assert e.value.status == ah.AH_E_IO
+        with pytest.raises(ah.AhError) as e:
+            ah.fasta_index([str(good), str(good), str(bad)], n_threads=n_threads)
+        assert e.value.status == ah.AH_E_FORMAT
     assert ah.fasta_index([]).n_records == 0
 
 

@@ -63,12 +63,13 @@ def _same_store(a, b):
     assert torch.equal(a.seq_block0[:a.n_seqs], b.seq_block0[:b.n_seqs])
 
 
+@pytest.mark.parametrize("n_threads", [1, 4])
 @pytest.mark.parametrize("chunk,tiny", [(4096, False), (4096, True), (64 << 20, False)])
-def test_ingest_equals_pack_and_oracle(ah, tmp_path, chunk, tiny):
+def test_ingest_equals_pack_and_oracle(ah, tmp_path, chunk, tiny, n_threads):
     rng = np.random.default_rng(chunk % 1000 + tiny)
-    paths = _files(tmp_path, rng, 3, 400 if tiny else 25, 20000, tiny)
-    _say("fasta ingest chunk", chunk, "tiny", tiny)
-    st = ah.Store.from_fasta(paths, chunk_bytes=chunk)
+    paths = _files(tmp_path, rng, 5, 300 if tiny else 20, 20000, tiny)
+    _say("fasta ingest chunk", chunk, "tiny", tiny, "threads", n_threads)
+    st = ah.Store.from_fasta(paths, chunk_bytes=chunk, n_threads=n_threads)
     recs = of.read_fasta(paths)
     ref = ah.Store.from_ascii([s for _, _, s in recs])
     _same_store(st, ref)
@@ -83,8 +84,9 @@ def test_ingest_grows_small_arrays(ah, tmp_path):
     _say("fasta ingest regrow")
     recs = of.read_fasta(paths)
     ref = ah.Store.from_ascii([s for _, _, s in recs])
-    st = ah.Store.from_fasta(paths, chunk_bytes=8192, blocks_cap=10, nmask_cap=2)
-    _same_store(st, ref)
+    for n_threads in (1, 2):
+        st = ah.Store.from_fasta(paths, chunk_bytes=8192, blocks_cap=10, nmask_cap=2, n_threads=n_threads)
+        _same_store(st, ref)
 
 
 def test_ingest_large_file(ah, tmp_path):
