@@ -64,6 +64,39 @@ struct DPair {
 
 __device__ __forceinline__ uint32_t ah_lane() { return __lane_id(); }
 
+// Load through a pointer marked global.  A pointer made from an integer is
+// generic and compiles to a FLAT load, which also counts against the LDS
+// counter: every later wait for an LDS or cross-lane result would then wait
+// for that load too, so a load issued one tile ahead would not overlap.
+// uint4 goes through a plain vector type (its class type cannot be copied
+// out of an address-space-qualified object).
+typedef uint32_t ah_v4u __attribute__((ext_vector_type(4)));
+template <typename T>
+struct AhLoadAs {
+    typedef T raw;
+    __device__ static T cvt(raw v) { return v; }
+};
+template <>
+struct AhLoadAs<uint4> {
+    typedef ah_v4u raw;
+    __device__ static uint4 cvt(ah_v4u v) { return make_uint4(v.x, v.y, v.z, v.w); }
+};
+template <typename T>
+__device__ __forceinline__ T ah_ldg(const void *p) {
+    return AhLoadAs<T>::cvt(*(const __attribute__((address_space(1))) typename AhLoadAs<T>::raw *)p);
+}
+template <typename T>
+__device__ __forceinline__ T ah_ldg(uint64_t addr) {
+    return ah_ldg<T>((const void *)addr);
+}
+// Load from LDS through a pointer marked local (p must point into LDS).  With
+// one load per address space, a choice between an LDS and a global record
+// stays two loads instead of being merged into one FLAT load of either.
+template <typename T>
+__device__ __forceinline__ T ah_lds(const void *p) {
+    return AhLoadAs<T>::cvt(*(const __attribute__((address_space(3))) typename AhLoadAs<T>::raw *)p);
+}
+
 __device__ __forceinline__ uint32_t ah_mbcnt(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }

@@ -48,12 +48,21 @@ struct GenericFilter {
 #pragma unroll
         for (int x = 0; x < 4; x++) {
             const uint32_t X = 4 * g + (uint32_t)x;
-            const DPat *P = X < n_lds ? &sPat[X] : &gPat[X];
-            const uint32_t meta = __builtin_amdgcn_readfirstlane(P->meta);
+            uint32_t meta, f0, f1;
+            if (X < n_lds) {
+                meta = ah_lds<uint32_t>(&sPat[X].meta);
+                f0 = ah_lds<uint32_t>(&sPat[X].fcode[0]);
+                f1 = ah_lds<uint32_t>(&sPat[X].fcode[4]);
+            } else {
+                meta = ah_ldg<uint32_t>(&gPat[X].meta);
+                f0 = ah_ldg<uint32_t>(&gPat[X].fcode[0]);
+                f1 = ah_ldg<uint32_t>(&gPat[X].fcode[4]);
+            }
+            meta = __builtin_amdgcn_readfirstlane(meta);
+            f0 = __builtin_amdgcn_readfirstlane(f0);
+            f1 = __builtin_amdgcn_readfirstlane(f1);
             // positions past a pattern's own W read as N (every base matches)
             const uint32_t wx = (meta >> 16) & 0xFFu;
-            const uint32_t f0 = __builtin_amdgcn_readfirstlane(*(const uint32_t *)&P->fcode[0]);
-            const uint32_t f1 = __builtin_amdgcn_readfirstlane(*(const uint32_t *)&P->fcode[4]);
             const uint64_t all = ((uint64_t)f1 << 32) | f0;
             const uint64_t keep = wx >= 8 ? ~0ull : ((1ull << (8 * wx)) - 1);
             const uint64_t codes = (all & keep) | (0x0F0F0F0F0F0F0F0Full & ~keep);

@@ -174,12 +174,12 @@ __device__ __forceinline__ void tile_issue(const ScanArgs &a, const SeqCursor &c
     for (int b = 0; b < AH_BPL; b++) {
         uint32_t own = AH_BPL * lane + b;
         own = own < L.nb ? own : L.nb - 1;
-        L.blk[b] = *(const uint4 *)(base + 16u * (own + 1));
+        L.blk[b] = ah_ldg<uint4>(base + 16u * (own + 1));
     }
     uint32_t o_hal = (AH_BPL * lane < L.nb ? AH_BPL * lane : L.nb - 1) + 1;
     if (lane == 0 && L.rel0 != 0) o_hal = 0;
     if (lane == 63 && L.rel0 + AH_TILE_BLOCKS < c.nblk) o_hal = AH_TILE_BLOCKS + 1;
-    L.hal = *(const uint4 *)(base + 16u * o_hal);
+    L.hal = ah_ldg<uint4>(base + 16u * o_hal);
     // N-bitmap words from wb = max(gb0/32, 1) - 1 cover blocks gb0-1 ..
     // gb0+AH_TILE_BLOCKS.  A nonzero word means the tile may touch an N -- a
     // superset, which only costs exact per-block lookups in verification.
@@ -189,8 +189,10 @@ __device__ __forceinline__ void tile_issue(const ScanArgs &a, const SeqCursor &c
     const uint32_t room = (uint32_t)(nw - 1 - wb);  // words after wb
     uint32_t wi = lane < AH_NBW - 1 ? lane : AH_NBW - 1;
     wi = wi < room ? wi : room;
-    L.nbw = *(const uint32_t *)((uint64_t)a.st.d_nbits + 4u * (uint64_t)wb + 4u * wi);
+    L.nbw = ah_ldg<uint32_t>((uint64_t)a.st.d_nbits + 4u * (uint64_t)wb + 4u * wi);
 }
+
+typedef __attribute__((address_space(3))) uint32_t ah_lds_u32;
 
 // A wave's hit buffer in LDS: records and the count of hits accepted since
 // the last write-out (those past AH_HCAP went to global memory directly).
@@ -233,11 +235,11 @@ __device__ __forceinline__ void ah_pattern_record(const ScanArgs &a, const DPat 
     // in the verification path would have to wait for the next tile's
     // prefetch as well (the vector memory counter is in order).
     if (kLdsOnly || X < n_lds) {
-        p0 = *(const uint4 *)&sPat[X].P[0];
-        p1 = *(const uint4 *)&sPat[X].clampmask;
+        p0 = ah_lds<uint4>(&sPat[X].P[0]);
+        p1 = ah_lds<uint4>(&sPat[X].clampmask);
     } else {
-        p0 = *(const uint4 *)&a.pats[X].P[0];
-        p1 = *(const uint4 *)&a.pats[X].clampmask;
+        p0 = ah_ldg<uint4>(&a.pats[X].P[0]);
+        p1 = ah_ldg<uint4>(&a.pats[X].clampmask);
     }
 }
 
@@ -294,9 +296,12 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
                 const uint32_t pos = (uint32_t)((int64_t)c.pos0 + pl), w2 = p1.w | (nmm << 24);
                 const uint32_t slot = atomicAdd(hb.n, 1u);  // LDS
                 if (slot < AH_HCAP) {
-                    hb.rec[slot][0] = c.seq;
-                    hb.rec[slot][1] = pos;
-                    hb.rec[slot][2] = w2;
+                    // through an LDS-qualified pointer: a generic one becomes
+                    // a FLAT store, which makes every later wait a full drain
+                    ah_lds_u32 *r = (ah_lds_u32 *)&hb.rec[slot][0];
+                    r[0] = c.seq;
+                    r[1] = pos;
+                    r[2] = w2;
                 } else {  // buffer full: straight to the hit array
                     const uint64_t h = atomicAdd((unsigned long long *)a.n_hits, 1ull);
                     if (h < a.hit_cap) {
