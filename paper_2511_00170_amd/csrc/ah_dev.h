@@ -30,6 +30,9 @@ typedef __hip_internal::int64_t int64_t;
 #define AH_MAXL 32
 // Variants per primer the Tm kernel will enumerate.
 #define AH_MAX_VARIANTS (1u << 24)
+// Variants per primer tabulated in its record (one load per variant in the
+// Tm kernel instead of a walk over the degenerate positions).
+#define AH_VARTAB 64
 
 // One oriented pattern: pair q, kind (bit0 reverse primer, bit1 minus strand).
 struct alignas(16) DPat {
@@ -54,7 +57,26 @@ struct DPrimer {
     uint8_t deg_pos[AH_MAXL];
     uint8_t deg_n[AH_MAXL];
     uint8_t deg_base[AH_MAXL][4];
+    uint64_t var[AH_VARTAB];  // codes of variants 0..D-1 when D <= AH_VARTAB (else enumerated on the fly)
 };
+
+// Variant v of a degenerate primer as 2-bit codes (base j at bits 2j): v in
+// mixed radix over the degenerate positions, the last one varying fastest.
+// The host fills DPrimer::var with it, the Tm kernel calls it past the table.
+__host__ __device__ inline uint64_t primer_variant(const DPrimer &P, uint64_t base, uint32_t v) {
+    uint64_t V = base;
+    for (int d = P.n_deg - 1; d >= 0; d--) {
+        const uint32_t n = P.deg_n[d];
+        uint32_t q, digit;
+        if (n == 2) { q = v >> 1; digit = v & 1u; }
+        else if (n == 4) { q = v >> 2; digit = v & 3u; }
+        else { q = v / 3u; digit = v - 3u * q; }
+        v = q;
+        const int pos = P.deg_pos[d];
+        V = (V & ~(3ull << (2 * pos))) | ((uint64_t)P.deg_base[d][digit] << (2 * pos));
+    }
+    return V;
+}
 
 struct DPair {
     uint32_t min_len, max_len;
@@ -63,6 +85,10 @@ struct DPair {
 };
 
 __device__ __forceinline__ uint32_t ah_lane() { return __lane_id(); }
+
+// Letter of 2-bit code c (0..3 = A, C, G, T) from a packed constant: indexing
+// a string literal instead is a dependent global load per byte.
+__device__ __forceinline__ char ah_letter(uint32_t c) { return (char)((0x54474341u >> (8u * c)) & 0xFFu); }
 
 // Load through a pointer marked global.  A pointer made from an integer is
 // generic and compiles to a FLAT load, which also counts against the LDS

@@ -46,6 +46,17 @@ static inline uint32_t ah_device_cus() {
     return (uint32_t)cus;
 }
 
+// Workgroups of `kernel` (block threads, no dynamic LDS) resident at once on
+// the current device: the grid of a grid-stride kernel beyond this only adds
+// dispatch work (its extra waves find nothing to do).
+template <typename K>
+static inline uint32_t ah_resident_wgs(K kernel, int block) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 1;
+    return (uint32_t)per_cu * ah_device_cus();
+}
+
 static inline uint64_t ah_align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // Device table layout inside one buffer: patterns first, then pair records.
 static inline uint64_t ah_pat_bytes(uint32_t n_pairs) { return ah_align_up(4ull * n_pairs * sizeof(DPat), 256); }

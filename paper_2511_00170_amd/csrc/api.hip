@@ -114,6 +114,8 @@ static void make_primer(const int *m, int L, DPrimer *p) {
         if (D > AH_MAX_VARIANTS) D = (uint64_t)AH_MAX_VARIANTS + 1;
     }
     p->D = D > AH_MAX_VARIANTS ? 0u : (uint32_t)D;  // 0: too many variants for Tm
+    if (p->D && p->D <= AH_VARTAB)
+        for (uint32_t v = 0; v < p->D; v++) p->var[v] = primer_variant(*p, p->base, v);
 }
 
 // Build the primer set's host tables; unless host_only, also its device tables.

@@ -49,40 +49,60 @@ __device__ __forceinline__ char base_at(const ah_store &st, uint64_t b0, uint64_
     uint32_t c = (((h >> (bit & 31)) & 1u) << 1) | ((l >> (bit & 31)) & 1u);
     if ((ah_block_nmask(st, b) >> bit) & 1ull) return 'N';
     if (rc) c ^= 3u;
-    return "ACGT"[c];
+    return ah_letter(c);
 }
 
-// Bases [a0, a1) of a sequence (first block b0) to out[dst0 ..], forward or
-// (rc) reverse-complemented: out[j] = comp(s[a1 - 1 - j]).  Whole wave.  The
-// span's blocks and their N masks are staged in LDS 64 at a time (one block
-// per lane, all loads in flight together); every output byte is then decoded
-// from LDS, consecutive lanes writing consecutive bytes.
+// Base at sequence position p from blocks staged in LDS (block p/64 at
+// sblk[p/64 - cb]): 'A','C','G','T' or 'N', complemented when rc.
+__device__ __forceinline__ char staged_base(const uint4 *sblk, const uint64_t *snm, uint64_t cb, uint64_t p, bool rc) {
+    const uint32_t k = (uint32_t)((p >> 6) - cb), bit = (uint32_t)(p & 63);
+    const uint4 w = sblk[k];
+    const uint32_t h = bit < 32 ? w.x : w.z, l = bit < 32 ? w.y : w.w;
+    uint32_t c = (((h >> (bit & 31)) & 1u) << 1) | ((l >> (bit & 31)) & 1u);
+    if (rc) c ^= 3u;
+    return ((snm[k] >> bit) & 1ull) ? 'N' : ah_letter(c);
+}
+
+// Stage blocks [cb, ce) (at most 64) of a sequence (first block b0) and their
+// N masks in LDS: one block per lane, all loads in flight together.  Whole
+// wave; the caller's previous reads of the staging area must be done.
+__device__ __forceinline__ void stage_blocks(const ah_store &st, uint64_t b0, uint64_t cb, uint64_t ce, uint4 *sblk,
+                                             uint64_t *snm) {
+    const uint32_t lane = ah_lane();
+    ah_wave_sync();
+    if (cb + lane < ce) {
+        const uint64_t gb = b0 + cb + lane;
+        sblk[lane] = ah_ldg<uint4>(st.d_blocks + 4 * gb);
+        snm[lane] = ah_block_nmask(st, gb);
+    }
+    ah_wave_sync();
+}
+
+// Output bytes j in [j0, j1) of the span [a0, a1), forward or (rc) reverse-
+// complemented (out[j] = comp(s[a1 - 1 - j])), decoded from blocks staged
+// from block cb on; consecutive lanes write consecutive bytes.  Whole wave.
+__device__ __forceinline__ void write_staged(const uint4 *sblk, const uint64_t *snm, uint64_t cb, uint64_t a0,
+                                             uint64_t a1, bool rc, uint64_t j0, uint64_t j1, char *out, uint64_t dst0,
+                                             uint64_t seq_cap) {
+    for (uint64_t j = j0 + ah_lane(); j < j1; j += 64) {
+        const uint64_t p = rc ? a1 - 1 - j : a0 + j;
+        if (dst0 + j < seq_cap) out[dst0 + j] = staged_base(sblk, snm, cb, p, rc);
+    }
+}
+
+// Bases [a0, a1) of a sequence (first block b0) to out[dst0 ..], for spans
+// of any length: staged 64 blocks at a time.  Whole wave.
 __device__ __forceinline__ void copy_span(const ah_store &st, uint64_t b0, uint64_t a0, uint64_t a1, bool rc,
                                           char *out, uint64_t dst0, uint64_t seq_cap, uint4 *sblk, uint64_t *snm) {
-    const uint32_t lane = ah_lane();
     if (a1 <= a0) return;
     const uint64_t bs = a0 >> 6, be = ((a1 - 1) >> 6) + 1;  // blocks of the span, sequence-relative
     for (uint64_t cb = bs; cb < be; cb += 64) {
         const uint64_t ce = cb + 64 < be ? cb + 64 : be;
-        ah_wave_sync();  // the previous chunk's bytes are written
-        if (cb + lane < ce) {
-            const uint64_t gb = b0 + cb + lane;
-            sblk[lane] = ((const uint4 *)st.d_blocks)[gb];
-            snm[lane] = ah_block_nmask(st, gb);
-        }
-        ah_wave_sync();
+        stage_blocks(st, b0, cb, ce, sblk, snm);
         // the chunk's positions inside the span, and their output indices
         const uint64_t p0 = cb * 64 > a0 ? cb * 64 : a0, p1 = ce * 64 < a1 ? ce * 64 : a1;
         const uint64_t j0 = rc ? a1 - p1 : p0 - a0, j1 = rc ? a1 - p0 : p1 - a0;
-        for (uint64_t j = j0 + lane; j < j1; j += 64) {
-            const uint64_t p = rc ? a1 - 1 - j : a0 + j;
-            const uint32_t k = (uint32_t)((p >> 6) - cb), bit = (uint32_t)(p & 63);
-            const uint4 w = sblk[k];
-            const uint32_t h = bit < 32 ? w.x : w.z, l = bit < 32 ? w.y : w.w;
-            uint32_t c = (((h >> (bit & 31)) & 1u) << 1) | ((l >> (bit & 31)) & 1u);
-            if (rc) c ^= 3u;
-            if (dst0 + j < seq_cap) out[dst0 + j] = ((snm[k] >> bit) & 1ull) ? 'N' : "ACGT"[c];
-        }
+        write_staged(sblk, snm, cb, a0, a1, rc, j0, j1, out, dst0, seq_cap);
     }
 }
 
@@ -174,14 +194,6 @@ __global__ void __launch_bounds__(256) ah_extract_write_kernel(ah_store st, cons
         }
         if (!on) f1 = f0, r1 = r0;
         const uint32_t nf = (uint32_t)(f1 - f0), nr = (uint32_t)(r1 - r0);
-        for (uint32_t j = lane; j < o.fb_len; j += 64)
-            fb[i * o.fb_len + j] = j < nf ? base_at(st, b0, rc ? f1 - 1 - j : f0 + j, rc) : 0;
-        for (uint32_t j = lane; j < o.rb_len; j += 64)
-            rb[i * o.rb_len + j] = j < nr ? base_at(st, b0, rc ? r1 - 1 - j : r0 + j, rc) : 0;
-        if (lane == 0) {
-            bc_len[2 * i] = (uint8_t)nf;
-            bc_len[2 * i + 1] = (uint8_t)nr;
-        }
         // primer snippets: upstream site as read, downstream site reverse-complemented
         char *left_dst = (g.lp == 0) ? fpr + 32 * i : rpr + 32 * i;
         char *right_dst = (g.rp == 1) ? rpr + 32 * i : fpr + 32 * i;
@@ -189,6 +201,42 @@ __global__ void __launch_bounds__(256) ah_extract_write_kernel(ah_store st, cons
             left_dst = fpr + 32 * i;
             right_dst = rpr + 32 * i;
         }
+        if (lane == 0) {
+            bc_len[2 * i] = (uint8_t)nf;
+            bc_len[2 * i + 1] = (uint8_t)nr;
+        }
+        uint64_t a0, a1;
+        amp_span(g, o.trim, &a0, &a1);
+        // Everything read lies in [start - barcode, end + barcode): when that
+        // window spans at most 64 blocks it is staged once and every byte is
+        // decoded from LDS; otherwise per-base loads and chunked staging.
+        const uint64_t pl1 = (uint64_t)g.start + g.Ll, pr0 = (uint64_t)g.end - g.Lr;  // primer sites
+        uint64_t lo = f0 < r0 ? f0 : r0, hi = f1 > r1 ? f1 : r1;
+        lo = lo < g.start ? lo : g.start;
+        lo = lo < pr0 ? lo : pr0;
+        hi = hi > g.end ? hi : g.end;
+        hi = hi > pl1 ? hi : pl1;
+        const uint64_t cb = lo >> 6, ce = hi > lo ? ((hi - 1) >> 6) + 1 : cb;
+        uint4 *sblk = s_blk[threadIdx.x >> 6];
+        uint64_t *snm = s_nm[threadIdx.x >> 6];
+        if (on && ce - cb <= 64) {
+            stage_blocks(st, b0, cb, ce, sblk, snm);
+            for (uint32_t j = lane; j < o.fb_len; j += 64)
+                fb[i * o.fb_len + j] = j < nf ? staged_base(sblk, snm, cb, rc ? f1 - 1 - j : f0 + j, rc) : 0;
+            for (uint32_t j = lane; j < o.rb_len; j += 64)
+                rb[i * o.rb_len + j] = j < nr ? staged_base(sblk, snm, cb, rc ? r1 - 1 - j : r0 + j, rc) : 0;
+            if (lane < 32)
+                left_dst[lane] = lane < g.Ll ? staged_base(sblk, snm, cb, (uint64_t)g.start + lane, false) : 0;
+            else
+                right_dst[lane - 32] =
+                    lane - 32 < g.Lr ? staged_base(sblk, snm, cb, (uint64_t)g.end - 1 - (lane - 32), true) : 0;
+            if (a1 > a0) write_staged(sblk, snm, cb, a0, a1, rc, 0, a1 - a0, out, seq_off[i], seq_cap);
+            continue;
+        }
+        for (uint32_t j = lane; j < o.fb_len; j += 64)
+            fb[i * o.fb_len + j] = j < nf ? base_at(st, b0, rc ? f1 - 1 - j : f0 + j, rc) : 0;
+        for (uint32_t j = lane; j < o.rb_len; j += 64)
+            rb[i * o.rb_len + j] = j < nr ? base_at(st, b0, rc ? r1 - 1 - j : r0 + j, rc) : 0;
         if (lane < 32) {
             left_dst[lane] = (on && lane < g.Ll) ? base_at(st, b0, (uint64_t)g.start + lane, false) : 0;
         } else {
@@ -196,9 +244,7 @@ __global__ void __launch_bounds__(256) ah_extract_write_kernel(ah_store st, cons
             right_dst[j] = (on && j < g.Lr) ? base_at(st, b0, (uint64_t)g.end - 1 - j, true) : 0;
         }
         if (!on) continue;
-        uint64_t a0, a1;
-        amp_span(g, o.trim, &a0, &a1);
-        copy_span(st, b0, a0, a1, rc, out, seq_off[i], seq_cap, s_blk[threadIdx.x >> 6], s_nm[threadIdx.x >> 6]);
+        copy_span(st, b0, a0, a1, rc, out, seq_off[i], seq_cap, sblk, snm);
     }
 }
 
@@ -255,8 +301,9 @@ extern "C" ah_status ah_extract(const ah_store *st, ah_primer_set ps, const ah_a
                            (const uint64_t *)w.total, d_seq_off, d_n_bytes);
     }
     if (amp_cap) {
-        uint64_t wgs = (amp_cap + 3) / 4;
-        if (wgs > 16384) wgs = 16384;
+        uint64_t wgs = (amp_cap + 3) / 4;  // one wave per amplicon, at most the resident grid
+        const uint64_t resident = ah_resident_wgs(ah_extract_write_kernel, 256);
+        if (wgs > resident) wgs = resident;
         hipLaunchKernelGGL(ah_extract_write_kernel, dim3((unsigned)wgs), dim3(256), 0, s, *st,
                            (const uint32_t *)d_amps, d_n_amps, amp_cap, (const DPair *)ps->d_pairs, d_pass, *o,
                            (const uint64_t *)d_seq_off, d_seq, seq_cap, d_fb, d_rb, d_bc_len, d_fprimer, d_rprimer);

@@ -182,7 +182,7 @@ __global__ void ah_unpack_kernel(ah_store st, uint32_t seq, uint64_t start, uint
         const uint32_t h = bit < 32 ? w.x : w.z, l = bit < 32 ? w.y : w.w;
         const uint32_t c = (((h >> (bit & 31)) & 1u) << 1) | ((l >> (bit & 31)) & 1u);
         const uint64_t nm = ah_block_nmask(st, b);
-        out[i] = ((nm >> bit) & 1ull) ? 'N' : "ACGT"[c];
+        out[i] = ((nm >> bit) & 1ull) ? 'N' : ah_letter(c);
     }
 }
 

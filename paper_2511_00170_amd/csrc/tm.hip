@@ -197,7 +197,10 @@ __host__ __device__ inline int tm_salt_setup(const ah_tm_params &p, TmConst *k) 
     return 0;
 }
 
-__device__ TmConst tm_const(const ah_tm_params &p) {
+// Computed once on the host and passed to the kernels by value: the
+// constants then sit in scalar registers instead of a dozen FP64 values per
+// lane, and no lane evaluates the logarithms.
+__host__ __device__ inline TmConst tm_const(const ah_tm_params &p) {
     TmConst k;
     (void)tm_salt_setup(p, &k);
     const double hiC = p.dnac1_nM > p.dnac2_nM ? p.dnac1_nM : p.dnac2_nM;
@@ -319,29 +322,13 @@ __device__ __forceinline__ uint64_t reverse_codes(uint64_t G, int L) {
     return r >> (64 - 2 * L);
 }
 
-// Variant v of a degenerate primer as 2-bit codes.
-__device__ __forceinline__ uint64_t primer_variant(const DPrimer &P, uint64_t base, uint32_t v) {
-    uint64_t V = base;
-    for (int d = P.n_deg - 1; d >= 0; d--) {
-        const uint32_t n = P.deg_n[d];
-        uint32_t q, digit;
-        if (n == 2) { q = v >> 1; digit = v & 1u; }
-        else if (n == 4) { q = v >> 2; digit = v & 3u; }
-        else { q = v / 3u; digit = v - 3u * q; }
-        v = q;
-        const int pos = P.deg_pos[d];
-        V = (V & ~(3ull << (2 * pos))) | ((uint64_t)P.deg_base[d][digit] << (2 * pos));
-    }
-    return V;
-}
-
 __device__ __forceinline__ uint64_t primer_base_codes(const DPrimer &P) { return P.base; }
 
 // Sites packed lps lanes apart (lps = the set's largest variant count rounded
 // up to a power of two, at most 64): a wave evaluates 64 / lps sites at once,
 // each lane a variant, and max-reduces within its site's lanes.
 __global__ void __launch_bounds__(256) ah_tm_site_kernel(ah_store st, const DPair *pairs, const uint32_t *amps,
-                                                         const uint64_t *d_n, uint64_t cap, ah_tm_params prm,
+                                                         const uint64_t *d_n, uint64_t cap, TmConst k,
                                                          uint32_t lps, double *tm_site) {
     __shared__ double sdh[256], sds[256], tdh[256], tds[256];
     __shared__ uint32_t sok[8], tok[8];
@@ -356,7 +343,6 @@ __global__ void __launch_bounds__(256) ah_tm_site_kernel(ah_store st, const DPai
         tok[threadIdx.x] = g_term.ok[threadIdx.x];
     }
     __syncthreads();
-    const TmConst k = tm_const(prm);
     const uint64_t n = *d_n < cap ? *d_n : cap;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t per_wave = 64u / lps, sub = lane / lps, vl = lane % lps;
@@ -385,9 +371,11 @@ __global__ void __launch_bounds__(256) ah_tm_site_kernel(ah_store st, const DPai
         double best = -INFINITY;
         if (live && !has_n && P.D) {
             const uint64_t base = primer_base_codes(P);
+            const bool tab = P.D <= AH_VARTAB;
             for (uint32_t v = vl; v < P.D; v += lps) {
                 double t;
-                if (duplex_tm(primer_variant(P, base, v), Cc, L, sdh, sds, sok, tdh, tds, tok, k, &t))
+                const uint64_t V = tab ? P.var[v] : primer_variant(P, base, v);
+                if (duplex_tm(V, Cc, L, sdh, sds, sok, tdh, tds, tok, k, &t))
                     best = t > best ? t : best;
             }
         }
@@ -428,13 +416,13 @@ extern "C" ah_status ah_tm_nn(const ah_store *st, ah_primer_set ps, const ah_amp
     while (lps < maxD && lps < 64) lps <<= 1;
     if (!amp_cap) return AH_OK;
     hipStream_t s = ah_stream(stream);
-    // one wave per site over a persistent grid: every workgroup stages the NN
-    // tables in LDS once, so no more workgroups than can be resident
+    // 64 / lps sites per wave over a persistent grid: every workgroup stages
+    // the NN tables in LDS once, so no more workgroups than can be resident
     uint64_t wgs = (2 * amp_cap + 4 * (64 / lps) - 1) / (4 * (64 / lps));
-    const uint64_t resident = 8ull * ah_device_cus();
+    const uint64_t resident = ah_resident_wgs(ah_tm_site_kernel, 256);
     if (wgs > resident) wgs = resident;
     hipLaunchKernelGGL(ah_tm_site_kernel, dim3((unsigned)wgs), dim3(256), 0, s, *st, (const DPair *)ps->d_pairs,
-                       (const uint32_t *)d_amps, d_n_amps, amp_cap, *p, lps, d_tm_site);
+                       (const uint32_t *)d_amps, d_n_amps, amp_cap, tm_const(*p), lps, d_tm_site);
     hipLaunchKernelGGL(ah_tm_finish_kernel, dim3(256), dim3(256), 0, s, (const double *)d_tm_site, d_amps, d_n_amps,
                        amp_cap, *p, d_tm, d_pass);
     return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
@@ -452,8 +440,7 @@ __device__ __forceinline__ int letter_code(char c) {
 }
 
 __global__ void ah_tm_duplex_kernel(const char *seq, const char *cseq, const uint32_t *len, uint32_t n,
-                                    uint32_t stride, ah_tm_params prm, double *out) {
-    const TmConst k = tm_const(prm);
+                                    uint32_t stride, TmConst k, double *out) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int L = (int)len[i];
         uint64_t V = 0, C = 0;
@@ -485,6 +472,6 @@ extern "C" ah_status ah_tm_duplex(const char *d_seq, const char *d_cseq, const u
     unsigned blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(ah_tm_duplex_kernel, dim3(blocks), dim3(256), 0, ah_stream(stream), d_seq, d_cseq, d_len, n,
-                       stride, *p, d_tm);
+                       stride, tm_const(*p), d_tm);
     return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
 }

@@ -1,7 +1,8 @@
 """Degenerate inputs through the whole GPU path, against the oracle: an empty
 store, a store of empty sequences, a pair that never hits, k at least the
 primer length (every window whose clamp matches is a hit), a clamp spanning
-the whole primer, no orientation asked for, and an empty sequence subset."""
+the whole primer, no orientation asked for, an empty sequence subset, and
+amplicons longer than one staging pass of the extraction kernel."""
 import numpy as np
 import pytest
 
@@ -88,3 +89,26 @@ def test_empty_subset(ah):
     print("edge case empty subset", flush=True)
     r = P.gpu_run(st, wl.pairs, wl.orient_mask, wl.tm, ExtractSpec(), subset=np.zeros(0, np.uint32), jit=True)
     assert len(r["hits"]) == 0 and len(r["amps"]) == 0
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_long_amplicons_span_many_blocks(ah, kernel):
+    """Amplicons of 4-12 kb (FR, and RF from swapped sites) with barcodes and
+    an N run inside: their windows exceed one 64-block staging pass of the
+    extraction kernel, so the chunked path writes them."""
+    rng = np.random.default_rng(6)
+    F, R = "ACGGTCAGTRCAGTACGT", "TTGACYGATCGGATCA"
+    Fv, Rv = "ACGGTCAGTACAGTACGT", "TTGACTGATCGGATCA"      # exact variants
+    s = list(synth.random_ascii(rng, 40000).tobytes().decode())
+    for at in (100, 12000):
+        s[at:at + len(Fv)] = Fv                            # F on the plus strand
+    for at in (5000, 21000):
+        s[at:at + len(Rv)] = synth.revcomp_str(Rv)         # R on the minus strand
+    s[26000:26000 + len(Rv)] = Rv                          # R on the plus strand ...
+    s[33000:33000 + len(Fv)] = synth.revcomp_str(Fv)       # ... F on the minus strand: RF
+    s[15000:15040] = "N" * 40                               # inside the second FR amplicon
+    tm = TmSpec(threshold_C=30.0, filter=False)
+    r, o = _run(ah, ["".join(s)], [PairSpec(F, R, k=1, clamp=3, min_len=3000, max_len=12000)], kernel, tm=tm)
+    a = o.amps.astype(np.int64)                            # [seq, start, end, pair, orient]
+    assert len(a) >= 3 and (a[:, 2] - a[:, 1]).max() > 64 * 64 and (a[:, 4] == 1).any()
+    assert len(r["seq"]) > 3 * 4096
