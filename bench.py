@@ -29,7 +29,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2, help="workload (2 = genome scale)")
     ap.add_argument("--n-seqs", type=int, default=None, help="shrink the workload (testing)")
@@ -432,7 +432,8 @@ def extra_batch(args):
     from paper_2511_00170_amd import synth
     wl = synth.gen_config(3)
     store = make_store(wl)
-    o = bench_batch(args, wl, store, None)
+    # a batched step is ~50 ms: at most 20 timed steps here
+    o = bench_batch(argparse.Namespace(**{**vars(args), "steps": min(args.steps, 20)}), wl, store, None)
     r = dict(o["batched_vs_plain"])
     r.update({"workload": o["config"]["workload"], "pairs": o["config"]["pairs"], "bases": o["config"]["bases"],
               "batched_pair_gbases_s": o["value"], "unit": "pair-Gbases/s", "scan_ms": o["roofline"]["kernel_ms"],
