@@ -326,10 +326,14 @@ __device__ __forceinline__ uint64_t primer_base_codes(const DPrimer &P) { return
 
 // Sites packed lps lanes apart (lps = the set's largest variant count rounded
 // up to a power of two, at most 64): a wave evaluates 64 / lps sites at once,
-// each lane a variant, and max-reduces within its site's lanes.
+// each lane a variant, and max-reduces within its site's lanes.  With
+// lps <= 32 the two sites of an amplicon (2a, 2a + 1) sit in one wave, lps
+// lanes apart, so the wave also takes their minimum and the pass flag
+// (tm != nullptr); otherwise a finish kernel does.
 __global__ void __launch_bounds__(256) ah_tm_site_kernel(ah_store st, const DPair *pairs, const uint32_t *amps,
                                                          const uint64_t *d_n, uint64_t cap, TmConst k,
-                                                         uint32_t lps, double *tm_site) {
+                                                         uint32_t lps, double *tm_site, const double *pair_thr,
+                                                         double *tm, uint8_t *pass) {
     __shared__ double sdh[256], sds[256], tdh[256], tds[256];
     __shared__ uint32_t sok[8], tok[8];
     for (int i = threadIdx.x; i < 256; i += blockDim.x) {
@@ -384,6 +388,15 @@ __global__ void __launch_bounds__(256) ah_tm_site_kernel(ah_store st, const DPai
             best = o > best ? o : best;
         }
         if (live && vl == 0) tm_site[2 * a + side] = best;
+        if (tm) {
+            const double other = __shfl_xor(best, (int)lps, 64);  // the amplicon's other site
+            if (live && vl == 0 && side == 0) {
+                const double t = best < other ? best : other;  // the weaker primer limits the amplicon
+                const double thr = pair_thr ? pair_thr[pair] : k.threshold;
+                tm[a] = t;
+                pass[a] = k.filter ? (uint8_t)(t >= thr) : (uint8_t)1;
+            }
+        }
     }
 }
 
@@ -421,10 +434,13 @@ extern "C" ah_status ah_tm_nn(const ah_store *st, ah_primer_set ps, const ah_amp
     uint64_t wgs = (2 * amp_cap + 4 * (64 / lps) - 1) / (4 * (64 / lps));
     const uint64_t resident = ah_resident_wgs(ah_tm_site_kernel, 256);
     if (wgs > resident) wgs = resident;
+    const bool fused = lps <= 32;  // both sites of an amplicon in one wave
     hipLaunchKernelGGL(ah_tm_site_kernel, dim3((unsigned)wgs), dim3(256), 0, s, *st, (const DPair *)ps->d_pairs,
-                       (const uint32_t *)d_amps, d_n_amps, amp_cap, tm_const(*p), lps, d_tm_site);
-    hipLaunchKernelGGL(ah_tm_finish_kernel, dim3(256), dim3(256), 0, s, (const double *)d_tm_site, d_amps, d_n_amps,
-                       amp_cap, *p, d_tm, d_pass);
+                       (const uint32_t *)d_amps, d_n_amps, amp_cap, tm_const(*p), lps, d_tm_site,
+                       p->d_pair_threshold, fused ? d_tm : nullptr, d_pass);
+    if (!fused)
+        hipLaunchKernelGGL(ah_tm_finish_kernel, dim3(256), dim3(256), 0, s, (const double *)d_tm_site, d_amps,
+                           d_n_amps, amp_cap, *p, d_tm, d_pass);
     return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
 }
 
