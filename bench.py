@@ -243,6 +243,71 @@ def extra_fasta(wl, store, res, ex, gbases, ps):
     return out
 
 
+_IUPAC_FOLD = {c: n for n, cs in ((1, "ACGTU"), (2, "RYSWKM"), (3, "BDHV"), (4, "N")) for c in cs}
+
+
+def _variants(primer: str) -> int:
+    v = 1
+    for c in primer.upper():
+        v *= _IUPAC_FOLD[c]
+    return v
+
+
+def bench_sweep(args, wl, store):
+    """Runtime against primer degeneracy and mismatch tolerance on the genome
+    store (the shape of the paper's degeneracy and mismatch tests): per point
+    the whole path, timed per stage with HIP events on the stream."""
+    import torch
+
+    from paper_2511_00170_amd import ah, synth
+    ex = synth.ExtractSpec(trim=wl.extract.trim, fb_len=wl.extract.fb_len, rb_len=wl.extract.rb_len)
+    total = wl.total_bases
+    stages = ("scan", "pair", "tm", "extract")
+    out = {"metric": "sweep: whole-path time vs primer degeneracy (N bases added, one per primer) and "
+                     "substitutions allowed (k)",
+           "unit": "ms per step", "data": "synthetic", "n_gpus": 1, "steps": args.steps,
+           "workload": "genome: %d seqs x 3-6 Mb, %.2f Gbases, base pair %s / %s, k=%d, clamp %d, FR/RF/FF/RR"
+                       % (wl.n_seqs, total / 1e9, wl.pairs[0].fwd, wl.pairs[0].rev, wl.pairs[0].k,
+                          wl.pairs[0].clamp)}
+    stream = torch.cuda.Stream()
+    for kind in ("degeneracy", "mismatch"):
+        rows = []
+        for x, pair in synth.sweep_pairs(wl.pairs[0], kind):
+            tc = time.perf_counter()
+            ps = ah.PrimerSet([pair], jit=True)
+            t_compile = time.perf_counter() - tc
+            with torch.cuda.stream(stream):
+                pipe = ah.Pipeline(store, ps, wl.orient_mask, wl.tm, ex)
+                pipe.run(stream)
+                n_hits, n_amps, n_bytes = pipe.counts()
+                n_pass = int(pipe.passed[:n_amps].sum().item())
+                pipe.launch(stream)
+                torch.cuda.synchronize()
+                ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
+                      for _ in range(args.steps)]
+                t0 = time.perf_counter()
+                for i in range(args.steps):
+                    ev[i][0].record(stream)
+                    for j, stg in enumerate(stages):
+                        pipe.launch(stream, (stg,))
+                        ev[i][j + 1].record(stream)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            st_ms = {stg: round(sum(e[j].elapsed_time(e[j + 1]) for e in ev) / args.steps, 4)
+                     for j, stg in enumerate(stages)}
+            alg = BYTES_PER_BASE * total + 12.0 * n_hits
+            row = {("n_N" if kind == "degeneracy" else "k"): x, "fwd": pair.fwd, "rev": pair.rev,
+                   "variants": [_variants(pair.fwd), _variants(pair.rev)], "k": pair.k,
+                   "ms_per_step": round(ms, 4), "gbases_s": round(total / (ms / 1e3) / 1e9, 1), "stage_ms": st_ms,
+                   "scan_hbm_frac": round(alg / (st_ms["scan"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "hits": n_hits, "amplicons": n_amps, "passed": n_pass, "jit_compile_s": round(t_compile, 2)}
+            log("sweep %s %s: %s" % (kind, x, json.dumps(row)))
+            rows.append(row)
+            del pipe, ps
+        out[kind] = rows
+    return out
+
+
 def bench_batch(args, wl, store, sample):
     """Many pairs: one autotuned, graph-captured pass over the store against
     the plain per-pair loop (64 single-pair pipelines).  value = pair-Gbases/s

@@ -37,31 +37,84 @@ __device__ __forceinline__ uint32_t orient_of(uint32_t up_primer, uint32_t down_
                                                                                                : (up_primer == 0 ? 2u : 3u);
 }
 
+// Hits of a sequence mostly arrive together (the scan writes each wave's
+// hits as one run), and with many hits per sequence per-hit atomics on one
+// counter serialise.  So a wave first groups its lanes by sequence (one pass
+// per distinct sequence, lane reads and ballots only), then the first lane of
+// every group adds the group's size with one atomic -- all groups in a single
+// instruction -- and the others take their share by rank.  Whole waves: hits
+// [b, b + 64) per wave and step.
+struct SeqGroup {
+    int lead;       // first lane of this lane's group
+    uint32_t rank;  // position in the group
+    uint32_t size;  // lanes in the group
+};
+
+__device__ __forceinline__ SeqGroup group_by_seq(uint32_t s, bool valid) {
+    SeqGroup g{(int)ah_lane(), 0u, 0u};
+    bool todo = valid;
+    for (uint64_t act = __ballot(todo); act; act = __ballot(todo)) {
+        const int first = (int)__ffsll((unsigned long long)act) - 1;
+        const uint32_t ls = __builtin_amdgcn_readlane(s, first);
+        const bool mine = todo && s == ls;
+        const uint64_t grp = __ballot(mine);
+        if (mine) {
+            g.lead = first;
+            g.rank = ah_mbcnt(grp);
+            g.size = (uint32_t)__popcll(grp);
+        }
+        todo = todo && !mine;
+    }
+    return g;
+}
+
 // 1. hits per sequence
 __global__ void ah_pair_count_kernel(const uint32_t *hits, const uint64_t *d_n, uint64_t cap, uint32_t n_seqs,
                                      uint64_t *cnt) {
     const uint64_t n = *d_n < cap ? *d_n : cap;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t s = hits[3 * i];
-        if (s < n_seqs) atomicAdd((unsigned long long *)&cnt[s], 1ull);
+    const uint32_t lane = ah_lane();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t b = wave * 64; b < n; b += n_waves * 64) {
+        const uint64_t i = b + lane;
+        const uint32_t s = i < n ? hits[3 * i] : 0xFFFFFFFFu;
+        const bool valid = s < n_seqs;
+        const SeqGroup g = group_by_seq(s, valid);
+        if (valid && g.rank == 0) atomicAdd((unsigned long long *)&cnt[s], (unsigned long long)g.size);
     }
 }
 
 // Hits into their sequence's bucket (in any order within it): the counts run
-// down to zero as the slots are taken.
+// down to zero as the slots are taken; a group of c lanes takes the c slots
+// below the count its first lane found.
 __global__ void ah_pair_scatter_kernel(const uint32_t *hits, const uint64_t *d_n, uint64_t cap, uint32_t n_seqs,
                                        const DPair *pairs, KeyLayout kl, const uint64_t *boff, uint64_t *cnt,
                                        uint64_t *keys) {
     const uint64_t n = *d_n < cap ? *d_n : cap;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t s = hits[3 * i], pos = hits[3 * i + 1], w = hits[3 * i + 2];
-        if (s >= n_seqs) continue;
-        const uint32_t pair = w & 0xFFFFu, kind = (w >> 16) & 0xFFu;
-        const uint32_t primer = kind & 1u, sense = (kind >> 1) & 1u;
-        const uint32_t L = primer ? pairs[pair].Lr : pairs[pair].Lf;
-        const uint64_t slot = boff[s] + atomicAdd((unsigned long long *)&cnt[s], ~0ull) - 1;  // count - 1, ...
-        keys[slot] = ((uint64_t)pair << (kl.pos_bits + 7)) | ((uint64_t)pos << 7) | ((uint64_t)(L - 1) << 2) |
-                     ((uint64_t)sense << 1) | primer;
+    const uint32_t lane = ah_lane();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t b = wave * 64; b < n; b += n_waves * 64) {
+        const uint64_t i = b + lane;
+        uint32_t s = 0xFFFFFFFFu, pos = 0, w = 0;
+        if (i < n) {
+            s = hits[3 * i];
+            pos = hits[3 * i + 1];
+            w = hits[3 * i + 2];
+        }
+        const bool valid = s < n_seqs;
+        const SeqGroup g = group_by_seq(s, valid);
+        unsigned long long old = 0;
+        if (valid && g.rank == 0)
+            old = atomicAdd((unsigned long long *)&cnt[s], (unsigned long long)(-(int64_t)g.size));
+        old = __shfl(old, g.lead, 64);
+        if (valid) {
+            const uint32_t pair = w & 0xFFFFu, kind = (w >> 16) & 0xFFu;
+            const uint32_t primer = kind & 1u, sense = (kind >> 1) & 1u;
+            const uint32_t L = primer ? pairs[pair].Lr : pairs[pair].Lf;
+            keys[boff[s] + old - 1 - g.rank] = ((uint64_t)pair << (kl.pos_bits + 7)) | ((uint64_t)pos << 7) |
+                                               ((uint64_t)(L - 1) << 2) | ((uint64_t)sense << 1) | primer;
+        }
     }
 }
 
