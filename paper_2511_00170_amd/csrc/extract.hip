@@ -78,15 +78,55 @@ __device__ __forceinline__ void stage_blocks(const ah_store &st, uint64_t b0, ui
     ah_wave_sync();
 }
 
+// Letters of the four sequence positions P .. P+3 (P a multiple of 4, so
+// all in one 32-bit word of the staged block), byte i for position P + i,
+// complemented when rc, 'N' where the N mask is set.  The 2-bit codes are
+// spread into the bytes of a selector (a 24-bit multiply per plane) and one
+// byte permute maps each to its letter.
+__device__ __forceinline__ uint32_t staged_quad(const uint4 *sblk, const uint64_t *snm, uint64_t cb, uint64_t P,
+                                                bool rc) {
+    const uint32_t k = (uint32_t)((P >> 6) - cb), bit = (uint32_t)(P & 63), sh = bit & 31u;
+    const uint4 w = sblk[k];
+    const uint32_t h4 = ((bit < 32 ? w.x : w.z) >> sh) & 15u, l4 = ((bit < 32 ? w.y : w.w) >> sh) & 15u;
+    // bit i of a 4-bit group to bit 0 of byte i
+    const uint32_t spread_l = (l4 * 0x204081u) & 0x01010101u;
+    const uint32_t spread_h = (h4 * 0x204081u) & 0x01010101u;
+    uint32_t sel = spread_l | (spread_h << 1);  // byte i: code of position P + i
+    if (rc) sel ^= 0x03030303u;
+    uint32_t q = __builtin_amdgcn_perm(0u, 0x54474341u, sel);  // bytes 0..3 of "ACGT"
+    const uint32_t n4 = (uint32_t)(snm[k] >> bit) & 15u;
+    if (n4) {
+        const uint32_t nb = ((n4 * 0x204081u) & 0x01010101u) * 0xFFu;
+        q = (q & ~nb) | (0x4E4E4E4Eu & nb);
+    }
+    return q;
+}
+
 // Output bytes j in [j0, j1) of the span [a0, a1), forward or (rc) reverse-
 // complemented (out[j] = comp(s[a1 - 1 - j])), decoded from blocks staged
-// from block cb on; consecutive lanes write consecutive bytes.  Whole wave.
+// from block cb on.  Whole wave.  The positions they come from are taken in
+// aligned groups of four (one per lane, consecutive lanes on consecutive
+// groups); the < 4 positions before the first and after the last group go
+// one byte per lane.  Nothing is written at or past seq_cap.
 __device__ __forceinline__ void write_staged(const uint4 *sblk, const uint64_t *snm, uint64_t cb, uint64_t a0,
                                              uint64_t a1, bool rc, uint64_t j0, uint64_t j1, char *out, uint64_t dst0,
                                              uint64_t seq_cap) {
-    for (uint64_t j = j0 + ah_lane(); j < j1; j += 64) {
-        const uint64_t p = rc ? a1 - 1 - j : a0 + j;
-        if (dst0 + j < seq_cap) out[dst0 + j] = staged_base(sblk, snm, cb, p, rc);
+    if (j1 <= j0) return;
+    const uint32_t lane = ah_lane();
+    // positions [pl, ph) of the output range, and its whole groups [qa, qb)
+    const uint64_t pl = rc ? a1 - j1 : a0 + j0, ph = rc ? a1 - j0 : a0 + j1;
+    uint64_t qa = (pl + 3) & ~3ull, qb = ph & ~3ull;
+    if (qa > qb) qa = qb = ph;  // no whole group: every position one by one
+    auto put = [&](uint64_t p, char c) {
+        const uint64_t j = rc ? a1 - 1 - p : p - a0;
+        if (dst0 + j < seq_cap) out[dst0 + j] = c;
+    };
+    if (lane < qa - pl) put(pl + lane, staged_base(sblk, snm, cb, pl + lane, rc));
+    if (lane < ph - qb && qb + lane >= qa) put(qb + lane, staged_base(sblk, snm, cb, qb + lane, rc));
+    for (uint64_t P = qa + 4u * lane; P < qb; P += 256) {
+        const uint32_t q = staged_quad(sblk, snm, cb, P, rc);
+#pragma unroll
+        for (uint32_t i = 0; i < 4; i++) put(P + i, (char)(q >> (8 * i)));
     }
 }
 
