@@ -6,8 +6,9 @@
 //      integer order is the site order within a sequence
 //        key = pair | start | (L - 1) | sense | primer   (most to least significant)
 //      with end = start + L;
-//   2. one workgroup per sequence sorts its bucket -- in LDS (bitonic) when it
-//      fits, else with a radix sort in global memory -- and, in the sorted
+//   2. every bucket is sorted -- by one wave in registers up to 64 keys,
+//      else by a workgroup in LDS (bitonic) when it fits, else with a radix
+//      sort in global memory -- and, in the sorted
 //      order, gives every minus site its only possible partner: the nearest
 //      plus site before it in the same pair (a plus site stops the walk);
 //      the pairs inside the length window and the orientation mask are
@@ -223,7 +224,39 @@ __device__ void bucket_radix_sort(uint64_t *a, uint64_t *b, uint64_t m, int key_
     __syncthreads();
 }
 
-// 2. one workgroup per sequence: sort the bucket, pair, rank
+// A bucket of at most 64 keys, by one wave: bitonic sort across the lanes
+// (one key per lane, compare-exchange through lane shuffles, no barrier),
+// then pairing and ranking over a per-wave LDS copy of the sorted keys.
+__device__ __forceinline__ void wave_bucket(uint64_t *keys, uint64_t base, uint32_t m, const DPair *pairs,
+                                            KeyLayout kl, uint32_t orient_mask, uint32_t *rank, uint32_t *part,
+                                            uint64_t *acnt_s, uint64_t *swk) {
+    const uint32_t lane = ah_lane();
+    uint64_t v = lane < m ? keys[base + lane] : ~0ull;
+#pragma unroll
+    for (uint32_t len = 2; len <= 64; len <<= 1) {
+#pragma unroll
+        for (uint32_t st = len >> 1; st > 0; st >>= 1) {
+            const uint64_t o = __shfl_xor(v, (int)st, 64);
+            const bool keep_min = ((lane & st) == 0) == ((lane & len) == 0);  // lower lane of an ascending run
+            v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+        }
+    }
+    ah_wave_sync();
+    swk[lane] = v;
+    ah_wave_sync();
+    const int64_t p = lane < m ? partner_of(swk, lane, pairs, kl, orient_mask) : -1;
+    const uint64_t bal = __ballot(p >= 0);
+    if (lane < m) {
+        keys[base + lane] = v;
+        rank[base + lane] = p >= 0 ? ah_mbcnt(bal) : PAIR_NO_AMP;
+        part[base + lane] = p >= 0 ? (uint32_t)p : 0u;
+    }
+    if (lane == 0) *acnt_s = (uint64_t)__popcll(bal);
+}
+
+// 2. sort every bucket, pair, rank: one workgroup per sequence; a bucket of
+// at most 64 keys is done by its first wave alone (no barrier), a larger one
+// by the whole workgroup (in LDS up to PAIR_LDS_KEYS, else in global memory).
 __global__ void __launch_bounds__(PAIR_WG) ah_pair_bucket_kernel(uint64_t *keys, uint64_t *scratch,
                                                                  const uint64_t *boff, uint32_t n_seqs,
                                                                  const DPair *pairs, KeyLayout kl,
@@ -233,12 +266,17 @@ __global__ void __launch_bounds__(PAIR_WG) ah_pair_bucket_kernel(uint64_t *keys,
     __shared__ uint32_t srank[PAIR_LDS_KEYS], spart[PAIR_LDS_KEYS];
     __shared__ uint32_t h[4][256];
     __shared__ uint32_t lds16[16];
+    __shared__ uint64_t swk[64];
     for (uint32_t s = blockIdx.x; s < n_seqs; s += gridDim.x) {
+        // every thread reads the same bounds: the branch is the workgroup's
         const uint64_t base = boff[s], m = boff[s + 1] - base;
+        if (m <= 64) {
+            if (threadIdx.x < 64) wave_bucket(keys, base, (uint32_t)m, pairs, kl, orient_mask, rank, part,
+                                              &acnt[s], swk);
+            continue;
+        }
         uint32_t total = 0;
-        if (m == 0) {
-            // nothing to do
-        } else if (m <= PAIR_LDS_KEYS) {
+        if (m <= PAIR_LDS_KEYS) {
             uint32_t P = 1;
             while (P < m) P <<= 1;
             for (uint32_t i = threadIdx.x; i < P; i += PAIR_WG) sk[i] = i < m ? keys[base + i] : ~0ull;
