@@ -330,7 +330,10 @@ __device__ __forceinline__ uint64_t primer_base_codes(const DPrimer &P) { return
 // lps <= 32 the two sites of an amplicon (2a, 2a + 1) sit in one wave, lps
 // lanes apart, so the wave also takes their minimum and the pass flag
 // (tm != nullptr); otherwise a finish kernel does.
-__global__ void __launch_bounds__(256) ah_tm_site_kernel(ah_store st, const DPair *pairs, const uint32_t *amps,
+// Bounded to six waves per SIMD (80 VGPRs, two spilled): latency-bound, it
+// gains more from the sixth wave than the spills cost (seven: 72, eleven
+// spilled, slower).
+__global__ void __launch_bounds__(256, 6) ah_tm_site_kernel(ah_store st, const DPair *pairs, const uint32_t *amps,
                                                          const uint64_t *d_n, uint64_t cap, TmConst k,
                                                          uint32_t lps, double *tm_site, const double *pair_thr,
                                                          double *tm, uint8_t *pass) {
