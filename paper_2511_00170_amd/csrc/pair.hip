@@ -20,7 +20,7 @@
 #include "ah_scan_impl.h"
 
 #define PAIR_WG 256
-#define PAIR_LDS_KEYS 2048  // buckets up to this size are sorted in LDS
+#define PAIR_LDS_KEYS 1024  // buckets up to this size are sorted in LDS (16.6 KB: 8 workgroups per CU)
 #define PAIR_NO_AMP 0xFFFFFFFFu
 
 struct KeyLayout {
@@ -257,14 +257,18 @@ __device__ __forceinline__ void wave_bucket(uint64_t *keys, uint64_t base, uint3
 // 2. sort every bucket, pair, rank: one workgroup per sequence; a bucket of
 // at most 64 keys is done by its first wave alone (no barrier), a larger one
 // by the whole workgroup (in LDS up to PAIR_LDS_KEYS, else in global memory).
-__global__ void __launch_bounds__(PAIR_WG) ah_pair_bucket_kernel(uint64_t *keys, uint64_t *scratch,
+// Bounded to 64 VGPRs (no spill) so that, with 16.6 KB of LDS, eight
+// workgroups fit on a CU: 2048 sequences in one round.
+__global__ void __launch_bounds__(PAIR_WG, 8) ah_pair_bucket_kernel(uint64_t *keys, uint64_t *scratch,
                                                                  const uint64_t *boff, uint32_t n_seqs,
                                                                  const DPair *pairs, KeyLayout kl,
                                                                  uint32_t orient_mask, uint32_t *rank,
                                                                  uint32_t *part, uint64_t *acnt) {
     __shared__ uint64_t sk[PAIR_LDS_KEYS];
     __shared__ uint32_t srank[PAIR_LDS_KEYS], spart[PAIR_LDS_KEYS];
-    __shared__ uint32_t h[4][256];
+    // the radix path's digit counts reuse srank (that path ranks in global memory)
+    static_assert(PAIR_LDS_KEYS >= 4 * 256, "digit counts fit in srank");
+    uint32_t(*h)[256] = (uint32_t(*)[256])srank;
     __shared__ uint32_t lds16[16];
     __shared__ uint64_t swk[64];
     for (uint32_t s = blockIdx.x; s < n_seqs; s += gridDim.x) {
