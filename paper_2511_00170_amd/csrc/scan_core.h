@@ -40,6 +40,15 @@ struct ScanArgs {
     uint64_t *n_hits;
 };
 
+// Lane i receives lane i+1's value (lane 63: 0) / lane i-1's (lane 0: 0):
+// DPP whole-wave shifts, plain vector moves instead of an LDS permute.
+__device__ __forceinline__ uint32_t ah_from_next_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, false);  // wave_shl:1
+}
+__device__ __forceinline__ uint32_t ah_from_prev_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xF, 0xF, false);  // wave_shr:1
+}
+
 __device__ __forceinline__ uint32_t ah_funnel(uint32_t hi, uint32_t lo, uint32_t sh) {
     return __builtin_amdgcn_alignbit(hi, lo, sh);
 }
@@ -385,8 +394,8 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
         B.h[2 + 2 * b] = L.blk[b].z;
         B.l[2 + 2 * b] = L.blk[b].w;
     }
-    B.h[AH_NW + 1] = __shfl_down(B.h[1], 1, 64);
-    B.l[AH_NW + 1] = __shfl_down(B.l[1], 1, 64);
+    B.h[AH_NW + 1] = ah_from_next_lane(B.h[1]);
+    B.l[AH_NW + 1] = ah_from_next_lane(B.l[1]);
     if (lane == 63) {
         B.h[AH_NW + 1] = L.hal.x;
         B.l[AH_NW + 1] = L.hal.y;
@@ -396,8 +405,8 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
         // the previous 32 positions (lane 0: the block before the tile; at a
         // sequence start they are another sequence's or padding, which only
         // windows that verification rejects can see)
-        B.h[0] = __shfl_up(B.h[AH_NW], 1, 64);
-        B.l[0] = __shfl_up(B.l[AH_NW], 1, 64);
+        B.h[0] = ah_from_prev_lane(B.h[AH_NW]);
+        B.l[0] = ah_from_prev_lane(B.l[AH_NW]);
         if (lane == 0) {
             B.h[0] = L.hal.z;
             B.l[0] = L.hal.w;
