@@ -214,6 +214,46 @@ __host__ __device__ inline TmConst tm_const(const ah_tm_params &p) {
 
 __device__ __forceinline__ bool tab_ok(const uint32_t *ok, int i) { return (ok[i >> 5] >> (i & 31)) & 1u; }
 
+// The two tables as the constant-memory records (values and validity bits).
+struct ConstTables {
+    __device__ bool stack(int i, double &dh, double &ds) const {
+        dh = g_stack.dh[i];
+        ds = g_stack.ds[i];
+        return tab_ok(g_stack.ok, i);
+    }
+    __device__ bool term(int i, double &dh, double &ds) const {
+        dh = g_term.dh[i];
+        ds = g_term.ds[i];
+        return tab_ok(g_term.ok, i);
+    }
+};
+
+// The two tables staged in LDS as (dH, dS) pairs, NaN where not tabulated:
+// one 16-byte read per step instead of two values and a validity word.
+struct LdsTables {
+    const double2 *st, *tt;
+    __device__ bool stack(int i, double &dh, double &ds) const {
+        const double2 e = st[i];
+        dh = e.x;
+        ds = e.y;
+        return e.x == e.x;
+    }
+    __device__ bool term(int i, double &dh, double &ds) const {
+        const double2 e = tt[i];
+        dh = e.x;
+        ds = e.y;
+        return e.x == e.x;
+    }
+};
+
+__device__ void stage_tables(double2 *st, double2 *tt) {
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+        st[i] = tab_ok(g_stack.ok, i) ? make_double2(g_stack.dh[i], g_stack.ds[i]) : make_double2(NAN, NAN);
+        tt[i] = tab_ok(g_term.ok, i) ? make_double2(g_term.dh[i], g_term.ds[i]) : make_double2(NAN, NAN);
+    }
+    __syncthreads();
+}
+
 // Duplex Tm of variant V with partner C (2-bit codes, base j at bits 2j; C is
 // the partner strand read 3'->5' against V).  Steps: a mismatched end pair
 // is charged with the terminal-mismatch stack and leaves the helix; one
@@ -221,8 +261,8 @@ __device__ __forceinline__ bool tab_ok(const uint32_t *ok, int i) { return (ok[i
 // 5' to 3'; the salt term; Tm = 1000 dH / (dS + R ln C) - 273.15.  The order
 // of the floating-point additions is fixed.  Returns false if a stack is not
 // tabulated.
-__device__ bool duplex_tm(uint64_t V, uint64_t C, int L, const double *sdh, const double *sds, const uint32_t *sok,
-                          const double *tdh, const double *tds, const uint32_t *tok, const TmConst &k, double *out) {
+template <class Tab>
+__device__ bool duplex_tm(uint64_t V, uint64_t C, int L, const Tab &tab, const TmConst &k, double *out) {
     if (L < 2) return false;
     auto bb = [](uint64_t X, int j) { return (int)((X >> (2 * j)) & 3u); };
     double dh = 0.0, ds = 0.0;
@@ -230,17 +270,19 @@ __device__ bool duplex_tm(uint64_t V, uint64_t C, int L, const double *sdh, cons
     {
         // left end read from the partner strand, so the end pair comes second
         const int i = nn_index(bb(C, 1), bb(C, 0), bb(V, 1), bb(V, 0));
-        if (tab_ok(tok, i)) {
-            dh += tdh[i];
-            ds += tds[i];
+        double a, b;
+        if (tab.term(i, a, b)) {
+            dh += a;
+            ds += b;
             lo = 1;
         }
     }
     if (hi - 1 >= lo) {
         const int i = nn_index(bb(V, hi - 1), bb(V, hi), bb(C, hi - 1), bb(C, hi));
-        if (tab_ok(tok, i)) {
-            dh += tdh[i];
-            ds += tds[i];
+        double a, b;
+        if (tab.term(i, a, b)) {
+            dh += a;
+            ds += b;
             hi -= 1;
         }
     }
@@ -253,9 +295,10 @@ __device__ bool duplex_tm(uint64_t V, uint64_t C, int L, const double *sdh, cons
     }
     for (int j = lo; j < hi; j++) {
         const int i = nn_index(bb(V, j), bb(V, j + 1), bb(C, j), bb(C, j + 1));
-        if (!tab_ok(sok, i)) return false;
-        dh += sdh[i];
-        ds += sds[i];
+        double a, b;
+        if (!tab.stack(i, a, b)) return false;
+        dh += a;
+        ds += b;
     }
     if (k.saltcorr == 5) ds += 0.368 * (double)(L - 1) * k.ln_mon;
     double tm = (1000.0 * dh) / (ds + k.rlnc) - 273.15;
@@ -337,19 +380,9 @@ __global__ void __launch_bounds__(256, 6) ah_tm_site_kernel(ah_store st, const D
                                                          const uint64_t *d_n, uint64_t cap, TmConst k,
                                                          uint32_t lps, double *tm_site, const double *pair_thr,
                                                          double *tm, uint8_t *pass) {
-    __shared__ double sdh[256], sds[256], tdh[256], tds[256];
-    __shared__ uint32_t sok[8], tok[8];
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) {
-        sdh[i] = g_stack.dh[i];
-        sds[i] = g_stack.ds[i];
-        tdh[i] = g_term.dh[i];
-        tds[i] = g_term.ds[i];
-    }
-    if (threadIdx.x < 8) {
-        sok[threadIdx.x] = g_stack.ok[threadIdx.x];
-        tok[threadIdx.x] = g_term.ok[threadIdx.x];
-    }
-    __syncthreads();
+    __shared__ double2 sst[256], stt[256];
+    stage_tables(sst, stt);
+    const LdsTables nn{sst, stt};
     const uint64_t n = *d_n < cap ? *d_n : cap;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t per_wave = 64u / lps, sub = lane / lps, vl = lane % lps;
@@ -382,7 +415,7 @@ __global__ void __launch_bounds__(256, 6) ah_tm_site_kernel(ah_store st, const D
             for (uint32_t v = vl; v < P.D; v += lps) {
                 double t;
                 const uint64_t V = tab ? P.var[v] : primer_variant(P, base, v);
-                if (duplex_tm(V, Cc, L, sdh, sds, sok, tdh, tds, tok, k, &t))
+                if (duplex_tm(V, Cc, L, nn, k, &t))
                     best = t > best ? t : best;
             }
         }
@@ -474,7 +507,7 @@ __global__ void ah_tm_duplex_kernel(const char *seq, const char *cseq, const uin
             }
         }
         double t = NAN;
-        if (okc && !duplex_tm(V, C, L, g_stack.dh, g_stack.ds, g_stack.ok, g_term.dh, g_term.ds, g_term.ok, k, &t))
+        if (okc && !duplex_tm(V, C, L, ConstTables{}, k, &t))
             t = NAN;
         out[i] = t;
     }
