@@ -58,3 +58,18 @@ def test_more_than_one_gpu_is_refused(n):
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)], capture_output=True,
                        text=True, timeout=120, env={**os.environ, "RANK": "0", "WORLD_SIZE": "1"})
     assert r.returncode != 0 and "one GPU" in (r.stdout + r.stderr)
+
+
+def test_counters_are_used_only_for_the_profiled_sources():
+    """The committed counter runs carry the hash of the scan sources they were
+    taken on: the bench reports traffic and VALU figures from them only while
+    the sources are unchanged (any other hash gives nothing)."""
+    b = _bench()
+    h = b.scan_source_hash()
+    for name in ("scan_genome", "scan_batch"):
+        d = b.counters_from_profiles(name, h)
+        assert d is not None, "%s: profiles/ were not taken on the current scan sources" % name
+        assert d["hbm_bytes_per_launch"] > 0 and d["valu_insts_per_launch"] > 0
+        assert b.counters_from_profiles(name, "0" * 64) is None
+    assert b.traffic_from_profiles(h) == b.counters_from_profiles("scan_genome", h)["hbm_bytes_per_launch"]
+    assert b.traffic_from_profiles("0" * 64) is None
