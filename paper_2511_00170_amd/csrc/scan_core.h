@@ -131,9 +131,12 @@ struct SeqCursor {
     __device__ void load(const ScanArgs &a) {
         seq = ah_uni(a.list ? a.list[i] : i);
         gm = a.gmask ? ah_uni64(a.gmask[i]) : ~0ull;
-        len = ah_uni(a.st.d_seq_len[seq]);
+        // a listed index outside the store has no tiles (the tile table gives
+        // it none) and its per-sequence entries are never read
+        const bool in_store = seq < a.st.n_seqs;
+        len = in_store ? ah_uni(a.st.d_seq_len[seq]) : 0u;
         nblk = (len + 63u) / 64u;
-        blk0 = ah_uni64(a.st.d_seq_block0[seq]);
+        blk0 = in_store ? ah_uni64(a.st.d_seq_block0[seq]) : 0ull;
         tp0 = ah_uni64(a.tile_pref[i]);
         tp1 = ah_uni64(a.tile_pref[i + 1]);
     }

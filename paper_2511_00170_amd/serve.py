@@ -230,9 +230,22 @@ class BatchPlan:
     slot_thr: np.ndarray        # slot -> Tm threshold
 
 
-def plan_batch(reqs: Sequence[Request], pool: Sequence[PairSpec], n_seqs: int) -> BatchPlan:
+def check_request_k(req: Request, pool_k: int) -> None:
+    """The pool is scanned once at pool_k; routing keeps a hit for a request
+    when its mismatch count is at most the request's k.  A request asking for
+    more than pool_k would silently lose the hits with pool_k < mm <= k, so it
+    is refused."""
+    if req.k > pool_k:
+        raise ValueError("request %d asks for k=%d, but the pool is scanned at k=%d" % (req.rid, req.k, pool_k))
+
+
+def plan_batch(reqs: Sequence[Request], pool: Sequence[PairSpec], n_seqs: int,
+               pool_k: Optional[int] = None) -> BatchPlan:
     n_pool = len(pool)
     assert len(reqs) <= MAX_REQ_PER_BATCH and n_pool <= MAX_POOL
+    if pool_k is not None:
+        for rq in reqs:
+            check_request_k(rq, pool_k)
     seq_req = np.zeros(n_seqs, np.uint64)
     seq_pairs = np.zeros(n_seqs, np.uint64)
     vpair = np.full((len(reqs), n_pool), 0xFFFF, np.uint16)
@@ -360,7 +373,7 @@ class GpuExecutor:
         return self.collect(self._launch_plan(plan))
 
     def launch(self, batch: List[Request]) -> Ticket:
-        return self._launch_plan(plan_batch(batch, self.pool, self.store.n_seqs))
+        return self._launch_plan(plan_batch(batch, self.pool, self.store.n_seqs, self.pool_k))
 
     def ready(self, tk: Ticket) -> bool:
         return tk.slot.event.query()
@@ -527,4 +540,6 @@ class ServeEngine:
                                max_requests)
 
     def serve(self, requests: Sequence[Request]) -> Dict[int, RequestResult]:
+        for rq in requests:  # refused before any of them runs
+            check_request_k(rq, self.exe.pool_k)
         return self.sched.run(requests)

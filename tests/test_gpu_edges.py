@@ -112,3 +112,24 @@ def test_long_amplicons_span_many_blocks(ah, kernel):
     a = o.amps.astype(np.int64)                            # [seq, start, end, pair, orient]
     assert len(a) >= 3 and (a[:, 2] - a[:, 1]).max() > 64 * 64 and (a[:, 4] == 1).any()
     assert len(r["seq"]) > 3 * 4096
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_subset_index_outside_the_store_is_skipped(ah, kernel):
+    """A listed index >= n_seqs contributes nothing (and is never read as a
+    sequence): the hits equal those of the valid entries alone."""
+    wl = synth.gen_config(1, n_seqs=24)
+    buf, off = wl.concat()
+    st = ah.Store.from_workload(wl)
+    valid = [0, 3, 7, 11, 19, 23]
+    listed = [0, 3, 1 << 20, 7, 11, wl.n_seqs, 19, 0xFFFFFFFF, 23]
+    print("subset with out-of-range ids", kernel, listed, flush=True)
+    r = P.gpu_run(st, wl.pairs, wl.orient_mask, wl.tm, subset=listed, jit=kernel == "jit")
+    sel = np.concatenate([np.arange(int(off[i]), int(off[i + 1])) for i in valid])
+    sub_off = np.zeros(len(valid) + 1, np.uint64)
+    sub_off[1:] = np.cumsum([int(off[i + 1] - off[i]) for i in valid])
+    o = P.oracle.run(buf[sel], sub_off, wl.pairs, wl.orient_mask, wl.tm)
+    oh = o.hits.copy()
+    oh[:, 0] = np.asarray(valid, np.uint32)[oh[:, 0]]
+    P.compare_hits(r["hits"], oh, o.mm)
+    assert len(o.hits) > 0

@@ -84,6 +84,19 @@ def test_plan_batch_masks_and_slots():
     assert p.slot_req.tolist() == [0, 0, 1] and p.slot_thr.tolist() == [45.0, 45.0, 55.0]
 
 
+def test_request_above_the_pool_k_is_refused():
+    """The pool is scanned once at its k; a request asking for more would lose
+    hits silently, so planning refuses it (a request at the pool's k plans)."""
+    pool = [PairSpec("ACGTACGTAC", "GGGCCCAAAT", k=3, clamp=3) for _ in range(2)]
+    ok = Request(1, 0.0, [0], np.array([0], np.uint32), 3, 45.0)
+    over = Request(2, 0.0, [1], np.array([1], np.uint32), 4, 45.0)
+    assert serve.plan_batch([ok], pool, n_seqs=2, pool_k=3).kmax.tolist() == [3]
+    with pytest.raises(ValueError, match="k=4"):
+        serve.plan_batch([ok, over], pool, n_seqs=2, pool_k=3)
+    with pytest.raises(ValueError):
+        serve.check_request_k(over, 3)
+
+
 def test_split_results_by_request():
     from paper_2511_00170_amd import ah
     pool = [PairSpec("ACGTACGTAC", "GGGCCCAAAT", k=3, clamp=3) for _ in range(3)]
