@@ -42,6 +42,7 @@ typedef int32_t ah_status;
 #define AH_E_IO 6        /* a file could not be opened or read */
 #define AH_E_FORMAT 7    /* not FASTA: data before the first header, a record of 2^32 or more bases,
                             2^32 or more records */
+#define AH_E_SCRATCH 8   /* input larger than the library's fixed scratch array allows */
 
 /* Human-readable name of a status code (static string). */
 const char *ah_status_str(ah_status s);
@@ -219,11 +220,28 @@ typedef struct {
 ah_status ah_scan_ws_size(const ah_store *st, uint32_t n_list, uint64_t *bytes);
 
 /* d_seq_subset: NULL for every sequence, else n_subset store indices
- * (n_subset may be 0: nothing is scanned; the pointer must still be non-null).
+ * (n_subset may be 0: nothing is scanned; the pointer must still be non-null;
+ * an index >= n_seqs is skipped).
  * Writes min(total, hit_cap) hits; *d_n_hits = total (the call resets it). */
 ah_status ah_scan_primers(const ah_store *st, ah_primer_set ps, const uint32_t *d_seq_subset, uint32_t n_subset,
                           ah_hit *d_hits, uint64_t hit_cap, uint64_t *d_n_hits, void *d_ws, uint64_t ws_bytes,
                           void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): ah_scan_primers
+ * without a workspace argument.  Its workspace is a fixed array inside the
+ * library (AH_STATIC_SCRATCH_BYTES per GPU, held until the process ends), so
+ * at most AH_STATIC_SCAN_MAX_LIST sequences may be listed (all of the store's
+ * when d_seq_subset is NULL); more returns AH_E_SCRATCH before any work.  The
+ * call allocates nothing.  Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (different streams, or host threads)
+ * race and give wrong hits -- order them on one stream.  Results are
+ * identical to ah_scan_primers.  Errors: as ah_scan_primers, AH_E_SCRATCH. */
+#define AH_STATIC_SCAN_MAX_LIST 65536u
+#define AH_STATIC_SCRATCH_BYTES ((1u << 20) + 4096u)
+ah_status ah_scan_primers_static(const ah_store *st, ah_primer_set ps, const uint32_t *d_seq_subset,
+                                 uint32_t n_subset, ah_hit *d_hits, uint64_t hit_cap, uint64_t *d_n_hits,
+                                 void *stream);
 
 /* As ah_scan_primers, with the pairs scanned chosen per listed sequence:
  * d_pair_mask[i] (device, one word per listed sequence, i.e. per subset entry

@@ -23,6 +23,8 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 AH_OK, AH_E_ARG, AH_E_ALPHABET, AH_E_LIMIT, AH_E_HIP, AH_E_WORKSPACE, AH_E_IO, AH_E_FORMAT = 0, 1, 2, 3, 4, 5, 6, 7
+AH_E_SCRATCH = 8
+STATIC_SCAN_MAX_LIST = 65536
 AH_STORE_SCRATCH = 2048
 ORIENT_ALL = 0xF
 
@@ -105,6 +107,7 @@ _sig("ah_primers_use_jit", I32, VP, I32)
 _sig("ah_primers_launch_shape", I32, VP, I32, C.POINTER(I32))
 _sig("ah_scan_ws_size", I32, C.POINTER(ah_store), U32, C.POINTER(U64))
 _sig("ah_scan_primers", I32, C.POINTER(ah_store), VP, VP, U32, VP, U64, VP, VP, U64, VP)
+_sig("ah_scan_primers_static", I32, C.POINTER(ah_store), VP, VP, U32, VP, U64, VP, VP)
 _sig("ah_scan_primers_masked", I32, C.POINTER(ah_store), VP, VP, U32, VP, VP, U64, VP, VP, U64, VP)
 _sig("ah_route_hits", I32, VP, VP, U64, U32, VP, VP, VP, U32, U32, VP, U64, VP, VP)
 _sig("ah_pair_ws_size", I32, C.POINTER(ah_store), VP, U64, C.POINTER(U64))
@@ -118,7 +121,7 @@ _sig("ah_extract", I32, C.POINTER(ah_store), VP, VP, VP, U64, VP, C.POINTER(ah_e
 EXPORTED = ["ah_status_str", "ah_version", "ah_pack_layout", "ah_pack_begin", "ah_pack", "ah_pack_finish",
             "ah_unpack", "ah_primers_compile", "ah_primers_compile_into", "ah_primers_table_bytes", "ah_primers_free", "ah_primers_count", "ah_primers_jit", "ah_primers_jit_check", "ah_primers_jit_variant", "ah_primers_use_jit",
             "ah_primers_launch_shape", "ah_scan_ws_size",
-            "ah_scan_primers", "ah_scan_primers_masked", "ah_route_hits", "ah_pair_ws_size", "ah_pair_amplicons", "ah_tm_nn", "ah_tm_duplex",
+            "ah_scan_primers", "ah_scan_primers_static", "ah_scan_primers_masked", "ah_route_hits", "ah_pair_ws_size", "ah_pair_amplicons", "ah_tm_nn", "ah_tm_duplex",
             "ah_extract_ws_size", "ah_extract", "ah_pack_pieces", "ah_fasta_ws_size", "ah_fasta_ingest",
             "ah_fasta_info", "ah_fasta_table", "ah_fasta_names_of", "ah_fasta_free", "ah_fasta_format",
             "ah_read_probe"]
@@ -551,6 +554,14 @@ def scan_primers(store, ps, hits, hit_cap, n_hits, ws, subset=None, stream=None)
     check(_lib.ah_scan_primers(C.byref(store.c), ps.h, _list_ptr(subset, n_hits), n_sub, _p(hits), hit_cap,
                                _p(n_hits), _p(ws), ws.numel() * ws.element_size(), _stream(stream)),
           "ah_scan_primers")
+
+
+def scan_primers_static(store, ps, hits, hit_cap, n_hits, subset=None, stream=None):
+    """ah_scan_primers with the library's fixed scratch array as its workspace
+    (no allocation anywhere; at most STATIC_SCAN_MAX_LIST listed sequences)."""
+    n_sub = 0 if subset is None else int(subset.numel())
+    check(_lib.ah_scan_primers_static(C.byref(store.c), ps.h, _list_ptr(subset, n_hits), n_sub, _p(hits), hit_cap,
+                                      _p(n_hits), _stream(stream)), "ah_scan_primers_static")
 
 
 def scan_primers_masked(store, ps, subset, pair_mask, hits, hit_cap, n_hits, ws, stream=None):

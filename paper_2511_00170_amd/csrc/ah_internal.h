@@ -37,6 +37,8 @@ ah_status ah_build_primer_set(const ah_pair_spec *h_pairs, uint32_t n_pairs, boo
 
 static inline hipStream_t ah_stream(void *s) { return (hipStream_t)s; }
 
+#define AH_MAX_DEVICES 64  // per-device state of the library (device ordinals 0..63)
+
 // Compute units of the current device (256 on MI355X if the query fails).
 static inline uint32_t ah_device_cus() {
     int dev = 0, cus = 0;

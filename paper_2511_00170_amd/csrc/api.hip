@@ -17,6 +17,7 @@ extern "C" const char *ah_status_str(ah_status s) {
     case AH_E_WORKSPACE: return "workspace too small";
     case AH_E_IO: return "file could not be opened or read";
     case AH_E_FORMAT: return "not FASTA (data before the first header, record or record count too large)";
+    case AH_E_SCRATCH: return "input larger than the library's fixed scratch array allows";
     default: return "unknown status";
     }
 }

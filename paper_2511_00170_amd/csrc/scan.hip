@@ -11,6 +11,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -571,5 +572,49 @@ extern "C" ah_status ah_scan_primers_masked(const ah_store *st, ah_primer_set ps
     if (!ps || !d_pair_mask) return AH_E_ARG;
     if (ps->n_pairs > 64) return AH_E_LIMIT;
     return scan_launch(st, ps, d_seq_subset, n_subset, d_pair_mask, d_hits, hit_cap, d_n_hits, d_ws, ws_bytes,
+                       stream);
+}
+
+// ---------------------------------------------------------------- no-allocation variant
+// For callers that cannot allocate device memory (code under graph capture,
+// serving loops, hosts that forbid hipMalloc): the scan's workspace -- the
+// tile count and first tile of every listed sequence -- lives in a fixed
+// array of the library instead of a caller buffer.  Each GPU holds its own
+// copy until the process ends.
+static __device__ __align__(256) uint8_t scratch[AH_STATIC_SCRATCH_BYTES];
+
+// Device address of `scratch` per device, looked up once with that device
+// current (the host-side name of the array is not a device address).
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[AH_MAX_DEVICES];
+
+static ah_status static_scratch(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= AH_MAX_DEVICES) return AH_E_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return AH_E_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return AH_OK;
+}
+
+extern "C" ah_status ah_scan_primers_static(const ah_store *st, ah_primer_set ps, const uint32_t *d_seq_subset,
+                                            uint32_t n_subset, ah_hit *d_hits, uint64_t hit_cap,
+                                            uint64_t *d_n_hits, void *stream) {
+    if (!st) return AH_E_ARG;
+    const uint32_t n_list = d_seq_subset ? n_subset : st->n_seqs;
+    if (n_list > AH_STATIC_SCAN_MAX_LIST) return AH_E_SCRATCH;
+    uint64_t need = 0;
+    ah_scan_ws_size(st, n_list, &need);
+    if (need > sizeof(scratch)) return AH_E_SCRATCH;
+    void *ws = nullptr;
+    const ah_status e = static_scratch(&ws);
+    if (e) return e;
+    // every workspace word the scan reads is written by the same call first
+    // (tile counts, then their prefix), so nothing needs clearing
+    return scan_launch(st, ps, d_seq_subset, n_subset, nullptr, d_hits, hit_cap, d_n_hits, ws, sizeof(scratch),
                        stream);
 }
