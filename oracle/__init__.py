@@ -30,8 +30,10 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 PARITY_UNPINNED = (
-    "Tm values against Biopython's Tm_NN for mismatched duplexes (the mismatch "
-    "tables are transcribed, not checked against a running Biopython)",
+    "the numeric values of the terminal-mismatch stacks (only a physical range is checked: every "
+    "entry but GG/CG is stabilising)",
+    "the numeric values of the dangling-end parameters other than .C/TG and CG/.C (only a range is checked)",
+    "the three tandem G.T stacks GG/TT, GT/TG, TG/GT (no printed free energy at hand)",
 )
 
 
@@ -60,11 +62,15 @@ def lib():
         L.or_pair.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_uint32, C.c_uint32, C.c_void_p, C.c_uint64]
         L.or_nn_thermo.restype = C.c_int
-        L.or_nn_thermo.argtypes = [C.c_char_p, C.c_char_p, P(C.c_double), P(C.c_double)]
+        L.or_nn_thermo.argtypes = [C.c_char_p, C.c_char_p, C.c_int, C.c_int, P(C.c_double), P(C.c_double)]
+        L.or_nn_table.restype = C.c_int
+        L.or_nn_table.argtypes = [C.c_int, C.c_int, C.c_char_p, P(C.c_double), C.c_int]
+        L.or_nn_init.restype = C.c_int
+        L.or_nn_init.argtypes = [C.c_int, P(C.c_double)]
         L.or_salt_correction.restype = C.c_int
         L.or_salt_correction.argtypes = [C.c_void_p, C.c_char_p, P(C.c_double), P(C.c_int)]
         L.or_tm_duplex.restype = C.c_double
-        L.or_tm_duplex.argtypes = [C.c_char_p, C.c_char_p, C.c_void_p, P(C.c_int)]
+        L.or_tm_duplex.argtypes = [C.c_char_p, C.c_char_p, C.c_int, C.c_void_p, P(C.c_int)]
         L.or_tm_amps.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
                                  C.c_double, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.or_extract.restype = C.c_int64
@@ -77,11 +83,13 @@ def lib():
 
 class _TmCond(C.Structure):
     _fields_ = [("na", C.c_double), ("k", C.c_double), ("tris", C.c_double), ("mg", C.c_double),
-                ("dntps", C.c_double), ("dnac1", C.c_double), ("dnac2", C.c_double), ("saltcorr", C.c_int)]
+                ("dntps", C.c_double), ("dnac1", C.c_double), ("dnac2", C.c_double), ("saltcorr", C.c_int),
+                ("nn_table", C.c_int)]
 
 
 def _cond(tm) -> _TmCond:
-    return _TmCond(tm.na_mM, tm.k_mM, tm.tris_mM, tm.mg_mM, tm.dntps_mM, tm.dnac1_nM, tm.dnac2_nM, tm.saltcorr)
+    return _TmCond(tm.na_mM, tm.k_mM, tm.tris_mM, tm.mg_mM, tm.dntps_mM, tm.dnac1_nM, tm.dnac2_nM, tm.saltcorr,
+                   int(getattr(tm, "nn_table", 3)))
 
 
 def _ptr(a: np.ndarray):
@@ -160,13 +168,37 @@ def pair(hits: np.ndarray, pairs, orient_mask: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- Tm
-def nn_thermo(seq: str, cseq: str):
-    """(dH kcal/mol, dS cal/K/mol) before salt correction, or None if untabulated."""
+def nn_thermo(seq: str, cseq: str, shift: int = 0, table: int = 3):
+    """(dH kcal/mol, dS cal/K/mol) before salt correction, or None if untabulated.
+    cseq is the partner strand written 3'->5'; cseq[i] faces seq[i - shift]."""
     dh, ds = C.c_double(0), C.c_double(0)
-    st = lib().or_nn_thermo(seq.encode(), cseq.encode(), C.byref(dh), C.byref(ds))
+    st = lib().or_nn_thermo(seq.encode(), cseq.encode(), int(shift), int(table), C.byref(dh), C.byref(ds))
     if st == 2:
         raise ValueError("bad duplex")
     return None if st == 1 else (dh.value, ds.value)
+
+
+def nn_table(which: str, table: int = 3):
+    """Parameter table as {key: (dH, dS)}: which = "wc" (Watson-Crick set
+    `table`), "imm" (internal mismatches), "tmm" (terminal mismatches), "de"
+    (dangling ends)."""
+    w = {"wc": 0, "imm": 1, "tmm": 2, "de": 3}[which]
+    keys = C.create_string_buffer(6 * 64)
+    vals = (C.c_double * 128)()
+    n = lib().or_nn_table(w, int(table), keys, vals, 64)
+    if n < 0:
+        raise ValueError((which, table))
+    raw = keys.raw
+    return {raw[6 * i:6 * i + 5].decode(): (vals[2 * i], vals[2 * i + 1]) for i in range(n)}
+
+
+def nn_init(table: int = 3) -> dict:
+    """Initiation terms of a Watson-Crick set: {name: (dH, dS)}."""
+    v = (C.c_double * 10)()
+    if lib().or_nn_init(int(table), v) < 0:
+        raise ValueError(table)
+    names = ("init", "terminal_AT", "terminal_GC", "one_GC", "all_AT")
+    return {n: (v[2 * i], v[2 * i + 1]) for i, n in enumerate(names)}
 
 
 def salt_correction(tm, seq: str):
@@ -179,10 +211,10 @@ def salt_correction(tm, seq: str):
     return corr.value, kind.value
 
 
-def tm_duplex(seq: str, cseq: str, tm) -> float:
+def tm_duplex(seq: str, cseq: str, tm, shift: int = 0) -> float:
     st = C.c_int(0)
     cond = _cond(tm)
-    v = lib().or_tm_duplex(seq.encode(), cseq.encode(), C.byref(cond), C.byref(st))
+    v = lib().or_tm_duplex(seq.encode(), cseq.encode(), int(shift), C.byref(cond), C.byref(st))
     if st.value == 2:
         raise ValueError("bad duplex")
     return float("nan") if st.value == 1 else v

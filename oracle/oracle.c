@@ -20,15 +20,14 @@
  *     extraction"; header fields: Supplementary "Headers and outputs".
  * Where the paper is silent the readings are named in comments (R-...).
  *
- * Parity unpinned: the numeric values of the internal-mismatch and
- * terminal-mismatch nearest-neighbour stacks, and the coefficients of salt
- * corrections 3, 4, 6 and 7.  They are transcribed from the primary papers
- * cited at them, but no published Tm of a mismatched duplex, and no
- * documented value for those corrections, is available to pin them (their
- * structure is checked: unit conversion, limits, monotonicity, the 2008
- * model's fall-back to the 2004 one).  The Watson-Crick stacks, corrections
- * 1, 2 and 5, the sodium equivalent and the strand concentration term are
- * pinned to documented values.
+ * Parity unpinned: the numeric values of the terminal-mismatch stacks (only
+ * their physical range is checked), of the three tandem G.T stacks, and of
+ * all but two dangling-end entries (only a range is checked).
+ * Everything else of the Tm model is pinned outside this file: documented
+ * Tm values of the Tm_NN model (every salt correction, the Watson-Crick
+ * tables, an internal mismatch, dangling ends), the free energies printed
+ * beside each Watson-Crick and internal-mismatch table, and duplexes summed
+ * by hand (terminal mismatches, initiation, dangling ends).
  *
  * Records exchanged with the Python wrapper (oracle/__init__.py):
  *   hit: 4 x u32 = {seq, pos, pair, kind | mm << 8}
@@ -435,20 +434,55 @@ typedef struct {
     double dh, ds;
 } nn_param;
 
-/* Watson-Crick stacks: unified parameters, SantaLucia (1998) PNAS 95:1460,
- * Table 2 (identical to Allawi & SantaLucia (1997) Biochemistry 36:10581). */
-static const nn_param NN_WC[] = {
-    {"AA/TT", -7.9, -22.2}, {"AT/TA", -7.2, -20.4}, {"TA/AT", -7.2, -21.3},
-    {"CA/GT", -8.5, -22.7}, {"GT/CA", -8.4, -22.4}, {"CT/GA", -7.8, -21.0},
-    {"GA/CT", -8.2, -22.2}, {"CG/GC", -10.6, -27.2}, {"GC/CG", -9.8, -24.4},
-    {"GG/CC", -8.0, -19.9},
-};
-/* Initiation with a terminal G.C or A.T pair, same source (applied per end). */
-static const double INIT_GC_DH = 0.1, INIT_GC_DS = -2.8;
-static const double INIT_AT_DH = 2.3, INIT_AT_DS = 4.1;
+/* Nearest-neighbour parameter sets for DNA/DNA duplexes that the Tm_NN
+ * model offers (selected by number, as it numbers them): Watson-Crick
+ * stacks and initiation terms.  Initiation: `init` for every duplex, `at` /
+ * `gc` per duplex end by its terminal pair, `one_gc` / `all_at` by whether
+ * any G.C pair occurs.  (The model's 5'-terminal T.A penalty is zero in all
+ * four sets and is left out.) */
+typedef struct {
+    nn_param stack[10];
+    double init_dh, init_ds;
+    double at_dh, at_ds;
+    double gc_dh, gc_ds;
+    double one_gc_dh, one_gc_ds;
+    double all_at_dh, all_at_ds;
+} nn_set;
 
-/* Internal single mismatches (one mismatched pair inside the stack):
- *   G.T  Allawi & SantaLucia (1997) Biochemistry 36:10581 (incl. tandem G.T);
+static const nn_set NN_SETS[5] = {
+    /* 0: unused (0 selects set 3) */
+    {{{"", 0, 0}}, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+    /* 1: Breslauer, Frank, Bloecker & Marky (1986) PNAS 83:3746, Table 2;
+     *    initiation 5.0 (with a G.C pair) or 6.0 (A.T only) kcal/mol at 25 C,
+     *    entropic. */
+    {{{"AA/TT", -9.1, -24.0}, {"AT/TA", -8.6, -23.9}, {"TA/AT", -6.0, -16.9}, {"CA/GT", -5.8, -12.9},
+      {"GT/CA", -6.5, -17.3}, {"CT/GA", -7.8, -20.8}, {"GA/CT", -5.6, -13.5}, {"CG/GC", -11.9, -27.8},
+      {"GC/CG", -11.1, -26.7}, {"GG/CC", -11.0, -26.6}},
+     0, 0, 0, 0, 0, 0, 0, -16.8, 0, -20.1},
+    /* 2: Sugimoto, Nakano, Yoneyama & Honda (1996) Nucleic Acids Res
+     *    24:4501, Table 1; one initiation term per duplex. */
+    {{{"AA/TT", -8.0, -21.9}, {"AT/TA", -5.6, -15.2}, {"TA/AT", -6.6, -18.4}, {"CA/GT", -8.2, -21.0},
+      {"GT/CA", -9.4, -25.5}, {"CT/GA", -6.6, -16.4}, {"GA/CT", -8.8, -23.5}, {"CG/GC", -11.8, -29.0},
+      {"GC/CG", -10.5, -26.4}, {"GG/CC", -10.9, -28.4}},
+     0.6, -9.0, 0, 0, 0, 0, 0, 0, 0, 0},
+    /* 3 (default): unified parameters, SantaLucia (1998) PNAS 95:1460,
+     *    Table 2 (= Allawi & SantaLucia (1997) Biochemistry 36:10581);
+     *    initiation per end with a terminal G.C or A.T pair. */
+    {{{"AA/TT", -7.9, -22.2}, {"AT/TA", -7.2, -20.4}, {"TA/AT", -7.2, -21.3}, {"CA/GT", -8.5, -22.7},
+      {"GT/CA", -8.4, -22.4}, {"CT/GA", -7.8, -21.0}, {"GA/CT", -8.2, -22.2}, {"CG/GC", -10.6, -27.2},
+      {"GC/CG", -9.8, -24.4}, {"GG/CC", -8.0, -19.9}},
+     0, 0, 2.3, 4.1, 0.1, -2.8, 0, 0, 0, 0},
+    /* 4: SantaLucia & Hicks (2004) Annu Rev Biophys Biomol Struct 33:415,
+     *    Table 1; one initiation term plus a penalty per terminal A.T pair. */
+    {{{"AA/TT", -7.6, -21.3}, {"AT/TA", -7.2, -20.4}, {"TA/AT", -7.2, -21.3}, {"CA/GT", -8.5, -22.7},
+      {"GT/CA", -8.4, -22.4}, {"CT/GA", -7.8, -21.0}, {"GA/CT", -8.2, -22.2}, {"CG/GC", -10.6, -27.2},
+      {"GC/CG", -9.8, -24.4}, {"GG/CC", -8.0, -19.9}},
+     0.2, -5.7, 2.2, 6.9, 0, 0, 0, 0, 0, 0},
+};
+
+/* Internal single mismatches (one mismatched pair inside the stack; also
+ * the tandem G.T stacks of the first paper):
+ *   G.T  Allawi & SantaLucia (1997) Biochemistry 36:10581;
  *   G.A  Allawi & SantaLucia (1998) Biochemistry 37:2170;
  *   C.T  Allawi & SantaLucia (1998) Nucleic Acids Res 26:2694;
  *   A.C  Allawi & SantaLucia (1998) Biochemistry 37:9435;
@@ -474,8 +508,9 @@ static const nn_param NN_IMM[] = {
     {"AT/TT", -2.7, -10.8}, {"CT/GT", -5.0, -15.8}, {"GT/CT", -2.2, -8.4}, {"TT/AT", 0.2, -1.5},
 };
 
-/* Terminal mismatches (the second pair of the stack is the mismatched end
- * pair): Bommarito, Peyret & SantaLucia (2000) Nucleic Acids Res 28:1929. */
+/* Terminal mismatches: the second pair of the stack is the mismatched duplex
+ * end, the first a Watson-Crick pair.  The Tm_NN model's DNA table, from
+ * SantaLucia & Peyret (2001), patent application WO 01/94611. */
 static const nn_param NN_TMM[] = {
     {"AA/TA", -3.1, -7.8}, {"TA/AA", -2.5, -6.3}, {"CA/GA", -4.3, -10.7}, {"GA/CA", -8.0, -22.5},
     {"AC/TC", -0.1, 0.5}, {"TC/AC", -0.7, -1.3}, {"CC/GC", -2.1, -5.1}, {"GC/CC", -3.9, -10.6},
@@ -491,17 +526,38 @@ static const nn_param NN_TMM[] = {
     {"GG/CT", -5.7, -15.9}, {"GT/CG", -5.9, -16.1}, {"TG/AT", -3.9, -10.5}, {"TT/AG", -3.6, -9.8},
 };
 
+/* Dangling ends: one unpaired base ('.' opposite it) beside a terminal
+ * Watson-Crick pair.  "XY/.Z": top 5'-XY-3' over bottom 3'-.Z-5', X a
+ * 5'-dangling base of the top strand; ".X/YZ": top 5'-.X-3' over bottom
+ * 3'-YZ-5', Y a 3'-dangling base of the bottom strand.  Bommarito, Peyret &
+ * SantaLucia (2000) Nucleic Acids Res 28:1929. */
+static const nn_param NN_DE[] = {
+    {"AA/.T", 0.2, 2.3}, {"AC/.G", -6.3, -17.1}, {"AG/.C", -3.7, -10.0}, {"AT/.A", -2.9, -7.6},
+    {"CA/.T", 0.6, 3.3}, {"CC/.G", -4.4, -12.6}, {"CG/.C", -4.0, -11.9}, {"CT/.A", -4.1, -13.0},
+    {"GA/.T", -1.1, -1.6}, {"GC/.G", -5.1, -14.0}, {"GG/.C", -3.9, -10.9}, {"GT/.A", -4.2, -15.0},
+    {"TA/.T", -6.9, -20.0}, {"TC/.G", -4.0, -10.9}, {"TG/.C", -4.9, -13.8}, {"TT/.A", -0.2, -0.5},
+    {".A/AT", -0.7, -0.8}, {".C/AG", -2.1, -3.9}, {".G/AC", -5.9, -16.5}, {".T/AA", -0.5, -1.1},
+    {".A/CT", 4.4, 14.9}, {".C/CG", -0.2, -0.1}, {".G/CC", -2.6, -7.4}, {".T/CA", 4.7, 14.2},
+    {".A/GT", -1.6, -3.6}, {".C/GG", -3.9, -11.2}, {".G/GC", -3.2, -10.4}, {".T/GA", -4.1, -13.1},
+    {".A/TT", 2.9, 10.4}, {".C/TG", -4.4, -13.1}, {".G/TC", -5.2, -15.0}, {".T/TA", -3.8, -12.6},
+};
+
 #define NPAR(t) ((int)(sizeof(t) / sizeof((t)[0])))
+
+/* Find "XY/WZ" in a table as written. */
+static const nn_param *nn_exact(const nn_param *tab, int n, const char key[6])
+{
+    for (int i = 0; i < n; i++)
+        if (!strcmp(tab[i].key, key)) return &tab[i];
+    return NULL;
+}
 
 /* Find "XY/WZ" in a table, first as written, then read from the other strand. */
 static const nn_param *nn_find(const nn_param *tab, int n, const char key[6])
 {
     char rev[6] = {key[4], key[3], '/', key[1], key[0], 0};
-    for (int i = 0; i < n; i++)
-        if (!strcmp(tab[i].key, key)) return &tab[i];
-    for (int i = 0; i < n; i++)
-        if (!strcmp(tab[i].key, rev)) return &tab[i];
-    return NULL;
+    const nn_param *p = nn_exact(tab, n, key);
+    return p ? p : nn_exact(tab, n, rev);
 }
 
 static int wc_pair(char top, char bottom)
@@ -514,6 +570,7 @@ typedef struct {
     double na, k, tris, mg, dntps; /* mM */
     double dnac1, dnac2;           /* nM */
     int saltcorr;
+    int nn_table;                  /* 1..4 as in NN_SETS; 0 = 3 */
 } or_tm_cond;
 
 /* Monovalent-equivalent concentration in M (von Ahsen et al. 2001 for Mg2+). */
@@ -597,68 +654,103 @@ int or_salt_correction(const or_tm_cond *c, const char *seq, double *corr, int *
     return 0;
 }
 
+#define OR_MAXC 64 /* longest partner strand of an explicit duplex */
+
 /*
- * dH and dS (before salt correction) of the duplex of `seq` (5'->3') with
- * `cseq` (its partner strand written 3'->5', position j pairing with seq[j]);
- * both of equal length L >= 2.  Steps 1-3 below; returns 0 ok, 1 untabulated
- * stack or non-ACGT base, 2 bad input.  or_tm_duplex adds step 4.
- * Steps (SantaLucia 1998; terminal mismatches as Bommarito et al. 2000):
- *  1. a mismatched first pair: add the terminal-mismatch stack read from the
- *     other strand and drop that pair; same for a mismatched last pair;
- *  2. initiation per duplex end, chosen by the primer's own end bases (R-init);
- *  3. sum the stacks of the remaining pairs in 5'->3' order: mismatch table,
- *     else Watson-Crick table; a stack in neither is untabulated (status 1);
- *  4. salt correction, then Tm = 1000 dH / (dS + R ln C) - 273.15, R = 1.987,
- *     C = (C_high - C_low / 2) for two distinct strands (R-selfcomp: never).
- * Returns Tm in degrees C; *status = 0 ok, 1 untabulated stack, 2 bad input.
+ * dH and dS (before salt correction) of the duplex of `seq` (5'->3', 2..32
+ * letters) with `cseq` (its partner strand written 3'->5', 1..64 letters),
+ * cseq[i] facing seq[i - shift] (shift 0 with equal lengths: position j
+ * pairs with position j).  `table` selects the Watson-Crick set (NN_SETS).
+ * Returns 0 ok, 1 untabulated stack or end or a non-ACGT letter, 2 bad input
+ * (fewer than two facing positions).  or_tm_duplex adds the salt term.
+ * Steps, in this order (the Tm_NN model; SantaLucia 1998 formulation):
+ *  1. align the strands; an end may keep one unpaired base of either strand
+ *     (a dangling end), any further overhang is ignored;
+ *  2. a dangling end is charged with its dangling-end parameter and leaves
+ *     the duplex (left end first, then right end);
+ *  3. a mismatched end pair is charged with the terminal-mismatch stack and
+ *     leaves the helix (left, then right);
+ *  4. initiation from the primer strand as given (R-init: its end bases and
+ *     whether it holds a G or C choose the terms, also when an end pair was
+ *     removed in steps 2-3, as the Tm_NN model does);
+ *  5. the stacks of the remaining pairs in 5'->3' order: Watson-Crick set,
+ *     else the internal-mismatch table; a stack in neither is untabulated.
  */
-int or_nn_thermo(const char *seq, const char *cseq, double *dh_out, double *ds_out)
+int or_nn_thermo(const char *seq, const char *cseq, int shift, int table, double *dh_out, double *ds_out)
 {
-    int L = (int)strlen(seq);
-    if (L < 2 || (int)strlen(cseq) != L) return 2;
-    for (int j = 0; j < L; j++) {
-        if (!strchr("ACGT", seq[j]) || !strchr("ACGT", cseq[j])) return 1;
+    int L = (int)strlen(seq), Lc = (int)strlen(cseq);
+    if (L < 2 || L > OR_MAXL || Lc < 1 || Lc > OR_MAXC || shift < -OR_MAXC || shift > OR_MAXC) return 2;
+    if (table == 0) table = 3;
+    if (table < 1 || table > 4) return 2;
+    const nn_set *set = &NN_SETS[table];
+    for (int j = 0; j < L; j++)
+        if (!strchr("ACGT", seq[j])) return 1;
+    for (int j = 0; j < Lc; j++)
+        if (!strchr("ACGT", cseq[j])) return 1;
+
+    /* 1. alignment: column i holds top[i] over bot[i], '.' = no base */
+    char top[2 * OR_MAXC + 8], bot[2 * OR_MAXC + 8];
+    int st = shift > 0 ? shift : 0, sb = shift < 0 ? -shift : 0;
+    int n = L + st > Lc + sb ? L + st : Lc + sb;
+    for (int i = 0; i < n; i++) {
+        top[i] = (i >= st && i < st + L) ? seq[i - st] : '.';
+        bot[i] = (i >= sb && i < sb + Lc) ? cseq[i - sb] : '.';
     }
+    int facing = 0;
+    for (int i = 0; i < n; i++) facing += top[i] != '.' && bot[i] != '.';
+    if (facing < 2) return 2;
+    int lo = 0, hi = n - 1; /* inclusive column range still in the duplex */
+    while ((top[lo] == '.' && top[lo + 1] == '.') || (bot[lo] == '.' && bot[lo + 1] == '.')) lo++;
+    while ((top[hi] == '.' && top[hi - 1] == '.') || (bot[hi] == '.' && bot[hi - 1] == '.')) hi--;
+
     double dh = 0.0, ds = 0.0;
-    int lo = 0, hi = L - 1; /* inclusive pair range still in the helix */
     char key[6];
     key[2] = '/';
     key[5] = 0;
+    const nn_param *p;
 
-    /* 1. terminal mismatches */
-    key[0] = cseq[1]; key[1] = cseq[0]; key[3] = seq[1]; key[4] = seq[0];
-    {
-        /* left end, read from the partner strand so the end pair comes second */
-        const nn_param *p = NULL;
-        for (int i = 0; i < NPAR(NN_TMM); i++)
-            if (!strcmp(NN_TMM[i].key, key)) p = &NN_TMM[i];
-        if (p) { dh += p->dh; ds += p->ds; lo = 1; }
+    /* 2. dangling ends; the right end is read from the partner strand */
+    if (top[lo] == '.' || bot[lo] == '.') {
+        key[0] = top[lo]; key[1] = top[lo + 1]; key[3] = bot[lo]; key[4] = bot[lo + 1];
+        if (!(p = nn_exact(NN_DE, NPAR(NN_DE), key))) return 1;
+        dh += p->dh; ds += p->ds; lo++;
     }
-    key[0] = seq[hi - 1]; key[1] = seq[hi]; key[3] = cseq[hi - 1]; key[4] = cseq[hi];
+    if (top[hi] == '.' || bot[hi] == '.') {
+        key[0] = bot[hi]; key[1] = bot[hi - 1]; key[3] = top[hi]; key[4] = top[hi - 1];
+        if (!(p = nn_exact(NN_DE, NPAR(NN_DE), key))) return 1;
+        dh += p->dh; ds += p->ds; hi--;
+    }
+
+    /* 3. terminal mismatches; the left end is read from the partner strand
+     * so that the end pair comes second */
+    key[0] = bot[lo + 1]; key[1] = bot[lo]; key[3] = top[lo + 1]; key[4] = top[lo];
+    if ((p = nn_exact(NN_TMM, NPAR(NN_TMM), key))) { dh += p->dh; ds += p->ds; lo++; }
     if (hi - 1 >= lo) {
-        const nn_param *p = NULL;
-        for (int i = 0; i < NPAR(NN_TMM); i++)
-            if (!strcmp(NN_TMM[i].key, key)) p = &NN_TMM[i];
-        if (p) { dh += p->dh; ds += p->ds; hi -= 1; }
+        key[0] = top[hi - 1]; key[1] = top[hi]; key[3] = bot[hi - 1]; key[4] = bot[hi];
+        if ((p = nn_exact(NN_TMM, NPAR(NN_TMM), key))) { dh += p->dh; ds += p->ds; hi--; }
     }
 
-    /* 2. initiation (one term per end, by the end bases of seq as written) */
+    /* 4. initiation from the primer strand as given */
     {
+        int any_gc = 0;
+        for (int j = 0; j < L; j++) any_gc |= seq[j] == 'G' || seq[j] == 'C';
+        dh += set->init_dh; ds += set->init_ds;
+        if (any_gc) { dh += set->one_gc_dh; ds += set->one_gc_ds; }
+        else { dh += set->all_at_dh; ds += set->all_at_ds; }
         char ends[2] = {seq[0], seq[L - 1]};
         for (int e = 0; e < 2; e++) {
-            if (ends[e] == 'A' || ends[e] == 'T') { dh += INIT_AT_DH; ds += INIT_AT_DS; }
-            else { dh += INIT_GC_DH; ds += INIT_GC_DS; }
+            if (ends[e] == 'A' || ends[e] == 'T') { dh += set->at_dh; ds += set->at_ds; }
+            else { dh += set->gc_dh; ds += set->gc_ds; }
         }
     }
 
-    /* 3. stacks */
+    /* 5. stacks */
     for (int j = lo; j < hi; j++) {
-        key[0] = seq[j]; key[1] = seq[j + 1]; key[3] = cseq[j]; key[4] = cseq[j + 1];
-        const nn_param *p = NULL;
-        if (!(wc_pair(seq[j], cseq[j]) && wc_pair(seq[j + 1], cseq[j + 1])))
-            p = nn_find(NN_IMM, NPAR(NN_IMM), key);
+        key[0] = top[j]; key[1] = top[j + 1]; key[3] = bot[j]; key[4] = bot[j + 1];
+        if (wc_pair(top[j], bot[j]) && wc_pair(top[j + 1], bot[j + 1]))
+            p = nn_find(set->stack, 10, key);
         else
-            p = nn_find(NN_WC, NPAR(NN_WC), key);
+            p = nn_find(NN_IMM, NPAR(NN_IMM), key);
         if (!p) return 1;
         dh += p->dh;
         ds += p->ds;
@@ -669,14 +761,18 @@ int or_nn_thermo(const char *seq, const char *cseq, double *dh_out, double *ds_o
     return 0;
 }
 
-double or_tm_duplex(const char *seq, const char *cseq, const or_tm_cond *cond, int *status)
+/* Tm (degrees C) of the duplex: the salt correction (on the primer strand),
+ * then Tm = 1000 dH / (dS + R ln C) - 273.15, R = 1.987, C = C_high -
+ * C_low / 2 for two distinct strands (R-selfcomp: never the self-
+ * complementary form).  *status = 0 ok, 1 untabulated (returns -inf), 2 bad
+ * input. */
+double or_tm_duplex(const char *seq, const char *cseq, int shift, const or_tm_cond *cond, int *status)
 {
     double dh = 0.0, ds = 0.0;
-    *status = or_nn_thermo(seq, cseq, &dh, &ds);
+    *status = or_nn_thermo(seq, cseq, shift, cond->nn_table, &dh, &ds);
     if (*status == 2) return 0.0;
     if (*status == 1) return -INFINITY;
 
-    /* 4. salt correction and Tm */
     double corr = 0.0;
     int kind = 0;
     if (or_salt_correction(cond, seq, &corr, &kind)) { *status = 2; return 0.0; }
@@ -688,6 +784,42 @@ double or_tm_duplex(const char *seq, const char *cseq, const or_tm_cond *cond, i
     if (kind == 1) tm += corr;
     if (kind == 6) tm = 1.0 / (1.0 / (tm + 273.15) + corr) - 273.15;
     return tm;
+}
+
+/* The partner table: parameter values of one set or table for inspection
+ * by the tests (which=0: Watson-Crick set `table`; 1 internal mismatches;
+ * 2 terminal mismatches; 3 dangling ends).  Returns the number of entries
+ * and copies up to cap keys (6 bytes each) and (dH, dS) pairs. */
+int or_nn_table(int which, int table, char *keys, double *vals, int cap)
+{
+    const nn_param *t;
+    int n;
+    if (which == 0) {
+        if (table == 0) table = 3;
+        if (table < 1 || table > 4) return -1;
+        t = NN_SETS[table].stack; n = 10;
+    } else if (which == 1) { t = NN_IMM; n = NPAR(NN_IMM); }
+    else if (which == 2) { t = NN_TMM; n = NPAR(NN_TMM); }
+    else if (which == 3) { t = NN_DE; n = NPAR(NN_DE); }
+    else return -1;
+    for (int i = 0; i < n && i < cap; i++) {
+        memcpy(keys + 6 * i, t[i].key, 6);
+        vals[2 * i] = t[i].dh;
+        vals[2 * i + 1] = t[i].ds;
+    }
+    return n;
+}
+
+/* Initiation terms of a Watson-Crick set: [init, at, gc, one_gc, all_at] x (dH, dS). */
+int or_nn_init(int table, double *vals)
+{
+    if (table == 0) table = 3;
+    if (table < 1 || table > 4) return -1;
+    const nn_set *s = &NN_SETS[table];
+    double v[10] = {s->init_dh, s->init_ds, s->at_dh, s->at_ds, s->gc_dh, s->gc_ds,
+                    s->one_gc_dh, s->one_gc_ds, s->all_at_dh, s->all_at_ds};
+    memcpy(vals, v, sizeof v);
+    return 0;
 }
 
 /* The partner strand (3'->5') of a site, from the genome codes.
@@ -732,7 +864,7 @@ static double site_tm(const char *primer, const char *cseq, const or_tm_cond *co
             r /= (uint64_t)nset[j];
         }
         int st;
-        double t = or_tm_duplex(v, cseq, cond, &st);
+        double t = or_tm_duplex(v, cseq, 0, cond, &st);
         if (st != 0) { (*skipped)++; continue; }
         if (t > best) best = t;
     }

@@ -92,6 +92,7 @@ class TmSpec:
     saltcorr: int = 5
     threshold_C: float = 45.0
     filter: bool = True
+    nn_table: int = 3          # Watson-Crick parameter set, numbered as the Tm_NN model numbers them
 
 
 @dataclasses.dataclass

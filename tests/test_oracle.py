@@ -357,12 +357,6 @@ def comp(s):
     return "".join(_WC[c] for c in s)
 
 
-def test_tm_biopython_documented_value():
-    for seq, na, d1, d2, sc, tm2 in _read_golden("tm_nn_perfect_duplex.txt"):
-        t = TmSpec(na_mM=float(na), dnac1_nM=float(d1), dnac2_nM=float(d2), saltcorr=int(sc))
-        assert "%.2f" % oracle.tm_duplex(seq, comp(seq), t) == tm2
-
-
 def test_nn_watson_crick_free_energies():
     rows = _read_golden("santalucia1998_nn.txt")
     init_dg = {"GC": 0.98, "AT": 1.03}  # same table: initiation with terminal G.C / A.T
@@ -417,12 +411,12 @@ def test_tm_mismatch_lowers_and_untabulated_is_nan():
     c = list(comp(seq))
     c[8] = "A" if c[8] != "A" else "C"
     assert oracle.tm_duplex(seq, "".join(c), TmSpec()) < perfect
+    # two adjacent mismatches that are not a tandem G.T: no table covers the
+    # stack between them, so the duplex is untabulated (the wrapper gives NaN)
     c2 = list(comp(seq))
-    c2[8] = "A" if c2[8] != "A" else "C"
-    c2[9] = "A" if c2[9] != "A" else "C"   # adjacent mismatches: not tabulated
-    if "".join(c2[8:10]) not in ("",):
-        v = oracle.tm_duplex(seq, "".join(c2), TmSpec())
-        assert math.isnan(v) or v < perfect
+    c2[8], c2[9] = "A", "A"      # opposite A (A.A) and G (G.A)
+    assert seq[8:10] == "AG"
+    assert math.isnan(oracle.tm_duplex(seq, "".join(c2), TmSpec()))
 
 
 def test_tm_primer_concentration_formula():
