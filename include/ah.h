@@ -250,14 +250,14 @@ ah_status ah_scan_primers_static(const ah_store *st, ah_primer_set ps, const uin
  * ah_scan_primers restricted to the (sequence, pair) combinations asked for;
  * a sequence whose word is 0 still costs its loads, so callers leave it out
  * of the subset.  Serving uses this to batch requests that ask for different
- * pairs on different sequences (Discussion and Methods, "Webserver").
+ * pairs on different sequences (Supplementary, "Webserver").
  * Errors: as ah_scan_primers; AH_E_LIMIT if the set has more than 64 pairs. */
 ah_status ah_scan_primers_masked(const ah_store *st, ah_primer_set ps, const uint32_t *d_seq_subset,
                                  uint32_t n_subset, const uint64_t *d_pair_mask, ah_hit *d_hits, uint64_t hit_cap,
                                  uint64_t *d_n_hits, void *d_ws, uint64_t ws_bytes, void *stream);
 
-/* Route hits of a shared scan to the requests of a serving batch (Discussion
- * and Methods, "Webserver").  Hit h = (seq s, pair q, mm) is copied once for
+/* Route hits of a shared scan to the requests of a serving batch (Discussion;
+ * Supplementary, "Webserver").  Hit h = (seq s, pair q, mm) is copied once for
  * every request r < n_req with bit r of d_seq_req[s] set (the request asked
  * for sequence s), d_vpair[r * n_pool + q] != 0xFFFF (it asked for pool pair
  * q) and mm <= d_kmax[r] (its own mismatch bound).  The copy's pair field is
@@ -286,7 +286,7 @@ typedef struct {
     uint32_t end;    /* end of the downstream (minus) site */
     uint16_t pair;
     uint8_t orient;  /* 0 FR, 1 RF, 2 FF, 3 RR */
-    uint8_t flags;   /* reserved, 0 */
+    uint8_t flags;   /* bit 0: a barcode was clipped at a sequence end (set by ah_extract; 0 before) */
 } ah_amp;            /* 16 bytes */
 
 #define AH_ORIENT_FR 1u
@@ -304,14 +304,24 @@ ah_status ah_pair_amplicons(const ah_store *st, ah_primer_set ps, const ah_hit *
 
 /* ------------------------------------------------------------------------
  * Nearest-neighbour melting temperature (Implementations, "AHv2": the model
- * of Biopython's Tm_NN).  Per amplicon, each of its two sites gets the
- * maximum over the concrete variants of its primer of the duplex Tm of
- * (variant 5'->3', genome strand it anneals to); the amplicon Tm is the
- * smaller site Tm; pass = Tm >= threshold_C (or 1 when filter == 0).  FP64.
- * Stacks: Watson-Crick (SantaLucia 1998), internal single mismatches
- * (Allawi & SantaLucia 1997/1998, Peyret et al. 1999), terminal mismatches
- * (Bommarito et al. 2000).  A variant with a stack none of them covers is
- * skipped; a site with no usable variant has Tm = -inf.
+ * of Biopython's Tm_NN, every parameter combination).  Per amplicon, each of
+ * its two sites gets the maximum over the concrete variants of its primer of
+ * the duplex Tm of (variant 5'->3', genome strand it anneals to); the
+ * amplicon Tm is the smaller site Tm; pass = Tm >= threshold_C (or 1 when
+ * filter == 0).  FP64.
+ * Duplex Tm, in this order: a dangling end (explicit duplexes only;
+ * Bommarito et al. 2000) and then a mismatched end pair (terminal-mismatch
+ * stack, SantaLucia & Peyret 2001) leave the helix with their terms;
+ * initiation from the primer strand as given (its end bases, whether it
+ * holds a G or C); the remaining Watson-Crick stacks of the selected set and
+ * internal single mismatches (Allawi & SantaLucia 1997/1998, Peyret et al.
+ * 1999); the salt term; Tm = 1000 dH / (dS + 1.987 ln C) - 273.15.  A
+ * variant with a stack none of the tables covers is skipped; a site with no
+ * usable variant has Tm = -inf.
+ * nn_table (Watson-Crick set and initiation, numbered as the Tm_NN model
+ * numbers its DNA tables): 1 Breslauer et al. 1986, 2 Sugimoto et al. 1996,
+ * 3 SantaLucia 1998 unified (= Allawi & SantaLucia 1997), 4 SantaLucia &
+ * Hicks 2004; 0 = 3.
  * saltcorr (the corrections the Tm_NN model offers; [Na+eq] = Na + K +
  * Tris/2 + 120 sqrt(Mg - dNTPs) mM, the last term only when Mg > dNTPs
  * (von Ahsen et al. 2001); N and the G+C fraction are the primer strand's):
@@ -326,8 +336,8 @@ ah_status ah_pair_amplicons(const ah_store *st, ah_primer_set ps, const ah_hit *
  *   7 1/Tm += the Mg2+ model of Owczarzy et al. 2008 (free Mg2+ after dNTP
  *     binding; monovalent ions Na + K + Tris/2; the 2004 formula when
  *     sqrt[Mg2+]/[mon] < 0.22)
- * AH_E_ARG for another value or a zero concentration under a logarithm.
- * Strand concentration C = C_high - C_low / 2.
+ * AH_E_ARG for another nn_table or saltcorr value or a zero concentration
+ * under a logarithm.  Strand concentration C = C_high - C_low / 2.
  * ---------------------------------------------------------------------- */
 typedef struct {
     double na_mM, k_mM, tris_mM, mg_mM, dntps_mM;
@@ -339,6 +349,8 @@ typedef struct {
      * replaces threshold_C for that pair's amplicons (serving batches whose
      * requests ask for different thresholds). */
     const double *d_pair_threshold;
+    int32_t nn_table;
+    int32_t reserved;  /* 0 */
 } ah_tm_params;
 
 /* d_tm[n], d_tm_site[n][2] (upstream, downstream), d_pass[n]; n = min(*d_n_amps, amp_cap). */
@@ -346,11 +358,18 @@ ah_status ah_tm_nn(const ah_store *st, ah_primer_set ps, const ah_amp *d_amps, c
                    uint64_t amp_cap, const ah_tm_params *p, double *d_tm, double *d_tm_site, uint8_t *d_pass,
                    void *stream);
 
-/* Tm of n explicit duplexes: d_seq and d_cseq hold n rows of `stride` bytes
- * (seq 5'->3'; cseq its partner written 3'->5'), d_len[i] <= 32 letters.
- * Writes d_tm[i] (NaN when a stack is not tabulated or a letter is not ACGT). */
-ah_status ah_tm_duplex(const char *d_seq, const char *d_cseq, const uint32_t *d_len, uint32_t n, uint32_t stride,
-                       const ah_tm_params *p, double *d_tm, void *stream);
+/* Tm of n explicit duplexes.  Row i of d_seq holds the primer strand
+ * (5'->3', d_len[i] letters, 2..32) and row i of d_cseq its partner strand
+ * written 3'->5' (d_clen[i] letters, 1..64; d_clen NULL = d_len), rows
+ * `stride` bytes apart; d_cseq[i][j] faces d_seq[i][j - d_shift[i]]
+ * (d_shift NULL = 0, |shift| <= 64).  An end may keep one unpaired base of
+ * either strand (a dangling end); further overhang is ignored.  Writes
+ * d_tm[i]: NaN when a letter is not ACGT, a stack or dangling end is not
+ * tabulated, fewer than two positions face each other, or a length is out
+ * of range. */
+ah_status ah_tm_duplex(const char *d_seq, const char *d_cseq, const uint32_t *d_len, const uint32_t *d_clen,
+                       const int32_t *d_shift, uint32_t n, uint32_t stride, const ah_tm_params *p, double *d_tm,
+                       void *stream);
 
 /* ------------------------------------------------------------------------
  * Extract (Supplementary, "Primer trimming and barcode extraction" and
@@ -359,7 +378,9 @@ ah_status ah_tm_duplex(const char *d_seq, const char *d_cseq, const uint32_t *d_
  * trim removes both primer sites.  fb = the fb_len bases upstream of the
  * forward site and rb = the rb_len bases downstream of the reverse site (FR,
  * FF, RR); for RF the opposite sides, both reverse-complemented.  Barcodes
- * are clipped at sequence ends (real lengths in d_bc_len[n][2]).
+ * are clipped at sequence ends (real lengths in d_bc_len[n][2]); ah_extract
+ * then sets bit 0 of that amplicon's flags, and clears it otherwise (the
+ * flags byte is the only part of d_amps it writes).
  * fprimer/rprimer: the genome bases under the forward/reverse site in that
  * primer's orientation (FF/RR: upstream / downstream site), NUL-padded to 32.
  * Amplicons with d_pass[i] == 0 (d_pass may be NULL) produce nothing.
@@ -375,7 +396,7 @@ ah_status ah_extract_ws_size(uint64_t amp_cap, uint64_t *bytes);
 /* d_seq_off has amp_cap + 1 entries; d_fb [n][fb_len], d_rb [n][rb_len],
  * d_fprimer/d_rprimer [n][32]; *d_n_bytes = total sequence bytes (bytes past
  * seq_cap are not written). */
-ah_status ah_extract(const ah_store *st, ah_primer_set ps, const ah_amp *d_amps, const uint64_t *d_n_amps,
+ah_status ah_extract(const ah_store *st, ah_primer_set ps, ah_amp *d_amps, const uint64_t *d_n_amps,
                      uint64_t amp_cap, const uint8_t *d_pass, const ah_extract_opts *o, char *d_seq, uint64_t seq_cap,
                      uint64_t *d_seq_off, char *d_fb, char *d_rb, uint8_t *d_bc_len, char *d_fprimer,
                      char *d_rprimer, uint64_t *d_n_bytes, void *d_ws, uint64_t ws_bytes, void *stream);

@@ -972,7 +972,8 @@ static uint64_t put_span(const uint8_t *ascii, uint64_t base, uint64_t a, uint64
  *             fb = s[start-fb : start], rb = s[end : end+rb];
  *   RF:       the reverse complement of the same spans; fb = rc(s[end : end+fb]),
  *             rb = rc(s[start-rb : start]).
- * Barcodes are clipped at the sequence ends (R-clip), real lengths in bc_len.
+ * Barcodes are clipped at the sequence ends (R-clip), real lengths in bc_len;
+ * flags[i] = 1 when a clipped barcode is shorter than asked for, else 0.
  * fprimer / rprimer: the genome bases under the forward / reverse primer's
  * site, read 5'->3' in that primer's orientation (FF/RR: upstream site ->
  * fprimer, downstream site -> rprimer), NUL-padded to 32 bytes.
@@ -981,7 +982,8 @@ static uint64_t put_span(const uint8_t *ascii, uint64_t base, uint64_t a, uint64
  */
 int64_t or_extract(const uint8_t *ascii, const uint64_t *off, const char *const *primers, const uint32_t *amps,
                    uint64_t n_amps, const uint8_t *pass, int trim, int fb_len, int rb_len, char *seq_out,
-                   uint64_t seq_cap, uint64_t *seq_off, char *fb, char *rb, uint8_t *bc_len, char *fpr, char *rpr)
+                   uint64_t seq_cap, uint64_t *seq_off, char *fb, char *rb, uint8_t *bc_len, char *fpr, char *rpr,
+                   uint8_t *flags)
 {
     uint64_t pos = 0;
     char tmp_buf[OR_MAXL];
@@ -995,6 +997,7 @@ int64_t or_extract(const uint8_t *ascii, const uint64_t *off, const char *const 
         if (fb_len) memset(fb + (uint64_t)fb_len * i, 0, (size_t)fb_len);
         if (rb_len) memset(rb + (uint64_t)rb_len * i, 0, (size_t)rb_len);
         bc_len[2 * i] = bc_len[2 * i + 1] = 0;
+        flags[i] = 0;
         if (pass && !pass[i]) continue;
         int lp = (o == 0 || o == 2) ? 0 : 1;
         int rp = (o == 0 || o == 3) ? 1 : 0;
@@ -1016,6 +1019,7 @@ int64_t or_extract(const uint8_t *ascii, const uint64_t *off, const char *const 
         }
         bc_len[2 * i] = (uint8_t)put_span(ascii, base, f0, f1, rc, fb + (uint64_t)fb_len * i);
         bc_len[2 * i + 1] = (uint8_t)put_span(ascii, base, r0, r1, rc, rb + (uint64_t)rb_len * i);
+        flags[i] = (bc_len[2 * i] < fb_len || bc_len[2 * i + 1] < rb_len) ? 1 : 0;
         /* primer snippets: left site is plus (read as is), right site is minus (rc) */
         char *left_dst = (lp == 0) ? fpr + 32 * i : rpr + 32 * i;
         char *right_dst = (rp == 1) ? rpr + 32 * i : fpr + 32 * i;

@@ -54,7 +54,8 @@ class ah_pair_spec(C.Structure):
 class ah_tm_params(C.Structure):
     _fields_ = [("na_mM", C.c_double), ("k_mM", C.c_double), ("tris_mM", C.c_double), ("mg_mM", C.c_double),
                 ("dntps_mM", C.c_double), ("dnac1_nM", C.c_double), ("dnac2_nM", C.c_double),
-                ("threshold_C", C.c_double), ("saltcorr", I32), ("filter", I32), ("d_pair_threshold", VP)]
+                ("threshold_C", C.c_double), ("saltcorr", I32), ("filter", I32), ("d_pair_threshold", VP),
+                ("nn_table", I32), ("reserved", I32)]
 
 
 class ah_extract_opts(C.Structure):
@@ -113,7 +114,7 @@ _sig("ah_route_hits", I32, VP, VP, U64, U32, VP, VP, VP, U32, U32, VP, U64, VP, 
 _sig("ah_pair_ws_size", I32, C.POINTER(ah_store), VP, U64, C.POINTER(U64))
 _sig("ah_pair_amplicons", I32, C.POINTER(ah_store), VP, VP, VP, U64, U32, VP, U64, VP, VP, U64, VP)
 _sig("ah_tm_nn", I32, C.POINTER(ah_store), VP, VP, VP, U64, C.POINTER(ah_tm_params), VP, VP, VP, VP)
-_sig("ah_tm_duplex", I32, VP, VP, VP, U32, U32, C.POINTER(ah_tm_params), VP, VP)
+_sig("ah_tm_duplex", I32, VP, VP, VP, VP, VP, U32, U32, C.POINTER(ah_tm_params), VP, VP)
 _sig("ah_extract_ws_size", I32, U64, C.POINTER(U64))
 _sig("ah_extract", I32, C.POINTER(ah_store), VP, VP, VP, U64, VP, C.POINTER(ah_extract_opts), VP, U64, VP, VP, VP,
      VP, VP, VP, VP, VP, U64, VP)
@@ -511,7 +512,8 @@ def jit_check(pairs, arch: str = "gfx950", variant=JIT_DEFAULT_VARIANT) -> int:
 
 def tm_params(tm) -> ah_tm_params:
     return ah_tm_params(tm.na_mM, tm.k_mM, tm.tris_mM, tm.mg_mM, tm.dntps_mM, tm.dnac1_nM, tm.dnac2_nM,
-                        tm.threshold_C, int(tm.saltcorr), int(bool(tm.filter)))
+                        tm.threshold_C, int(tm.saltcorr), int(bool(tm.filter)), None,
+                        int(getattr(tm, "nn_table", 3)), 0)
 
 
 def extract_opts(ex) -> ah_extract_opts:
@@ -598,23 +600,31 @@ def extract(store, ps, amps, n_amps, amp_cap, passed, opts: ah_extract_opts, seq
                           ws.numel() * ws.element_size(), _stream(stream)), "ah_extract")
 
 
-def tm_duplex(seqs: Sequence[str], cseqs: Sequence[str], tm) -> np.ndarray:
-    """Tm of explicit duplexes on the GPU (seq 5'->3', cseq its partner 3'->5')."""
+def tm_duplex(seqs: Sequence[str], cseqs: Sequence[str], tm, shifts: Optional[Sequence[int]] = None) -> np.ndarray:
+    """Tm of explicit duplexes on the GPU (seq 5'->3', cseq its partner 3'->5',
+    cseq[j] facing seq[j - shift]; lengths may differ)."""
     n = len(seqs)
-    stride = 32
+    stride = 64
     a = np.zeros((max(n, 1), stride), np.uint8)
     b = np.zeros((max(n, 1), stride), np.uint8)
     ln = np.zeros(max(n, 1), np.uint32)
+    lc = np.zeros(max(n, 1), np.uint32)
+    sh = np.zeros(max(n, 1), np.int32)
     for i, (s, c) in enumerate(zip(seqs, cseqs)):
         a[i, :len(s)] = np.frombuffer(s.encode(), np.uint8)
         b[i, :len(c)] = np.frombuffer(c.encode(), np.uint8)
-        ln[i] = len(s)
+        ln[i], lc[i] = len(s), len(c)
+        if shifts is not None:
+            sh[i] = int(shifts[i])
     dev = _dev()
     da, db = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
     dl = torch.from_numpy(ln.view(np.int32)).to(dev)
+    dc = torch.from_numpy(lc.view(np.int32)).to(dev)
+    ds = torch.from_numpy(sh).to(dev)
     out = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
     prm = tm_params(tm)
-    check(_lib.ah_tm_duplex(_p(da), _p(db), _p(dl), n, stride, C.byref(prm), _p(out), _stream()), "ah_tm_duplex")
+    check(_lib.ah_tm_duplex(_p(da), _p(db), _p(dl), _p(dc), _p(ds), n, stride, C.byref(prm), _p(out), _stream()),
+          "ah_tm_duplex")
     torch.cuda.synchronize()
     return out[:n].cpu().numpy()
 

@@ -203,7 +203,7 @@ __global__ void ah_extract_tail_kernel(const uint64_t *d_n, uint64_t cap, const 
     *n_bytes = *total;
 }
 
-__global__ void __launch_bounds__(256) ah_extract_write_kernel(ah_store st, const uint32_t *amps, const uint64_t *d_n,
+__global__ void __launch_bounds__(256) ah_extract_write_kernel(ah_store st, uint32_t *amps, const uint64_t *d_n,
                                                                uint64_t cap, const DPair *pairs, const uint8_t *pass,
                                                                ah_extract_opts o, const uint64_t *seq_off, char *out,
                                                                uint64_t seq_cap, char *fb, char *rb, uint8_t *bc_len,
@@ -244,6 +244,10 @@ __global__ void __launch_bounds__(256) ah_extract_write_kernel(ah_store st, cons
         if (lane == 0) {
             bc_len[2 * i] = (uint8_t)nf;
             bc_len[2 * i + 1] = (uint8_t)nr;
+            // flags bit 0: a barcode was clipped at a sequence end (the
+            // record's last byte; amp_geom above has read the others)
+            const bool clipped = on && (nf < o.fb_len || nr < o.rb_len);
+            amps[4 * i + 3] = (amps[4 * i + 3] & 0x00FFFFFFu) | ((uint32_t)clipped << 24);
         }
         uint64_t a0, a1;
         amp_span(g, o.trim, &a0, &a1);
@@ -315,7 +319,7 @@ extern "C" ah_status ah_extract_ws_size(uint64_t amp_cap, uint64_t *bytes) {
     return AH_OK;
 }
 
-extern "C" ah_status ah_extract(const ah_store *st, ah_primer_set ps, const ah_amp *d_amps, const uint64_t *d_n_amps,
+extern "C" ah_status ah_extract(const ah_store *st, ah_primer_set ps, ah_amp *d_amps, const uint64_t *d_n_amps,
                                 uint64_t amp_cap, const uint8_t *d_pass, const ah_extract_opts *o, char *d_seq,
                                 uint64_t seq_cap, uint64_t *d_seq_off, char *d_fb, char *d_rb, uint8_t *d_bc_len,
                                 char *d_fprimer, char *d_rprimer, uint64_t *d_n_bytes, void *d_ws, uint64_t ws_bytes,
@@ -345,7 +349,7 @@ extern "C" ah_status ah_extract(const ah_store *st, ah_primer_set ps, const ah_a
         const uint64_t resident = ah_resident_wgs(ah_extract_write_kernel, 256);
         if (wgs > resident) wgs = resident;
         hipLaunchKernelGGL(ah_extract_write_kernel, dim3((unsigned)wgs), dim3(256), 0, s, *st,
-                           (const uint32_t *)d_amps, d_n_amps, amp_cap, (const DPair *)ps->d_pairs, d_pass, *o,
+                           (uint32_t *)d_amps, d_n_amps, amp_cap, (const DPair *)ps->d_pairs, d_pass, *o,
                            (const uint64_t *)d_seq_off, d_seq, seq_cap, d_fb, d_rb, d_bc_len, d_fprimer, d_rprimer);
     }
     return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;

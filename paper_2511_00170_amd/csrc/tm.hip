@@ -19,12 +19,49 @@ struct NNRow {
     double dh, ds;
 };
 
-// Watson-Crick nearest neighbours, SantaLucia (1998) PNAS 95:1460, Table 2.
-static constexpr NNRow kWatsonCrick[] = {
+// Watson-Crick nearest neighbours of the Tm_NN model's DNA parameter sets,
+// numbered as it numbers them (3 is the default):
+// 1 Breslauer, Frank, Bloecker & Marky (1986) PNAS 83:3746, Table 2.
+static constexpr NNRow kWatsonCrick1[] = {
+    {'A', 'A', 'T', 'T', -9.1, -24.0}, {'A', 'T', 'T', 'A', -8.6, -23.9}, {'T', 'A', 'A', 'T', -6.0, -16.9},
+    {'C', 'A', 'G', 'T', -5.8, -12.9}, {'G', 'T', 'C', 'A', -6.5, -17.3}, {'C', 'T', 'G', 'A', -7.8, -20.8},
+    {'G', 'A', 'C', 'T', -5.6, -13.5}, {'C', 'G', 'G', 'C', -11.9, -27.8}, {'G', 'C', 'C', 'G', -11.1, -26.7},
+    {'G', 'G', 'C', 'C', -11.0, -26.6},
+};
+// 2 Sugimoto, Nakano, Yoneyama & Honda (1996) Nucleic Acids Res 24:4501, Table 1.
+static constexpr NNRow kWatsonCrick2[] = {
+    {'A', 'A', 'T', 'T', -8.0, -21.9}, {'A', 'T', 'T', 'A', -5.6, -15.2}, {'T', 'A', 'A', 'T', -6.6, -18.4},
+    {'C', 'A', 'G', 'T', -8.2, -21.0}, {'G', 'T', 'C', 'A', -9.4, -25.5}, {'C', 'T', 'G', 'A', -6.6, -16.4},
+    {'G', 'A', 'C', 'T', -8.8, -23.5}, {'C', 'G', 'G', 'C', -11.8, -29.0}, {'G', 'C', 'C', 'G', -10.5, -26.4},
+    {'G', 'G', 'C', 'C', -10.9, -28.4},
+};
+// 3 SantaLucia (1998) PNAS 95:1460, Table 2 (unified parameters).
+static constexpr NNRow kWatsonCrick3[] = {
     {'A', 'A', 'T', 'T', -7.9, -22.2}, {'A', 'T', 'T', 'A', -7.2, -20.4}, {'T', 'A', 'A', 'T', -7.2, -21.3},
     {'C', 'A', 'G', 'T', -8.5, -22.7}, {'G', 'T', 'C', 'A', -8.4, -22.4}, {'C', 'T', 'G', 'A', -7.8, -21.0},
     {'G', 'A', 'C', 'T', -8.2, -22.2}, {'C', 'G', 'G', 'C', -10.6, -27.2}, {'G', 'C', 'C', 'G', -9.8, -24.4},
     {'G', 'G', 'C', 'C', -8.0, -19.9},
+};
+// 4 SantaLucia & Hicks (2004) Annu Rev Biophys Biomol Struct 33:415, Table 1.
+static constexpr NNRow kWatsonCrick4[] = {
+    {'A', 'A', 'T', 'T', -7.6, -21.3}, {'A', 'T', 'T', 'A', -7.2, -20.4}, {'T', 'A', 'A', 'T', -7.2, -21.3},
+    {'C', 'A', 'G', 'T', -8.5, -22.7}, {'G', 'T', 'C', 'A', -8.4, -22.4}, {'C', 'T', 'G', 'A', -7.8, -21.0},
+    {'G', 'A', 'C', 'T', -8.2, -22.2}, {'C', 'G', 'G', 'C', -10.6, -27.2}, {'G', 'C', 'C', 'G', -9.8, -24.4},
+    {'G', 'G', 'C', 'C', -8.0, -19.9},
+};
+
+// Initiation terms of each set (dH, dS): every duplex; per duplex end with a
+// terminal A.T / G.C pair; a duplex holding at least one G.C pair / none.
+// (The model's 5'-terminal T.A penalty is zero in all four sets.)
+struct NNInit {
+    double init_dh, init_ds, at_dh, at_ds, gc_dh, gc_ds, one_gc_dh, one_gc_ds, all_at_dh, all_at_ds;
+};
+static constexpr NNInit kInit[5] = {
+    {0, 0, 2.3, 4.1, 0.1, -2.8, 0, 0, 0, 0},     // 0 = 3
+    {0, 0, 0, 0, 0, 0, 0, -16.8, 0, -20.1},      // Breslauer 1986: 5.0 / 6.0 kcal/mol at 25 C, entropic
+    {0.6, -9.0, 0, 0, 0, 0, 0, 0, 0, 0},         // Sugimoto 1996
+    {0, 0, 2.3, 4.1, 0.1, -2.8, 0, 0, 0, 0},     // SantaLucia 1998
+    {0.2, -5.7, 2.2, 6.9, 0, 0, 0, 0, 0, 0},     // SantaLucia & Hicks 2004
 };
 
 // Single internal mismatches (and tandem G.T), one mismatch type per row:
@@ -58,8 +95,9 @@ static constexpr NNRow kInternalMismatch[] = {
     {'T', 'T', 'A', 'T', 0.2, -1.5},
 };
 
-// Terminal mismatches, Bommarito, Peyret & SantaLucia (2000) NAR 28:1929.
-// The second pair of each stack is the mismatched duplex end.
+// Terminal mismatches: a Watson-Crick pair, then the mismatched duplex end.
+// The Tm_NN model's DNA table, from SantaLucia & Peyret (2001), patent
+// application WO 01/94611.
 static constexpr NNRow kTerminalMismatch[] = {
     {'A', 'A', 'T', 'A', -3.1, -7.8}, {'T', 'A', 'A', 'A', -2.5, -6.3}, {'C', 'A', 'G', 'A', -4.3, -10.7},
     {'G', 'A', 'C', 'A', -8.0, -22.5}, {'A', 'C', 'T', 'C', -0.1, 0.5}, {'T', 'C', 'A', 'C', -0.7, -1.3},
@@ -79,11 +117,27 @@ static constexpr NNRow kTerminalMismatch[] = {
     {'G', 'T', 'C', 'G', -5.9, -16.1}, {'T', 'G', 'A', 'T', -3.9, -10.5}, {'T', 'T', 'A', 'G', -3.6, -9.8},
 };
 
-// Initiation per duplex end (SantaLucia 1998): terminal A.T or G.C pair.
-#define AH_INIT_AT_DH 2.3
-#define AH_INIT_AT_DS 4.1
-#define AH_INIT_GC_DH 0.1
-#define AH_INIT_GC_DS (-2.8)
+// Dangling ends, Bommarito, Peyret & SantaLucia (2000) NAR 28:1929: one
+// unpaired base beside a terminal Watson-Crick pair x.w.  Row {d, x, w}: the
+// dangling base d and the pair.  kDangleTop5: a 5'-dangling base of the
+// strand written on top (5'-dx-3' over 3'-.w-5'); kDangleBottom3: a
+// 3'-dangling base of the bottom strand (5'-.x-3' over 3'-dw-5').
+struct DERow {
+    char d, x, w;
+    double dh, ds;
+};
+static constexpr DERow kDangleTop5[] = {
+    {'A', 'A', 'T', 0.2, 2.3}, {'A', 'C', 'G', -6.3, -17.1}, {'A', 'G', 'C', -3.7, -10.0}, {'A', 'T', 'A', -2.9, -7.6},
+    {'C', 'A', 'T', 0.6, 3.3}, {'C', 'C', 'G', -4.4, -12.6}, {'C', 'G', 'C', -4.0, -11.9}, {'C', 'T', 'A', -4.1, -13.0},
+    {'G', 'A', 'T', -1.1, -1.6}, {'G', 'C', 'G', -5.1, -14.0}, {'G', 'G', 'C', -3.9, -10.9}, {'G', 'T', 'A', -4.2, -15.0},
+    {'T', 'A', 'T', -6.9, -20.0}, {'T', 'C', 'G', -4.0, -10.9}, {'T', 'G', 'C', -4.9, -13.8}, {'T', 'T', 'A', -0.2, -0.5},
+};
+static constexpr DERow kDangleBottom3[] = {
+    {'A', 'A', 'T', -0.7, -0.8}, {'A', 'C', 'G', -2.1, -3.9}, {'A', 'G', 'C', -5.9, -16.5}, {'A', 'T', 'A', -0.5, -1.1},
+    {'C', 'A', 'T', 4.4, 14.9}, {'C', 'C', 'G', -0.2, -0.1}, {'C', 'G', 'C', -2.6, -7.4}, {'C', 'T', 'A', 4.7, 14.2},
+    {'G', 'A', 'T', -1.6, -3.6}, {'G', 'C', 'G', -3.9, -11.2}, {'G', 'G', 'C', -3.2, -10.4}, {'G', 'T', 'A', -4.1, -13.1},
+    {'T', 'A', 'T', 2.9, 10.4}, {'T', 'C', 'G', -4.4, -13.1}, {'T', 'G', 'C', -5.2, -15.0}, {'T', 'T', 'A', -3.8, -12.6},
+};
 
 struct NNTable {
     double dh[256];
@@ -108,11 +162,12 @@ constexpr void put_rows(NNTable &t, const NNRow (&rows)[N], bool reversed) {
     }
 }
 
-constexpr NNTable make_stack_table() {
+template <size_t N>
+constexpr NNTable make_stack_table(const NNRow (&wc)[N]) {
     NNTable t{};
-    put_rows(t, kWatsonCrick, false);
+    put_rows(t, wc, false);
     put_rows(t, kInternalMismatch, false);
-    put_rows(t, kWatsonCrick, true);
+    put_rows(t, wc, true);
     put_rows(t, kInternalMismatch, true);
     return t;
 }
@@ -123,8 +178,35 @@ constexpr NNTable make_terminal_table() {
     return t;
 }
 
-__constant__ NNTable g_stack = make_stack_table();
+// Dangling-end index: kind (0 = 5'-dangling base of the top strand, 1 =
+// 3'-dangling base of the bottom strand), dangling base, pair top base, pair
+// bottom base.
+constexpr int de_index(int kind, int d, int x, int w) { return (kind << 6) | (d << 4) | (x << 2) | w; }
+
+template <size_t N>
+constexpr void put_dangles(NNTable &t, const DERow (&rows)[N], int kind) {
+    for (size_t r = 0; r < N; r++) {
+        const int i = de_index(kind, base_of(rows[r].d), base_of(rows[r].x), base_of(rows[r].w));
+        t.dh[i] = rows[r].dh;
+        t.ds[i] = rows[r].ds;
+        t.ok[i >> 5] |= 1u << (i & 31);
+    }
+}
+
+constexpr NNTable make_dangle_table() {
+    NNTable t{};
+    put_dangles(t, kDangleTop5, 0);
+    put_dangles(t, kDangleBottom3, 1);
+    return t;
+}
+
+// Stack tables (Watson-Crick set + internal mismatches) by set number (0 = 3).
+__constant__ NNTable g_stack[5] = {make_stack_table(kWatsonCrick3), make_stack_table(kWatsonCrick1),
+                                   make_stack_table(kWatsonCrick2), make_stack_table(kWatsonCrick3),
+                                   make_stack_table(kWatsonCrick4)};
 __constant__ NNTable g_term = make_terminal_table();
+__constant__ NNTable g_dangle = make_dangle_table();
+__constant__ NNInit g_init[5] = {kInit[0], kInit[1], kInit[2], kInit[3], kInit[4]};
 
 // Salt terms (the seven corrections of the Tm_NN model, each from its
 // paper): 1-4 add a constant to Tm; 5 adds 0.368 (N-1) ln(mon) to dS;
@@ -132,14 +214,23 @@ __constant__ NNTable g_term = make_terminal_table();
 // G+C fraction and length of the primer strand to 1/Tm.
 struct TmConst {
     int saltcorr;
+    int mg_model;     // method 7: 1 = Mg2+ formula, 0 = monovalent formula of method 6
+    int table;        // Watson-Crick set, 1..4
+    int filter;
     double ln_mon;    // ln of the monovalent-equivalent concentration (M; methods 5, 6, 7-monovalent)
     double dtm;       // methods 1-4: added to Tm
-    int mg_model;     // method 7: 1 = Mg2+ formula, 0 = monovalent formula of method 6
-    double a, b, c, d, e, f, g, ln_mg;  // method 7 Mg2+ formula
+    // method 7 Mg2+ formula 1e-5 [m7a + fgc m7b + m7d / (2 (N - 1))] with
+    // m7a = a + b ln Mg, m7b = c + d ln Mg, m7d = e + f ln Mg + g ln^2 Mg
+    // (each folded on the host in the operation order of the full formula)
+    double m7a, m7b, m7d;
     double rlnc;      // R ln C, C = C_high - C_low / 2 (M)
     double threshold;
-    int filter;
 };
+
+// Watson-Crick set of the parameters: 0 selects the default 3; -1 if invalid.
+__host__ __device__ inline int tm_table(const ah_tm_params &p) {
+    return p.nn_table == 0 ? 3 : (p.nn_table >= 1 && p.nn_table <= 4 ? p.nn_table : -1);
+}
 
 // Everything here also runs on the host (ah_tm_nn checks the conditions).
 __host__ __device__ inline int tm_salt_setup(const ah_tm_params &p, TmConst *k) {
@@ -150,7 +241,7 @@ __host__ __device__ inline int tm_salt_setup(const ah_tm_params &p, TmConst *k) 
     k->ln_mon = 0.0;
     k->dtm = 0.0;
     k->mg_model = 0;
-    k->a = k->b = k->c = k->d = k->e = k->f = k->g = k->ln_mg = 0.0;
+    k->m7a = k->m7b = k->m7d = 0.0;
     if (p.saltcorr == 0) return 0;
     if (p.saltcorr >= 1 && p.saltcorr <= 6) {
         if (!(mon > 0.0)) return 1;
@@ -186,14 +277,10 @@ __host__ __device__ inline int tm_salt_setup(const ah_tm_params &p, TmConst *k) 
     }
     if (!(mg > 0.0)) return 1;
     k->mg_model = 1;
-    k->a = a;
-    k->b = -0.911;
-    k->c = 6.26;
-    k->d = d;
-    k->e = -48.2;
-    k->f = 52.5;
-    k->g = g;
-    k->ln_mg = log(mg);
+    const double b = -0.911, c = 6.26, e = -48.2, f = 52.5, lg = log(mg);
+    k->m7a = a + b * lg;
+    k->m7b = c + d * lg;
+    k->m7d = e + f * lg + g * lg * lg;
     return 0;
 }
 
@@ -209,17 +296,25 @@ __host__ __device__ inline TmConst tm_const(const ah_tm_params &p) {
     k.rlnc = 1.987 * log(C);
     k.threshold = p.threshold_C;
     k.filter = p.filter;
+    k.table = tm_table(p) < 0 ? 3 : tm_table(p);
     return k;
+}
+
+// The parameter checks of both Tm entry points (host, before any launch).
+static bool tm_params_ok(const ah_tm_params &p) {
+    TmConst k;
+    return tm_table(p) > 0 && tm_salt_setup(p, &k) == 0;  // a zero concentration under a logarithm fails
 }
 
 __device__ __forceinline__ bool tab_ok(const uint32_t *ok, int i) { return (ok[i >> 5] >> (i & 31)) & 1u; }
 
-// The two tables as the constant-memory records (values and validity bits).
+// The tables as the constant-memory records (values and validity bits).
 struct ConstTables {
+    int set;  // Watson-Crick set
     __device__ bool stack(int i, double &dh, double &ds) const {
-        dh = g_stack.dh[i];
-        ds = g_stack.ds[i];
-        return tab_ok(g_stack.ok, i);
+        dh = g_stack[set].dh[i];
+        ds = g_stack[set].ds[i];
+        return tab_ok(g_stack[set].ok, i);
     }
     __device__ bool term(int i, double &dh, double &ds) const {
         dh = g_term.dh[i];
@@ -228,8 +323,9 @@ struct ConstTables {
     }
 };
 
-// The two tables staged in LDS as (dH, dS) pairs, NaN where not tabulated:
-// one 16-byte read per step instead of two values and a validity word.
+// The stack and terminal-mismatch tables staged in LDS as (dH, dS) pairs,
+// NaN where not tabulated: one 16-byte read per step instead of two values
+// and a validity word.
 struct LdsTables {
     const double2 *st, *tt;
     __device__ bool stack(int i, double &dh, double &ds) const {
@@ -246,27 +342,41 @@ struct LdsTables {
     }
 };
 
-__device__ void stage_tables(double2 *st, double2 *tt) {
+__device__ void stage_tables(double2 *st, double2 *tt, int set) {
+    const NNTable &S = g_stack[set];
     for (int i = threadIdx.x; i < 256; i += blockDim.x) {
-        st[i] = tab_ok(g_stack.ok, i) ? make_double2(g_stack.dh[i], g_stack.ds[i]) : make_double2(NAN, NAN);
+        st[i] = tab_ok(S.ok, i) ? make_double2(S.dh[i], S.ds[i]) : make_double2(NAN, NAN);
         tt[i] = tab_ok(g_term.ok, i) ? make_double2(g_term.dh[i], g_term.ds[i]) : make_double2(NAN, NAN);
     }
     __syncthreads();
 }
 
-// Duplex Tm of variant V with partner C (2-bit codes, base j at bits 2j; C is
-// the partner strand read 3'->5' against V).  Steps: a mismatched end pair
-// is charged with the terminal-mismatch stack and leaves the helix; one
-// initiation term per end by the end bases of V; the remaining stacks from
-// 5' to 3'; the salt term; Tm = 1000 dH / (dS + R ln C) - 273.15.  The order
-// of the floating-point additions is fixed.  Returns false if a stack is not
+// What the initiation and salt terms read of the primer strand as given
+// (reading R-init: its end bases and G+C content, also when an end pair left
+// the helix): 2-bit codes of its first and last base, its length and G+C count.
+struct PrimerEnds {
+    int e0, e1, L, gc;
+};
+
+__device__ __forceinline__ int gc_count(uint64_t V, int L) {
+    // codes 1 (C) and 2 (G) have differing bits
+    const uint64_t lmask = L >= 32 ? ~0ull : ((1ull << (2 * L)) - 1);
+    return __popcll((V ^ (V >> 1)) & 0x5555555555555555ull & lmask);
+}
+
+// Steps after the dangling ends, on the helix of n facing pairs V / C (2-bit
+// codes, pair j at bits 2j; C is the partner strand read 3'->5' against V),
+// accumulating into dh / ds: a mismatched end pair is charged with the
+// terminal-mismatch stack and leaves the helix (left end, then right);
+// initiation from the primer strand P; the remaining stacks from 5' to 3';
+// the salt term; Tm = 1000 dH / (dS + R ln C) - 273.15.  The order of the
+// floating-point additions is fixed.  Returns false if a stack is not
 // tabulated.
 template <class Tab>
-__device__ bool duplex_tm(uint64_t V, uint64_t C, int L, const Tab &tab, const TmConst &k, double *out) {
-    if (L < 2) return false;
+__device__ bool helix_tm(uint64_t V, uint64_t C, int n, double dh, double ds, const PrimerEnds &P, const Tab &tab,
+                         const TmConst &k, double *out) {
     auto bb = [](uint64_t X, int j) { return (int)((X >> (2 * j)) & 3u); };
-    double dh = 0.0, ds = 0.0;
-    int lo = 0, hi = L - 1;
+    int lo = 0, hi = n - 1;
     {
         // left end read from the partner strand, so the end pair comes second
         const int i = nn_index(bb(C, 1), bb(C, 0), bb(V, 1), bb(V, 0));
@@ -287,11 +397,15 @@ __device__ bool duplex_tm(uint64_t V, uint64_t C, int L, const Tab &tab, const T
         }
     }
     {
-        const int e0 = bb(V, 0), e1 = bb(V, L - 1);
-        if (e0 == 0 || e0 == 3) { dh += AH_INIT_AT_DH; ds += AH_INIT_AT_DS; }
-        else { dh += AH_INIT_GC_DH; ds += AH_INIT_GC_DS; }
-        if (e1 == 0 || e1 == 3) { dh += AH_INIT_AT_DH; ds += AH_INIT_AT_DS; }
-        else { dh += AH_INIT_GC_DH; ds += AH_INIT_GC_DS; }
+        const NNInit &I = g_init[k.table];
+        dh += I.init_dh;
+        ds += I.init_ds;
+        if (P.gc) { dh += I.one_gc_dh; ds += I.one_gc_ds; }
+        else { dh += I.all_at_dh; ds += I.all_at_ds; }
+        if (P.e0 == 0 || P.e0 == 3) { dh += I.at_dh; ds += I.at_ds; }
+        else { dh += I.gc_dh; ds += I.gc_ds; }
+        if (P.e1 == 0 || P.e1 == 3) { dh += I.at_dh; ds += I.at_ds; }
+        else { dh += I.gc_dh; ds += I.gc_ds; }
     }
     for (int j = lo; j < hi; j++) {
         const int i = nn_index(bb(V, j), bb(V, j + 1), bb(C, j), bb(C, j + 1));
@@ -300,23 +414,31 @@ __device__ bool duplex_tm(uint64_t V, uint64_t C, int L, const Tab &tab, const T
         dh += a;
         ds += b;
     }
+    const int L = P.L;
     if (k.saltcorr == 5) ds += 0.368 * (double)(L - 1) * k.ln_mon;
     double tm = (1000.0 * dh) / (ds + k.rlnc) - 273.15;
     if (k.saltcorr >= 1 && k.saltcorr <= 4) tm += k.dtm;
     if (k.saltcorr >= 6) {
-        // G+C fraction of V: codes 1 (C) and 2 (G) have differing bits
-        const uint64_t lmask = L >= 32 ? ~0ull : ((1ull << (2 * L)) - 1);
-        const double fgc = (double)__popcll((V ^ (V >> 1)) & 0x5555555555555555ull & lmask) / (double)L;
+        const double fgc = (double)P.gc / (double)L;
         double corr;
         if (k.mg_model)
-            corr = (k.a + k.b * k.ln_mg + fgc * (k.c + k.d * k.ln_mg) +
-                    (k.e + k.f * k.ln_mg + k.g * k.ln_mg * k.ln_mg) / (2.0 * (L - 1))) * 1e-5;
+            corr = (k.m7a + fgc * k.m7b + k.m7d / (2.0 * (L - 1))) * 1e-5;
         else
             corr = (4.29 * fgc - 3.95) * 1e-5 * k.ln_mon + 9.40e-6 * k.ln_mon * k.ln_mon;
         tm = 1.0 / (1.0 / (tm + 273.15) + corr) - 273.15;
     }
     *out = tm;
     return true;
+}
+
+// Duplex Tm of primer variant V (L bases) with its partner C of equal length
+// and no dangling ends: the helix is the whole duplex.
+template <class Tab>
+__device__ __forceinline__ bool duplex_tm(uint64_t V, uint64_t C, int L, const Tab &tab, const TmConst &k,
+                                          double *out) {
+    if (L < 2) return false;
+    const PrimerEnds P{(int)(V & 3u), (int)((V >> (2 * (L - 1))) & 3u), L, gc_count(V, L)};
+    return helix_tm(V, C, L, 0.0, 0.0, P, tab, k, out);
 }
 
 // ---------------------------------------------------------------- sites
@@ -381,7 +503,7 @@ __global__ void __launch_bounds__(256, 6) ah_tm_site_kernel(ah_store st, const D
                                                          uint32_t lps, double *tm_site, const double *pair_thr,
                                                          double *tm, uint8_t *pass) {
     __shared__ double2 sst[256], stt[256];
-    stage_tables(sst, stt);
+    stage_tables(sst, stt, k.table);
     const LdsTables nn{sst, stt};
     const uint64_t n = *d_n < cap ? *d_n : cap;
     const uint32_t lane = threadIdx.x & 63;
@@ -452,10 +574,7 @@ extern "C" ah_status ah_tm_nn(const ah_store *st, ah_primer_set ps, const ah_amp
                               uint64_t amp_cap, const ah_tm_params *p, double *d_tm, double *d_tm_site,
                               uint8_t *d_pass, void *stream) {
     if (!st || !ps || !p || !d_n_amps || (amp_cap && (!d_amps || !d_tm || !d_tm_site || !d_pass))) return AH_E_ARG;
-    {
-        TmConst k;
-        if (tm_salt_setup(*p, &k)) return AH_E_ARG;  // unknown method or a zero concentration under a logarithm
-    }
+    if (!tm_params_ok(*p)) return AH_E_ARG;  // unknown set or method, or a zero concentration under a logarithm
     uint32_t maxD = 1;
     for (uint32_t q = 0; q < ps->n_pairs; q++) {
         if (!ps->h_pairs[q].prim[0].D || !ps->h_pairs[q].prim[1].D) return AH_E_LIMIT;
@@ -491,39 +610,82 @@ __device__ __forceinline__ int letter_code(char c) {
     }
 }
 
-__global__ void ah_tm_duplex_kernel(const char *seq, const char *cseq, const uint32_t *len, uint32_t n,
-                                    uint32_t stride, TmConst k, double *out) {
+// Tm of one explicit duplex: primer s[0..L) 5'->3', partner c[0..Lc)
+// written 3'->5', c[i] facing s[i - shift].  In a common column frame the
+// primer occupies [st, st + L) and the partner [sb, sb + Lc); the positions
+// facing each other are [f0, f1).  An end where one strand runs past the
+// other keeps one unpaired base next to the helix (a dangling end; further
+// overhang is dropped), charged with its dangling-end term -- left end
+// first, then the right end read from the partner strand.  The helix is
+// columns [f0, f1).  NaN if a letter is not ACGT or a stack or end is not
+// tabulated; the caller has checked the lengths and that f1 - f0 >= 2.
+__device__ double explicit_duplex_tm(const char *s, int L, const char *c, int Lc, int shift, const TmConst &k) {
+    const int st = shift > 0 ? shift : 0, sb = shift < 0 ? -shift : 0;
+    const int f0 = st > sb ? st : sb, f1 = st + L < sb + Lc ? st + L : sb + Lc;
+    uint64_t S = 0, C = 0;  // the primer, and the partner positions facing the helix [f0, f1)
+    for (int j = 0; j < L; j++) {
+        const int b = letter_code(s[j]);
+        if (b < 0) return NAN;
+        S |= (uint64_t)b << (2 * j);
+    }
+    for (int j = 0; j < Lc; j++) {
+        const int b = letter_code(c[j]);
+        if (b < 0) return NAN;
+        const int col = j + sb;
+        if (col >= f0 && col < f1) C |= (uint64_t)b << (2 * (col - f0));
+    }
+    const int n = f1 - f0;
+    const uint64_t V = S >> (2 * (f0 - st));  // primer bases of the helix columns
+    double dh = 0.0, ds = 0.0;
+    if (f0 > 0) {
+        // left end: the strand that starts first keeps its base at column f0 - 1
+        const int top0 = (int)(V & 3u), bot0 = (int)(C & 3u);
+        const int i = st > sb ? de_index(1, letter_code(c[f0 - 1 - sb]), top0, bot0)   // partner's 3' base
+                              : de_index(0, letter_code(s[f0 - 1 - st]), top0, bot0);  // primer's 5' base
+        if (!tab_ok(g_dangle.ok, i)) return NAN;
+        dh += g_dangle.dh[i];
+        ds += g_dangle.ds[i];
+    }
+    if (st + L != sb + Lc) {
+        // right end, read from the partner strand: the primer's 3' base, or
+        // the partner's 5' base, at column f1
+        const int topn = (int)((V >> (2 * (n - 1))) & 3u), botn = (int)((C >> (2 * (n - 1))) & 3u);
+        const int i = st + L > sb + Lc ? de_index(1, letter_code(s[f1 - st]), botn, topn)
+                                       : de_index(0, letter_code(c[f1 - sb]), botn, topn);
+        if (!tab_ok(g_dangle.ok, i)) return NAN;
+        dh += g_dangle.dh[i];
+        ds += g_dangle.ds[i];
+    }
+    const PrimerEnds P{(int)(S & 3u), (int)((S >> (2 * (L - 1))) & 3u), L, gc_count(S, L)};
+    double t;
+    if (!helix_tm(V, C, n, dh, ds, P, ConstTables{k.table}, k, &t)) return NAN;
+    return t;
+}
+
+__global__ void ah_tm_duplex_kernel(const char *seq, const char *cseq, const uint32_t *len, const uint32_t *clen,
+                                    const int32_t *shift, uint32_t n, uint32_t stride, TmConst k, double *out) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int L = (int)len[i];
-        uint64_t V = 0, C = 0;
-        bool okc = L >= 2 && L <= 32 && (uint32_t)L <= stride;
-        for (int j = 0; okc && j < L; j++) {
-            const int a = letter_code(seq[(uint64_t)i * stride + j]);
-            const int b = letter_code(cseq[(uint64_t)i * stride + j]);
-            if (a < 0 || b < 0) okc = false;
-            else {
-                V |= (uint64_t)a << (2 * j);
-                C |= (uint64_t)b << (2 * j);
-            }
-        }
-        double t = NAN;
-        if (okc && !duplex_tm(V, C, L, ConstTables{}, k, &t))
-            t = NAN;
-        out[i] = t;
+        const int Lc = clen ? (int)clen[i] : L;
+        const int sh = shift ? shift[i] : 0;
+        const int st = sh > 0 ? sh : 0, sb = sh < 0 ? -sh : 0;
+        // facing positions: columns where both strands have a base
+        const int f0 = st > sb ? st : sb, f1 = (st + L < sb + Lc ? st + L : sb + Lc);
+        const bool ok = L >= 2 && L <= 32 && Lc >= 1 && Lc <= 64 && (uint32_t)L <= stride &&
+                        (uint32_t)Lc <= stride && sh >= -64 && sh <= 64 && f1 - f0 >= 2;
+        out[i] = ok ? explicit_duplex_tm(seq + (uint64_t)i * stride, L, cseq + (uint64_t)i * stride, Lc, sh, k) : NAN;
     }
 }
 
-extern "C" ah_status ah_tm_duplex(const char *d_seq, const char *d_cseq, const uint32_t *d_len, uint32_t n,
-                                  uint32_t stride, const ah_tm_params *p, double *d_tm, void *stream) {
+extern "C" ah_status ah_tm_duplex(const char *d_seq, const char *d_cseq, const uint32_t *d_len,
+                                  const uint32_t *d_clen, const int32_t *d_shift, uint32_t n, uint32_t stride,
+                                  const ah_tm_params *p, double *d_tm, void *stream) {
     if (!p || (n && (!d_seq || !d_cseq || !d_len || !d_tm))) return AH_E_ARG;
-    {
-        TmConst k;
-        if (tm_salt_setup(*p, &k)) return AH_E_ARG;  // unknown method or a zero concentration under a logarithm
-    }
+    if (!tm_params_ok(*p)) return AH_E_ARG;  // unknown set or method, or a zero concentration under a logarithm
     if (!n) return AH_OK;
     unsigned blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(ah_tm_duplex_kernel, dim3(blocks), dim3(256), 0, ah_stream(stream), d_seq, d_cseq, d_len, n,
-                       stride, tm_const(*p), d_tm);
+    hipLaunchKernelGGL(ah_tm_duplex_kernel, dim3(blocks), dim3(256), 0, ah_stream(stream), d_seq, d_cseq, d_len,
+                       d_clen, d_shift, n, stride, tm_const(*p), d_tm);
     return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
 }

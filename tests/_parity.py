@@ -59,6 +59,7 @@ def compare_tm(g_tm, g_site, g_pass, o):
 
 def compare_extract(r, e):
     assert r["seq"] == e.seq
+    assert (r["amps"]["flags"] == e.flags).all()
     assert (r["seq_off"] == e.seq_off).all()
     assert (r["bc_len"] == e.bc_len).all()
     if r["fb"].shape[1]:

@@ -132,7 +132,7 @@ def _random_run(rng, n, n_seqs, fb_len, rb_len):
     passed = (rng.random(n) < 0.7).astype(np.uint8)
     res = {"amps": amps, "tm": tm, "pass": passed, "seq": seq, "seq_off": off, "fb": fb, "rb": rb, "bc_len": bc,
            "fprimer": fp, "rprimer": rp}
-    ext = oracle.Extracted(seq, off, fb, rb, bc, fp, rp)
+    ext = oracle.Extracted(seq, off, fb, rb, bc, fp, rp, np.zeros(n, np.uint8))
     return res, ext
 
 

@@ -496,6 +496,9 @@ def test_extract_barcodes_clipped_at_ends():
     ex = oracle.extract(buf, off, pairs, amps, ExtractSpec(fb_len=16, rb_len=16))
     assert list(ex.bc_len[0]) == [3, 2]
     assert bytes(ex.fb[0][:3]) == b"GGA" and bytes(ex.rb[0][:2]) == b"TT"
+    assert list(ex.flags) == [1]                     # clipped barcodes are flagged
+    ex = oracle.extract(buf, off, pairs, amps, ExtractSpec(fb_len=3, rb_len=2))
+    assert list(ex.bc_len[0]) == [3, 2] and list(ex.flags) == [0]
 
 
 def test_extract_planted_barcodes_dense_config():
