@@ -76,7 +76,7 @@ def lib():
         L.or_extract.restype = C.c_int64
         L.or_extract.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
                                  C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
-                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -105,7 +105,14 @@ def _primer_array(pairs) -> tuple:
 
 
 def n_threads_default() -> int:
-    return os.cpu_count() or 1
+    """The CPUs this process may run on, capped by the OpenMP thread setting
+    (the host's share of a shared machine)."""
+    n = len(os.sched_getaffinity(0))
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS") or n))
+    except ValueError:
+        pass
+    return max(1, n)
 
 
 # ---------------------------------------------------------------- primers
@@ -253,6 +260,7 @@ class Extracted:
     bc_len: np.ndarray
     fprimer: np.ndarray
     rprimer: np.ndarray
+    flags: np.ndarray       # 1 where a barcode was clipped at a sequence end
 
     def amplicon(self, i: int) -> bytes:
         return self.seq[int(self.seq_off[i]):int(self.seq_off[i + 1])]
@@ -270,17 +278,18 @@ def extract(ascii, off, pairs, amps: np.ndarray, ex, passed: Optional[np.ndarray
     fp = np.zeros((n, 32), np.uint8)
     rp = np.zeros((n, 32), np.uint8)
     so = np.zeros(n + 1, np.uint64)
+    fl = np.zeros(max(n, 1), np.uint8)
     pas = None if passed is None else np.ascontiguousarray(passed, np.uint8)
     cap = 1 << 20
     while True:
         buf = np.zeros(cap, np.uint8)
         tot = lib().or_extract(_ptr(ascii), _ptr(off), C.cast(arr, C.c_void_p), _ptr(amps), n,
                                None if pas is None else _ptr(pas), int(ex.trim), ex.fb_len, ex.rb_len,
-                               _ptr(buf), cap, _ptr(so), _ptr(fb), _ptr(rb), _ptr(bc), _ptr(fp), _ptr(rp))
+                               _ptr(buf), cap, _ptr(so), _ptr(fb), _ptr(rb), _ptr(bc), _ptr(fp), _ptr(rp), _ptr(fl))
         if tot <= cap:
             break
         cap = int(tot)
-    return Extracted(buf[:tot].tobytes(), so, fb[:, :ex.fb_len], rb[:, :ex.rb_len], bc, fp, rp)
+    return Extracted(buf[:tot].tobytes(), so, fb[:, :ex.fb_len], rb[:, :ex.rb_len], bc, fp, rp, fl[:n])
 
 
 # ---------------------------------------------------------------- pipeline

@@ -2,9 +2,11 @@
 benchmark times: the 9 Gb genome store with the specialised scan, the 9 Gb
 64-pair batch through the autotuned graph, the 2 Gb dense store with trimming
 and barcodes, and the 20 Gb serving store.  Sites never cross sequences, so
-the oracle computes any sequence alone: sampled sequences (the first, the
-last and random ones) are compared element by element; the whole output is
-checked against properties that hold at any size."""
+the oracle computes any group of whole sequences alone: the genome and dense
+outputs are compared with the oracle element by element in full (the oracle
+runs over groups of about 1 Gb), the 64-pair batch on random sequences
+holding at least 5% of its bases, and serving on 10 requests of mixed sizes;
+the whole output is also checked against properties that hold at any size."""
 import numpy as np
 import pytest
 
@@ -70,6 +72,34 @@ def _compare_sample(ah, wl, r, idx, pairs, ex, tm=None):
     return o
 
 
+def _compare_all(ah, wl, r, pairs, ex, group_bases=1 << 30):
+    """Every sequence against the oracle, a group of whole sequences at a time."""
+    n_amps = 0
+    for first, buf, off in wl.chunks(group_bases):
+        idx = np.arange(first, first + len(off) - 1, dtype=np.int64)
+        _say("oracle group", int(idx[0]), int(idx[-1]), int(off[-1]))
+        o = oracle.run(buf, off, pairs, wl.orient_mask, wl.tm, ex)
+        g = _restrict(ah, r, idx)
+        P.compare_hits(g["hits"], o.hits, o.mm)
+        P.compare_amps(g["amps"], o.amps)
+        P.compare_tm(g["tm"], g["tm_site"], g["pass"], o.tm)
+        if ex is not None:
+            P.compare_extract(g, o.ext)
+        n_amps += len(o.amps)
+        del buf, off, o, g
+    assert n_amps == len(r["amps"])
+    return n_amps
+
+
+def _sample_bases(wl, frac, seed):
+    """Random sequences holding at least frac of the bases, plus the first and the last."""
+    rng = np.random.default_rng(seed)
+    lens = wl.lengths.astype(np.int64)
+    order = rng.permutation(wl.n_seqs)
+    take = np.searchsorted(np.cumsum(lens[order]), frac * lens.sum()) + 1
+    return np.array(sorted(set(order[:take].tolist()) | {0, wl.n_seqs - 1}), np.int64)
+
+
 def _properties(ah, wl, r, pairs, ex):
     """What holds for every record at any size."""
     lens = wl.lengths.astype(np.int64)
@@ -106,20 +136,20 @@ def _trim_len(a, L):
     return up + dn
 
 
+@pytest.mark.timeout(900)
 def test_genome_full_size(ah):
     wl = synth.gen_config(2)
     _say("full genome", wl.total_bases)
     st = ah.Store.from_workload(wl)
     ex = synth.ExtractSpec(trim=wl.extract.trim, fb_len=wl.extract.fb_len, rb_len=wl.extract.rb_len)
     r = ah.Pipeline(st, ah.PrimerSet(wl.pairs, jit=True), wl.orient_mask, wl.tm, ex).run().results()
+    del st
     assert len(r["amps"]) > 10000
     _properties(ah, wl, r, wl.pairs, ex)
-    idx = _sample(wl, 10, 1)
-    _say("full genome sample", idx.tolist())
-    o = _compare_sample(ah, wl, r, idx, wl.pairs, ex)
-    assert len(o.amps) > 0
+    assert _compare_all(ah, wl, r, wl.pairs, ex) > 10000
 
 
+@pytest.mark.timeout(900)
 def test_batch_full_size_tuned_graph(ah):
     from paper_2511_00170_amd import batch
     wl = synth.gen_config(3)
@@ -131,34 +161,36 @@ def test_batch_full_size_tuned_graph(ah):
     br.run()
     br.replay()
     r = br.pipe.results()
+    del br, st
     _properties(ah, wl, r, wl.pairs, ex)
-    idx = _sample(wl, 4, 2)
-    _say("full batch sample", idx.tolist())
+    idx = _sample_bases(wl, 0.05, 2)
+    _say("full batch sample", len(idx), int(wl.lengths[idx].sum()))
+    assert wl.lengths[idx].sum() >= 0.05 * wl.total_bases
     o = _compare_sample(ah, wl, r, idx, wl.pairs, ex)
     assert len(o.hits) > 0
 
 
+@pytest.mark.timeout(600)
 def test_dense_full_size(ah):
     wl = synth.gen_config(4)
     _say("full dense", wl.total_bases)
     st = ah.Store.from_workload(wl)
     ex = synth.ExtractSpec(trim=wl.extract.trim, fb_len=wl.extract.fb_len, rb_len=wl.extract.rb_len)
     r = ah.Pipeline(st, ah.PrimerSet(wl.pairs, jit=True), wl.orient_mask, wl.tm, ex).run().results()
+    del st
     _properties(ah, wl, r, wl.pairs, ex)
-    idx = _sample(wl, 8, 3)
-    _say("full dense sample", idx.tolist())
-    o = _compare_sample(ah, wl, r, idx, wl.pairs, ex)
-    assert len(o.amps) > 0
+    assert _compare_all(ah, wl, r, wl.pairs, ex) > 5000
 
 
+@pytest.mark.timeout(900)
 def test_serve_full_store(ah):
     from paper_2511_00170_amd import serve
     wl = synth.gen_config(5)
     _say("full serve store", wl.total_bases)
     st = ah.Store.from_workload(wl)
     reqs = synth.gen_requests(wl, 12, qps=0, seed=31)
-    small = [r for r in synth.gen_requests(wl, 40, qps=0, seed=32, max_subset=60, min_subset=20)
-             if len(r.pairs) <= 2][:2]
+    # ten requests of mixed sizes (1-8 pairs, 20-200 sequences, k 0-3) for the oracle
+    small = synth.gen_requests(wl, 10, qps=0, seed=32, max_subset=200, min_subset=20)
     for i, r in enumerate(small):
         r.rid = 1000 + i
     ex = synth.ExtractSpec()

@@ -104,6 +104,28 @@ def test_scan_pair_tm_adversarial(ah, pi, kernel):
     assert len(o.hits) > 0
 
 
+@pytest.mark.parametrize("kernel", ["generic", "jit"])
+def test_all_n_primers(ah, kernel):
+    """Primers of N only, no clamp, k = 0: every window without an N is a hit of
+    all four patterns; each plus site pairs with the minus sites at its own
+    position (the next plus site stops the walk); every site's Tm is the
+    maximum over 4^6 variants (more than the per-primer variant table holds)."""
+    rng = np.random.default_rng(77)
+    seqs = [synth.random_ascii(rng, L).tobytes().decode() for L in (0, 5, 6, 7, 64, 65, 300)]
+    s = list(synth.random_ascii(rng, 400).tobytes().decode())
+    for j in (10, 11, 200, 399):
+        s[j] = "N"
+    seqs.append("".join(s))
+    buf, off = _concat(seqs)
+    pair = PairSpec("NNNNNN", "NNNNNN", k=0, clamp=0, min_len=1, max_len=50)
+    _say("all-N primers", kernel)
+    st = ah.Store.from_ascii(seqs)
+    r, o = P.full_parity(st, buf, off, [pair], 0xF, TmSpec(threshold_C=0.0),
+                         ExtractSpec(trim=True, fb_len=3, rb_len=3), jit=kernel == "jit")
+    windows = sum(1 for x in seqs for p in range(len(x) - 5) if "N" not in x[p:p + 6])
+    assert len(o.hits) == 4 * windows and len(o.amps) == 2 * windows
+
+
 def test_tiny_config_full_path(ah):
     wl = synth.gen_config(1)
     buf, off = wl.concat()
