@@ -43,8 +43,8 @@ struct GenericFilter {
     static constexpr int kW = AH_WMAX;
     static constexpr bool kHoistGuard = false;  // codes are read at run time
     static constexpr bool kSkipEmpty = true;
-    __device__ __forceinline__ void filter(uint32_t g, const AhBase &, const uint32_t (&Sh)[AH_WMAX][AH_NW],
-                                           const uint32_t (&Sl)[AH_WMAX][AH_NW], uint32_t (&C)[4 * AH_NW]) const {
+    __device__ __forceinline__ void filter(uint32_t g, const AhBase &, const uint32_t (&Sh)[AH_WMAX][AH_HW],
+                                           const uint32_t (&Sl)[AH_WMAX][AH_HW], uint32_t (&C)[4 * AH_HW]) const {
         uint32_t fc[4][2], W = 0;
 #pragma unroll
         for (int x = 0; x < 4; x++) {
@@ -71,19 +71,19 @@ struct GenericFilter {
             fc[x][1] = (uint32_t)(codes >> 32);
             W = wx > W ? wx : W;
 #pragma unroll
-            for (int w = 0; w < AH_NW; w++) C[AH_NW * x + w] = 0xFFFFFFFFu;
+            for (int w = 0; w < AH_HW; w++) C[AH_HW * x + w] = 0xFFFFFFFFu;
         }
 #pragma unroll
         for (int i = 0; i < AH_WMAX; i++) {
             if ((uint32_t)i >= W) break;
 #pragma unroll
-            for (int w = 0; w < AH_NW; w++) {
+            for (int w = 0; w < AH_HW; w++) {
                 const uint32_t h = Sh[i][w], l = Sl[i][w];
                 const uint32_t aa = ~(h | l), cc = ~h & l, gg = h & ~l, tt = h & l;
 #pragma unroll
                 for (int x = 0; x < 4; x++) {
                     const uint32_t m = ((i < 4 ? fc[x][0] >> (8 * i) : fc[x][1] >> (8 * (i - 4)))) & 0xFu;
-                    C[AH_NW * x + w] &= ah_pick(aa, cc, gg, tt, m);
+                    C[AH_HW * x + w] &= ah_pick(aa, cc, gg, tt, m);
                 }
             }
         }
@@ -279,7 +279,7 @@ static std::string set_test_chain(std::string acc, const std::vector<FiltPos> &p
 // pattern's filter positions become template constants of the set tests.
 static std::string jit_source(const ah_primer_set_ *ps, uint32_t bpl, uint32_t hcap) {
     std::string s;
-    const int nw = 2 * (int)bpl;  // words per lane and plane in the variant
+    const int nw = AH_HW;  // words per plane of the block the filter sees
     std::vector<FiltPlan> plans(ps->n_pats);
     bool any_groups = false;
     for (uint32_t X = 0; X < ps->n_pats; X++) {
@@ -296,8 +296,8 @@ static std::string jit_source(const ah_primer_set_ *ps, uint32_t bpl, uint32_t h
     s += std::string("  static constexpr bool kHoistGuard = ") + (ps->n_pairs > 1 ? "true" : "false") + ";\n";
     s += std::string("  static constexpr bool kSkipEmpty = ") + (ps->n_pairs > 1 ? "true" : "false") + ";\n";
     s += "  __device__ uint32_t groups(const ScanArgs &) const { return " + std::to_string(ps->n_pairs) + "u; }\n";
-    s += "  __device__ __forceinline__ void filter(uint32_t g, const AhBase &B, const uint32_t (&Sh)[AH_WMAX][AH_NW], "
-         "const uint32_t (&Sl)[AH_WMAX][AH_NW], uint32_t (&C)[4 * AH_NW]) const {\n";
+    s += "  __device__ __forceinline__ void filter(uint32_t g, const AhBase &B, const uint32_t (&Sh)[AH_WMAX][AH_HW], "
+         "const uint32_t (&Sl)[AH_WMAX][AH_HW], uint32_t (&C)[4 * AH_HW]) const {\n";
     s += "    switch (g) {\n";
     for (uint32_t g = 0; g < ps->n_pairs; g++) {
         s += "    case " + std::to_string(g) + "u: {\n";
@@ -325,12 +325,15 @@ static std::string jit_source(const ah_primer_set_ *ps, uint32_t bpl, uint32_t h
         }
         s += "      break; }\n";
     }
-    s += "    default: for (int w = 0; w < 4 * AH_NW; w++) C[w] = 0u;\n";
+    s += "    default: for (int w = 0; w < 4 * AH_HW; w++) C[w] = 0u;\n";
     s += "    }\n  }\n};\n";
     const uint32_t n_lds = ps->n_pats < AH_LDS_PATS ? ps->n_pats : AH_LDS_PATS;
     s += "#define AH_JIT_LDS_PATS " + std::to_string(n_lds) + "u\n";
     s += std::string("#define AH_JIT_LDS_ONLY ") + (ps->n_pats <= AH_LDS_PATS ? "true" : "false") + "\n";
-    s += "extern \"C\" __global__ void __launch_bounds__(256) ah_scan_jit(ScanArgs a) {\n"
+    // two-block tiles for a few pairs: bound the registers to six waves per
+    // SIMD (80 VGPRs, no spills), the count the LDS allows
+    const std::string bounds = (bpl == 2 && ps->n_pairs <= 4) ? "__launch_bounds__(256, 6)" : "__launch_bounds__(256)";
+    s += "extern \"C\" __global__ void " + bounds + " ah_scan_jit(ScanArgs a) {\n"
          "  __shared__ DPat sPat[AH_JIT_LDS_PATS];\n"
          "  __shared__ TileCtx sCtx[4][AH_NCTX];\n"
          "  __shared__ uint32_t sQ[4][AH_QCAP][AH_QW];\n"

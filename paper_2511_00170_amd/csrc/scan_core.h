@@ -7,7 +7,10 @@
 // Work layout.  A tile is 64 x AH_BPL blocks of one sequence (64 bases each);
 // a wave owns a contiguous run of tiles and walks it in order, prefetching
 // the next tile's blocks while it works on the current one (lane i owns
-// blocks AH_BPL*i .. AH_BPL*i + AH_BPL-1, read with 128-bit loads).  For its
+// blocks AH_BPL*i .. AH_BPL*i + AH_BPL-1, read with 128-bit loads).  The
+// lane's blocks are filtered one after the other (a "half" of a two-block
+// tile), so a larger tile shares the per-tile work -- its loads, context and
+// sequence walk -- without holding more planes in registers.  For its
 // clamp sites q a lane builds bit-vectors "base q+i is in IUPAC set m" from
 // funnel shifts of the two bit planes and ANDs them over the filter
 // positions of each oriented pattern -- a window that fails this pre-filter
@@ -63,18 +66,19 @@ __device__ __forceinline__ uint32_t ah_and_set(uint32_t acc, uint32_t h, uint32_
     return acc & ((h & high) | (~h & low));
 }
 
-// The lane's positions of both planes with their neighbours: word 0 = the
-// 32 positions before them (previous lane, or the block before the tile),
-// words 1..AH_NW = the lane's own, word AH_NW+1 = the 32 positions after.
+// One block of a lane (64 positions) in both planes with its neighbours:
+// word 0 = the 32 positions before it, words 1..AH_HW = the block's own,
+// word AH_HW+1 = the 32 positions after it.
+#define AH_HW 2  // words per plane of one block
 struct AhBase {
-    uint32_t h[AH_NW + 2];
-    uint32_t l[AH_NW + 2];
+    uint32_t h[AH_HW + 2];
+    uint32_t l[AH_HW + 2];
 };
 
 // Word Wd (positions 32*Wd .. 32*Wd+31 of the lane) of a plane shifted by D
 // positions (bit q = base q + D), -31 <= D <= 31: one funnel shift, none for D = 0.
 template <int D, int Wd>
-__device__ __forceinline__ uint32_t ah_shw(const uint32_t (&x)[AH_NW + 2]) {
+__device__ __forceinline__ uint32_t ah_shw(const uint32_t (&x)[AH_HW + 2]) {
     static_assert(D > -32 && D < 32, "shift out of range");
     if constexpr (D == 0) return x[Wd + 1];
     else if constexpr (D > 0) return ah_funnel(x[Wd + 2], x[Wd + 1], D);
@@ -102,13 +106,15 @@ struct TileCtx {
 #define AH_QCAP 320                       // queue entries per wave: < 64 left over + 4 x 64 of one group
 #endif
 #ifndef AH_NCTX
-#define AH_NCTX 2                         // tiles whose candidates may wait in the queue (<= 4)
+// tiles whose candidates may wait in the queue (<= 4); a two-block tile
+// holds enough candidates for full verification rounds on its own
+#define AH_NCTX (AH_BPL == 1 ? 2 : 1)
 #endif
 #ifndef AH_HCAP
 #define AH_HCAP 48                        // hits buffered per wave (LDS) before one atomic reserves their room
 #endif
 #define AH_TW (2 * AH_TILE_BLOCKS + 2)    // words per plane of a tile (+ one word each side)
-#define AH_QW (AH_NW + 1)                 // queue entry: the lane's candidate words + tag
+#define AH_QW (AH_HW + 1)                 // queue entry: one block's candidate words + tag
 // N-bitmap words covering the tile's blocks and one block on each side
 #define AH_NBW ((AH_TILE_BLOCKS + 2 + 31) / 32 + 1)
 
@@ -256,21 +262,20 @@ __device__ __forceinline__ void ah_pattern_record(const ScanArgs &a, const DPat 
 }
 
 // Verify queued entries [e0, e1) (at most 64: one per lane).  Entry =
-// {candidate words 0..AH_NW-1 (bit q of word w: clamp site 32w+q of the
-// lane), X << 8 | ctx << 6 | lane}; windows are read from the tile words
-// kept in LDS (sW[ctx][plane][word]).
+// {candidate words 0..AH_HW-1 (bit q of word w: clamp site 32w+q of one
+// block of the lane), X << 9 | block << 8 | ctx << 6 | lane}; windows are
+// read from the tile words kept in LDS (sW[ctx][plane][word]).
 template <bool kLdsOnly>
 __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
-                                const uint32_t (*sQ)[AH_QW], uint32_t e0, uint32_t e1,
+                                const TileCtx &rctx, const uint32_t (*sQ)[AH_QW], uint32_t e0, uint32_t e1,
                                 const uint32_t (*sW)[2][AH_TW], const HitBuf &hb) {
     const uint32_t e = e0 + ah_lane();
     if (e >= e1) return;
-    uint64_t m[AH_BPL];
-#pragma unroll
-    for (int b = 0; b < AH_BPL; b++) m[b] = ((uint64_t)sQ[e][2 * b + 1] << 32) | sQ[e][2 * b];
-    const uint32_t tag = sQ[e][AH_NW];
-    const uint32_t X = tag >> 8, ci = (tag >> 6) & 3u, ln = tag & 63u;
-    const TileCtx c = sCtx[ci];
+    uint64_t mm64 = ((uint64_t)sQ[e][1] << 32) | sQ[e][0];
+    const uint32_t tag = sQ[e][AH_HW];
+    const uint32_t X = tag >> 9, blk = (tag >> 8) & 1u, ci = (tag >> 6) & 3u, ln = tag & 63u;
+    // with one tile in the ring its context is wave-uniform (scalar registers)
+    const TileCtx c = AH_NCTX == 1 ? rctx : sCtx[ci];
     uint4 p0, p1;
     ah_pattern_record<kLdsOnly>(a, sPat, n_lds, X, p0, p1);
     const uint32_t L = p1.z & 0xFFu, k = (p1.z >> 8) & 0xFFu, shift = p1.z >> 24;
@@ -278,50 +283,46 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
     // window starts (tile-relative) allowed by the sequence bounds
     const int32_t lo_ok = c.lo;
     const int32_t hi_ok = c.room - (int32_t)L;
-    const int32_t lane0 = (int32_t)(64 * AH_BPL * ln) - (int32_t)shift;
-#pragma unroll
-    for (int bk = 0; bk < AH_BPL; bk++) {
-        uint64_t mm64 = m[bk];
-        while (mm64) {
-            const uint32_t bit = (uint32_t)__ffsll((unsigned long long)mm64) - 1;
-            mm64 &= mm64 - 1;
-            const int32_t pl = lane0 + 64 * bk + (int32_t)bit;  // window start, tile-relative
-            if (pl < lo_ok || pl > hi_ok) continue;
-            const uint32_t idx = (uint32_t)(pl + 32);
-            const uint32_t w = idx >> 5, off = idx & 31u;
-            const uint32_t hW = ah_funnel(Wh[w + 1], Wh[w], off);
-            const uint32_t lW = ah_funnel(Wl[w + 1], Wl[w], off);
-            uint32_t nW = 0;
-            if (c.has_n) {
-                const uint64_t gp = c.gbase + (uint64_t)(int64_t)pl;
-                const uint64_t ba = gp >> 6, bb = (gp + L - 1) >> 6;
-                const uint32_t o = (uint32_t)(gp & 63);
-                uint64_t nm = ah_block_nmask(a.st, ba) >> o;
-                if (bb != ba && o) nm |= ah_block_nmask(a.st, bb) << (64 - o);
-                nW = (uint32_t)nm;
-            }
-            const uint32_t lo = (lW & p0.y) | (~lW & p0.x);  // C : A
-            const uint32_t hi = (lW & p0.w) | (~lW & p0.z);  // T : G
-            const uint32_t matched = ((hW & hi) | (~hW & lo)) & ~nW & p1.y;
-            const uint32_t nmm = __popc(p1.y & ~matched);
-            if ((matched & p1.x) == p1.x && nmm <= k) {
-                const uint32_t pos = (uint32_t)((int64_t)c.pos0 + pl), w2 = p1.w | (nmm << 24);
-                const uint32_t slot = atomicAdd(hb.n, 1u);  // LDS
-                if (slot < AH_HCAP) {
-                    // through an LDS-qualified pointer: a generic one becomes
-                    // a FLAT store, which makes every later wait a full drain
-                    ah_lds_u32 *r = (ah_lds_u32 *)&hb.rec[slot][0];
+    const int32_t lane0 = (int32_t)(64 * (AH_BPL * ln + blk)) - (int32_t)shift;
+    while (mm64) {
+        const uint32_t bit = (uint32_t)__ffsll((unsigned long long)mm64) - 1;
+        mm64 &= mm64 - 1;
+        const int32_t pl = lane0 + (int32_t)bit;  // window start, tile-relative
+        if (pl < lo_ok || pl > hi_ok) continue;
+        const uint32_t idx = (uint32_t)(pl + 32);
+        const uint32_t w = idx >> 5, off = idx & 31u;
+        const uint32_t hW = ah_funnel(Wh[w + 1], Wh[w], off);
+        const uint32_t lW = ah_funnel(Wl[w + 1], Wl[w], off);
+        uint32_t nW = 0;
+        if (c.has_n) {
+            const uint64_t gp = c.gbase + (uint64_t)(int64_t)pl;
+            const uint64_t ba = gp >> 6, bb = (gp + L - 1) >> 6;
+            const uint32_t o = (uint32_t)(gp & 63);
+            uint64_t nm = ah_block_nmask(a.st, ba) >> o;
+            if (bb != ba && o) nm |= ah_block_nmask(a.st, bb) << (64 - o);
+            nW = (uint32_t)nm;
+        }
+        const uint32_t lo = (lW & p0.y) | (~lW & p0.x);  // C : A
+        const uint32_t hi = (lW & p0.w) | (~lW & p0.z);  // T : G
+        const uint32_t matched = ((hW & hi) | (~hW & lo)) & ~nW & p1.y;
+        const uint32_t nmm = __popc(p1.y & ~matched);
+        if ((matched & p1.x) == p1.x && nmm <= k) {
+            const uint32_t pos = (uint32_t)((int64_t)c.pos0 + pl), w2 = p1.w | (nmm << 24);
+            const uint32_t slot = atomicAdd(hb.n, 1u);  // LDS
+            if (slot < AH_HCAP) {
+                // through an LDS-qualified pointer: a generic one becomes
+                // a FLAT store, which makes every later wait a full drain
+                ah_lds_u32 *r = (ah_lds_u32 *)&hb.rec[slot][0];
+                r[0] = c.seq;
+                r[1] = pos;
+                r[2] = w2;
+            } else {  // buffer full: straight to the hit array
+                const uint64_t h = atomicAdd((unsigned long long *)a.n_hits, 1ull);
+                if (h < a.hit_cap) {
+                    uint32_t *r = a.hits + 3 * h;
                     r[0] = c.seq;
                     r[1] = pos;
                     r[2] = w2;
-                } else {  // buffer full: straight to the hit array
-                    const uint64_t h = atomicAdd((unsigned long long *)a.n_hits, 1ull);
-                    if (h < a.hit_cap) {
-                        uint32_t *r = a.hits + 3 * h;
-                        r[0] = c.seq;
-                        r[1] = pos;
-                        r[2] = w2;
-                    }
                 }
             }
         }
@@ -332,13 +333,14 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
 // Entries left over move to the front of the queue.
 template <bool kLdsOnly>
 __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
+                                         const TileCtx &rctx,
                                          uint32_t (*sQ)[AH_QW], uint32_t &qn, const uint32_t (*sW)[2][AH_TW],
                                          const HitBuf &hb, bool drain) {
     ah_wave_sync();
     uint32_t e0 = 0;
-    for (; e0 + 64 <= qn; e0 += 64) ah_verify_round<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, e0, e0 + 64, sW, hb);
+    for (; e0 + 64 <= qn; e0 += 64) ah_verify_round<kLdsOnly>(a, sPat, n_lds, sCtx, rctx, sQ, e0, e0 + 64, sW, hb);
     if (drain) {
-        if (e0 < qn) ah_verify_round<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, e0, qn, sW, hb);
+        if (e0 < qn) ah_verify_round<kLdsOnly>(a, sPat, n_lds, sCtx, rctx, sQ, e0, qn, sW, hb);
         qn = 0u;
     } else if (e0 > 0) {
         const uint32_t rest = qn - e0;  // < 64
@@ -365,133 +367,143 @@ __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, ui
 // and verify full rounds of queued candidates.
 template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds, TileCtx *sCtx,
-                                        uint32_t (*sQ)[AH_QW], uint32_t (*sW)[2][AH_TW], const HitBuf &hb,
-                                        const TileLoad &L, const SeqCursor &cur, uint32_t groups, uint32_t &qn,
-                                        uint32_t &nctx) {
+                                        TileCtx &rctx, uint32_t (*sQ)[AH_QW], uint32_t (*sW)[2][AH_TW],
+                                        const HitBuf &hb, const TileLoad &L, const SeqCursor &cur, uint32_t groups,
+                                        uint32_t &qn, uint32_t &nctx) {
     const uint32_t lane = ah_lane();
     if (nctx == AH_NCTX) {  // every context slot is referenced: verify all
-        ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, hb, true);
+        ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, rctx, sQ, qn, sW, hb, true);
         nctx = 0;
     }
     const uint32_t ci = nctx;
     nctx = ah_uni(nctx + 1);
-    const bool has_n = tile_has_n(L);
-    if (lane == 0) {
-        TileCtx c;
-        c.gbase = L.gb0 * 64;
-        c.seq = cur.seq;
-        c.pos0 = L.rel0 * 64;
-        c.lo = -(int32_t)(c.pos0 < 32u ? c.pos0 : 32u);
-        const uint32_t rest = cur.len - c.pos0;
-        c.room = (int32_t)(rest < (1u << 20) ? rest : (1u << 20));
-        c.has_n = has_n;
-        c.pad = 0;
-        sCtx[ci] = c;
-    }
-    // base words: [0] previous 32 positions, [1..AH_NW] the lane's, [AH_NW+1] next 32
-    AhBase B;
-#pragma unroll
-    for (int b = 0; b < AH_BPL; b++) {
-        B.h[1 + 2 * b] = L.blk[b].x;
-        B.l[1 + 2 * b] = L.blk[b].y;
-        B.h[2 + 2 * b] = L.blk[b].z;
-        B.l[2 + 2 * b] = L.blk[b].w;
-    }
-    B.h[AH_NW + 1] = ah_from_next_lane(B.h[1]);
-    B.l[AH_NW + 1] = ah_from_next_lane(B.l[1]);
-    if (lane == 63) {
-        B.h[AH_NW + 1] = L.hal.x;
-        B.l[AH_NW + 1] = L.hal.y;
-    }
-    B.h[0] = B.l[0] = 0u;
-    if (F::kUsesBase) {
-        // the previous 32 positions (lane 0: the block before the tile; at a
-        // sequence start they are another sequence's or padding, which only
-        // windows that verification rejects can see)
-        B.h[0] = ah_from_prev_lane(B.h[AH_NW]);
-        B.l[0] = ah_from_prev_lane(B.l[AH_NW]);
-        if (lane == 0) {
-            B.h[0] = L.hal.z;
-            B.l[0] = L.hal.w;
-        }
-    }
+    TileCtx c;  // wave-uniform
+    c.gbase = L.gb0 * 64;
+    c.seq = cur.seq;
+    c.pos0 = L.rel0 * 64;
+    c.lo = -(int32_t)(c.pos0 < 32u ? c.pos0 : 32u);
+    const uint32_t rest = cur.len - c.pos0;
+    c.room = (int32_t)(rest < (1u << 20) ? rest : (1u << 20));
+    c.has_n = tile_has_n(L);
+    c.pad = 0;
+    if (AH_NCTX == 1) rctx = c;
+    else if (lane == 0) sCtx[ci] = c;
+    // the tile's words for deferred verification: [0] the 32 positions
+    // before the tile, then every lane's blocks in order, then the 32 after
     uint32_t *Wh = sW[ci][0], *Wl = sW[ci][1];
 #pragma unroll
-    for (int w = 0; w < AH_NW; w++) {
-        Wh[1 + AH_NW * lane + w] = B.h[1 + w];
-        Wl[1 + AH_NW * lane + w] = B.l[1 + w];
+    for (int b = 0; b < AH_BPL; b++) {
+        Wh[1 + AH_NW * lane + 2 * b] = L.blk[b].x;
+        Wl[1 + AH_NW * lane + 2 * b] = L.blk[b].y;
+        Wh[2 + AH_NW * lane + 2 * b] = L.blk[b].z;
+        Wl[2 + AH_NW * lane + 2 * b] = L.blk[b].w;
+    }
+    // the lane after's first words (lane 63: the block after the tile)
+    uint32_t nxh = ah_from_next_lane(L.blk[0].x), nxl = ah_from_next_lane(L.blk[0].y);
+    if (lane == 63) {
+        nxh = L.hal.x;
+        nxl = L.hal.y;
     }
     if (lane == 0) {
         Wh[0] = L.hal.z;
         Wl[0] = L.hal.w;
     }
     if (lane == 63) {
-        Wh[AH_TW - 1] = B.h[AH_NW + 1];
-        Wl[AH_TW - 1] = B.l[AH_NW + 1];
+        Wh[AH_TW - 1] = nxh;
+        Wl[AH_TW - 1] = nxl;
     }
-    // Lanes past the sequence end hold repeated blocks; their candidates are
-    // windows past the end, which verification rejects, so no lane mask.
-    // bit q of S*[i][w]: plane bit of base 32w + q + i of the lane; only the
-    // F::kW offsets the filter reads are formed
-    uint32_t Sh[AH_WMAX][AH_NW], Sl[AH_WMAX][AH_NW];
 #pragma unroll
-    for (int i = 0; i < F::kW; i++) {
-#pragma unroll
-        for (int w = 0; w < AH_NW; w++) {
-            Sh[i][w] = ah_funnel(B.h[w + 2], B.h[w + 1], i);
-            Sl[i][w] = ah_funnel(B.l[w + 2], B.l[w + 1], i);
-        }
-    }
-    for (uint32_t g = 0; g < groups; g++) {
-        if (g < 64 && !((cur.gm >> g) & 1ull)) continue;  // group not asked for on this sequence
-        // Mark the shifted planes as redefined in every iteration (an empty
-        // asm, no instruction): otherwise, with compile-time codes, the
-        // compiler hoists every group's set tests out of this loop as
-        // invariants and runs out of registers once there are many groups.
-        if (F::kHoistGuard) {
-#pragma unroll
-            for (int i = 0; i < F::kW; i++)
-#pragma unroll
-                for (int w = 0; w < AH_NW; w++) asm volatile("" : "+v"(Sh[i][w]), "+v"(Sl[i][w]));
-            if (F::kUsesBase) {
-#pragma unroll
-                for (int w = 0; w < AH_NW + 2; w++) asm volatile("" : "+v"(B.h[w]), "+v"(B.l[w]));
+    for (int blk = 0; blk < AH_BPL; blk++) {
+        // the block's words and their neighbours
+        AhBase B;
+        B.h[1] = L.blk[blk].x;
+        B.l[1] = L.blk[blk].y;
+        B.h[2] = L.blk[blk].z;
+        B.l[2] = L.blk[blk].w;
+        B.h[3] = blk + 1 < AH_BPL ? L.blk[blk + 1 < AH_BPL ? blk + 1 : 0].x : nxh;
+        B.l[3] = blk + 1 < AH_BPL ? L.blk[blk + 1 < AH_BPL ? blk + 1 : 0].y : nxl;
+        B.h[0] = B.l[0] = 0u;
+        if (F::kUsesBase) {
+            // the 32 positions before (lane 0's first block: the block before
+            // the tile; at a sequence start they are another sequence's or
+            // padding, which only windows that verification rejects can see)
+            if (blk > 0) {
+                B.h[0] = L.blk[blk > 0 ? blk - 1 : 0].z;
+                B.l[0] = L.blk[blk > 0 ? blk - 1 : 0].w;
+            } else {
+                B.h[0] = ah_from_prev_lane(L.blk[AH_BPL - 1].z);
+                B.l[0] = ah_from_prev_lane(L.blk[AH_BPL - 1].w);
+                if (lane == 0) {
+                    B.h[0] = L.hal.z;
+                    B.l[0] = L.hal.w;
+                }
             }
         }
-        uint32_t C[4 * AH_NW];  // C[AH_NW * x + w]: clamp sites of word w, pattern x
-        f.filter(g, B, Sh, Sl, C);
-        if (F::kSkipEmpty) {  // many groups: most have no candidate in a tile
-            uint32_t any = 0;
+        // Lanes past the sequence end hold repeated blocks; their candidates
+        // are windows past the end, which verification rejects, so no lane
+        // mask.  bit q of S*[i][w]: plane bit of base 32w + q + i of the
+        // block; only the F::kW offsets the filter reads are formed
+        uint32_t Sh[AH_WMAX][AH_HW], Sl[AH_WMAX][AH_HW];
 #pragma unroll
-            for (int j = 0; j < 4 * AH_NW; j++) any |= C[j];
-            if (__ballot(any != 0) == 0) continue;
-        }
-        // room for this group's entries (at most 4 x 64); a non-draining
-        // flush leaves fewer than 64
-        if (qn > AH_QCAP - 256) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, hb, false);
+        for (int i = 0; i < F::kW; i++) {
 #pragma unroll
-        for (int x = 0; x < 4; x++) {
-            uint32_t nzw = 0;
-#pragma unroll
-            for (int w = 0; w < AH_NW; w++) nzw |= C[AH_NW * x + w];
-            const bool nz = nzw != 0;
-            const uint64_t bal = __ballot(nz);
-            if (nz) {
-                const uint32_t slot = qn + ah_mbcnt(bal);
-#pragma unroll
-                for (int w = 0; w < AH_NW; w++) sQ[slot][w] = C[AH_NW * x + w];
-                sQ[slot][AH_NW] = ((4 * g + (uint32_t)x) << 8) | (ci << 6) | lane;
+            for (int w = 0; w < AH_HW; w++) {
+                Sh[i][w] = ah_funnel(B.h[w + 2], B.h[w + 1], i);
+                Sl[i][w] = ah_funnel(B.l[w + 2], B.l[w + 1], i);
             }
-            qn = ah_uni(qn + (uint32_t)__popcll(bal));  // keeps the queue count in a scalar register
+        }
+        for (uint32_t g = 0; g < groups; g++) {
+            if (g < 64 && !((cur.gm >> g) & 1ull)) continue;  // group not asked for on this sequence
+            // Mark the shifted planes as redefined in every iteration (an
+            // empty asm, no instruction): otherwise, with compile-time codes,
+            // the compiler hoists every group's set tests out of this loop as
+            // invariants and runs out of registers once there are many groups.
+            if (F::kHoistGuard) {
+#pragma unroll
+                for (int i = 0; i < F::kW; i++)
+#pragma unroll
+                    for (int w = 0; w < AH_HW; w++) asm volatile("" : "+v"(Sh[i][w]), "+v"(Sl[i][w]));
+                if (F::kUsesBase) {
+#pragma unroll
+                    for (int w = 0; w < AH_HW + 2; w++) asm volatile("" : "+v"(B.h[w]), "+v"(B.l[w]));
+                }
+            }
+            uint32_t C[4 * AH_HW];  // C[AH_HW * x + w]: clamp sites of word w, pattern x
+            f.filter(g, B, Sh, Sl, C);
+            if (F::kSkipEmpty) {  // many groups: most have no candidate in a block
+                uint32_t any = 0;
+#pragma unroll
+                for (int j = 0; j < 4 * AH_HW; j++) any |= C[j];
+                if (__ballot(any != 0) == 0) continue;
+            }
+            // room for this group's entries (at most 4 x 64); a non-draining
+            // flush leaves fewer than 64
+            if (qn > AH_QCAP - 256) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, rctx, sQ, qn, sW, hb, false);
+#pragma unroll
+            for (int x = 0; x < 4; x++) {
+                uint32_t nzw = 0;
+#pragma unroll
+                for (int w = 0; w < AH_HW; w++) nzw |= C[AH_HW * x + w];
+                const bool nz = nzw != 0;
+                const uint64_t bal = __ballot(nz);
+                if (nz) {
+                    const uint32_t slot = qn + ah_mbcnt(bal);
+#pragma unroll
+                    for (int w = 0; w < AH_HW; w++) sQ[slot][w] = C[AH_HW * x + w];
+                    sQ[slot][AH_HW] = ((4 * g + (uint32_t)x) << 9) | ((uint32_t)blk << 8) | (ci << 6) | lane;
+                }
+                qn = ah_uni(qn + (uint32_t)__popcll(bal));  // keeps the queue count in a scalar register
+            }
         }
     }
-    if (qn >= 64) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, hb, false);
+    if (qn >= 64) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, rctx, sQ, qn, sW, hb, false);
 }
 
 // The kernel body.  Filter F provides
 //   f.groups(a)                         number of pattern groups (primer pairs),
-//   f.filter(g, B, Sh, Sl, C)           candidate words of group g (C[AH_NW*x + w]:
-//                                       clamp sites 32w..32w+31 of pattern x); a
+//   f.filter(g, B, Sh, Sl, C)           candidate words of group g in one block
+//                                       (C[AH_HW*x + w]: clamp sites 32w..32w+31
+//                                       of the block, pattern x); a
 //                                       candidate must pass a necessary condition
 //                                       of a hit; verification decides.
 //   F::kUsesBase                        whether filter reads the base words B,
@@ -527,6 +539,7 @@ __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat
 
     const uint32_t groups = f.groups(a);
     uint32_t qn = 0, nctx = 0;
+    TileCtx rctx{};  // the ring tile's context when the ring holds one tile
     SeqCursor cur;
     cur.init(a, t);
     // Two load sets used in turn: the next tile's loads go to the set not being
@@ -539,18 +552,18 @@ __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat
         SeqCursor nc = cur;
         nc.advance(a, tn);
         tile_issue(a, nc, tn, B);
-        ah_tile<kLdsOnly>(a, f, sPat, n_lds, sCtx, sQ, sW, hb, A, cur, groups, qn, nctx);
+        ah_tile<kLdsOnly>(a, f, sPat, n_lds, sCtx, rctx, sQ, sW, hb, A, cur, groups, qn, nctx);
         cur = nc;
         if (++t >= tend) break;
         tn = t + 1 < tend ? t + 1 : t;
         nc = cur;
         nc.advance(a, tn);
         tile_issue(a, nc, tn, A);
-        ah_tile<kLdsOnly>(a, f, sPat, n_lds, sCtx, sQ, sW, hb, B, cur, groups, qn, nctx);
+        ah_tile<kLdsOnly>(a, f, sPat, n_lds, sCtx, rctx, sQ, sW, hb, B, cur, groups, qn, nctx);
         cur = nc;
         if (++t >= tend) break;
     }
-    if (qn) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, sQ, qn, sW, hb, true);
+    if (qn) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, rctx, sQ, qn, sW, hb, true);
     ah_hits_out(a, hb);
 }
 
