@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--stages", default="scan,pair,tm,extract")
     ap.add_argument("--generic", action="store_true", help="use the generic scan kernel (no primer-set JIT)")
     ap.add_argument("--plain-reps", type=int, default=1, help="timed repetitions of the plain per-pair loop (batch)")
-    ap.add_argument("--no-tune", action="store_true", help="batch: skip the autotuner")
+    ap.add_argument("--no-tune", action="store_true", help="skip the scan autotuner (genome and batch lines)")
     ap.add_argument("--serve", action="store_true", help="serving workload (continuous batching, latency)")
     ap.add_argument("--sweep", action="store_true",
                     help="degeneracy and mismatch sweeps on the genome workload (prints their own line)")
@@ -134,6 +134,18 @@ def cpu_threads():
     return max(1, n)
 
 
+def cpu_model():
+    """The host CPU's model name (first processor entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(wl, sample, ex, what):
     """The oracle, unmodified, timed on the leading sequences of the workload
     (whole chunks of sequences, each run as one call; the time is their sum)."""
@@ -150,7 +162,8 @@ def cpu_baseline(wl, sample, ex, what):
         m += len(off) - 1
         n_amps += len(o.amps)
     log("oracle sample: %d amplicons in %.1f s" % (n_amps, dt))
-    return {"value": round(len(wl.pairs) * sb / dt / 1e9, 4), "unit": what, "cores": nt, "kind": "oracle",
+    return {"value": round(len(wl.pairs) * sb / dt / 1e9, 4), "unit": what, "cores": nt, "cpu": cpu_model(),
+            "kind": "oracle",
             "sample": "first %d sequences (%.4f Gbases) of the workload, %d pairs, scan+pair+Tm+extract, %.1f s"
                       % (m, sb / 1e9, len(wl.pairs), dt)}
 
@@ -612,6 +625,18 @@ def main():
     log("primer set compiled in %.2f s (specialised scan kernel: %s)" % (time.time() - tj, ps.jit))
     ex = synth.ExtractSpec(trim=wl.extract.trim, fb_len=wl.extract.fb_len, rb_len=wl.extract.rb_len)
     stream = torch.cuda.Stream()
+    tuned = None
+    if ps.jit and not args.no_tune:
+        # the autotuner's pick of tile size, hit buffer and workgroups per CU
+        # (every variant gives the same hits), timed on the whole store (a
+        # scan takes under a millisecond; a sample can rank the grids
+        # differently)
+        from paper_2511_00170_amd import batch
+        tt = time.time()
+        tuned = batch.tune_scan(store, ps, wl.pairs, wl.orient_mask, wl.tm, stream,
+                                sample_bases=float(total), reps=5, tolerance=0.01)
+        log("scan tuned in %.1f s: variant %s, %d workgroups per CU (%.4f ms on the sample)"
+            % (time.time() - tt, tuned.variant, tuned.wg_per_cu, tuned.ms))
     stages = tuple(args.stages.split(","))
     with torch.cuda.stream(stream):
         pipe = ah.Pipeline(store, ps, wl.orient_mask, wl.tm, ex)
@@ -667,7 +692,10 @@ def main():
                                % (wl.n_seqs, total / 1e9, wl.pairs[0].k, wl.pairs[0].clamp),
                    "pairs": len(wl.pairs), "k": wl.pairs[0].k, "bases": total, "stages": list(stages),
                    "hits": n_hits, "amplicons": n_amps,
-                   "scan_kernel": "primer-set specialised (hipRTC)" if ps.jit else "generic"},
+                   "scan_kernel": "primer-set specialised (hipRTC)" if ps.jit else "generic",
+                   "scan_tile_bases": 4096 * (ps.variant[0] if ps.jit and ps.variant else 1),
+                   "scan_hit_buffer": ps.variant[1] if ps.jit and ps.variant else 48,
+                   "scan_wg_per_cu": tuned.wg_per_cu if tuned else None},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

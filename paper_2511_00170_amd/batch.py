@@ -67,6 +67,73 @@ class TuneResult:
     variant: Optional[tuple] = None   # (blocks per lane, LDS hit buffer) of the specialised kernel
 
 
+def tune_scan(store: ah.Store, ps: ah.PrimerSet, pairs, orient_mask: int, tm, stream, sample_bases: float = 1e9,
+              wg_options=None, reps: int = 3, variants=None, tolerance: float = 0.02) -> TuneResult:
+    """Time the scan of a leading sample of the store (about sample_bases)
+    under each kernel variant -- the specialised kernel at every (tile size =
+    blocks per lane, LDS hit buffer) of `variants`, the generic kernel -- and
+    each persistent grid (workgroups per CU: the resident maximum, one less,
+    half).  Keep the first candidate (default variant first, larger grids
+    first) within `tolerance` of the fastest, so timing noise does not flip
+    the choice between runs, and select it in `ps`.  Every variant must give
+    the same hit set."""
+    lens = store.lengths.astype(np.int64)
+    m = int(np.searchsorted(np.cumsum(lens), sample_bases, side="left")) + 1
+    m = max(1, min(m, store.n_seqs))
+    sub = torch.arange(m, dtype=torch.int32, device=store.blocks.device)
+    cap = hit_capacity(pairs, int(lens[:m].sum()))
+    probe = ah.Pipeline(store, ps, orient_mask, tm, None, caps=ah.Caps(cap, 1, 1), subset=sub)
+    kinds = [("jit", v) for v in (variants or ah.JIT_VARIANTS)] if ps.has_jit else []
+    kinds.append(("generic", None))
+    ref, table, cands = None, [], []
+    for kind, v in kinds:
+        if kind == "jit":
+            ps.jit_variant(*v)
+        elif ps.has_jit:
+            ps.use_jit(False)
+        max_wg = ps.launch_shape(0)
+        opts = wg_options or sorted({max_wg, max(1, max_wg - 1), max(1, max_wg // 2)}, reverse=True)
+        for wg in opts:
+            if wg > max_wg:
+                continue
+            ps.launch_shape(wg)
+            while True:  # warm-up launch, sized exactly
+                probe.launch(stream, ("scan",))
+                h = probe.counts()[0]
+                if h <= probe.caps.hits:
+                    break
+                probe._alloc(ah.Caps(int(h * 1.25) + 1024, 1, 1))
+            ts = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                probe.launch(stream, ("scan",))
+                e1.record(stream)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            h = probe.counts()[0]
+            hits = ah.hits_canonical(probe.hits[:h].cpu().numpy().view(np.uint8).reshape(-1).view(ah.HIT_DTYPE))
+            if ref is None:
+                ref = hits
+            elif not np.array_equal(ref, hits):
+                raise RuntimeError("scan variant %s %s wg_per_cu=%d changed the hits" % (kind, v, wg))
+            ms = float(np.median(ts))
+            bpl, hb = v if v else (1, 48)
+            table.append({"kernel": kind, "tile_bases": 4096 * bpl, "blocks_per_lane": bpl, "hit_buffer": hb,
+                          "wg_per_cu": wg, "ms": round(ms, 4)})
+            cands.append(TuneResult(kind == "jit", wg, ms, variant=v))
+    fastest = min(c.ms for c in cands)
+    best = next(c for c in cands if c.ms <= fastest * (1.0 + tolerance))
+    best.table = table
+    if best.jit:
+        ps.jit_variant(*best.variant)
+    elif ps.has_jit:
+        ps.use_jit(False)
+    ps.launch_shape(best.wg_per_cu)
+    return best
+
+
 class BatchRunner:
     """One graph = scan (all pairs, persistent) -> pair -> Tm -> extract."""
 
@@ -91,68 +158,10 @@ class BatchRunner:
     # ------------------------------------------------------------- autotune
     def tune(self, sample_bases: float = 1e9, wg_options=None, reps: int = 3, variants=None,
              tolerance: float = 0.02) -> TuneResult:
-        """Time the scan of a leading sample of the store (about sample_bases)
-        under each kernel variant -- the specialised kernel at every (tile
-        size = blocks per lane, LDS hit buffer) of `variants`, the generic
-        kernel -- and each persistent grid (workgroups per CU).  Keep the
-        first candidate (default variant first, larger grids first) within
-        `tolerance` of the fastest, so timing noise does not flip the choice
-        between runs.  Every variant must give the same hit set."""
-        lens = self.store.lengths.astype(np.int64)
-        m = int(np.searchsorted(np.cumsum(lens), sample_bases, side="left")) + 1
-        m = max(1, min(m, self.store.n_seqs))
-        sub = torch.arange(m, dtype=torch.int32, device=self.store.blocks.device)
-        cap = hit_capacity(self.pairs, int(lens[:m].sum()))
-        probe = ah.Pipeline(self.store, self.ps, self.orient_mask, self.tm, None,
-                            caps=ah.Caps(cap, 1, 1), subset=sub)
-        kinds = [("jit", v) for v in (variants or ah.JIT_VARIANTS)] if self.ps.has_jit else []
-        kinds.append(("generic", None))
-        ref, table, cands = None, [], []
-        for kind, v in kinds:
-            if kind == "jit":
-                self.ps.jit_variant(*v)
-            elif self.ps.has_jit:
-                self.ps.use_jit(False)
-            max_wg = self.ps.launch_shape(0)
-            opts = wg_options or sorted({1, 2, max(1, max_wg // 2), max_wg}, reverse=True)
-            for wg in opts:
-                if wg > max_wg:
-                    continue
-                self.ps.launch_shape(wg)
-                while True:  # warm-up launch, sized exactly
-                    probe.launch(self.stream, ("scan",))
-                    h = probe.counts()[0]
-                    if h <= probe.caps.hits:
-                        break
-                    probe._alloc(ah.Caps(int(h * 1.25) + 1024, 1, 1))
-                ts = []
-                for _ in range(reps):
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e1 = torch.cuda.Event(enable_timing=True)
-                    e0.record(self.stream)
-                    probe.launch(self.stream, ("scan",))
-                    e1.record(self.stream)
-                    e1.synchronize()
-                    ts.append(e0.elapsed_time(e1))
-                h = probe.counts()[0]
-                hits = ah.hits_canonical(probe.hits[:h].cpu().numpy().view(np.uint8).reshape(-1).view(ah.HIT_DTYPE))
-                if ref is None:
-                    ref = hits
-                elif not np.array_equal(ref, hits):
-                    raise RuntimeError("scan variant %s %s wg_per_cu=%d changed the hits" % (kind, v, wg))
-                ms = float(np.median(ts))
-                bpl, hb = v if v else (1, 48)
-                table.append({"kernel": kind, "tile_bases": 4096 * bpl, "blocks_per_lane": bpl, "hit_buffer": hb,
-                              "wg_per_cu": wg, "ms": round(ms, 4)})
-                cands.append(TuneResult(kind == "jit", wg, ms, variant=v))
-        fastest = min(c.ms for c in cands)
-        best = next(c for c in cands if c.ms <= fastest * (1.0 + tolerance))
-        best.table = table
-        if best.jit:
-            self.ps.jit_variant(*best.variant)
-        elif self.ps.has_jit:
-            self.ps.use_jit(False)
-        self.ps.launch_shape(best.wg_per_cu)
+        """Pick the scan kernel variant and launch shape (tune_scan) for this
+        runner's pairs; the graph is captured again afterwards."""
+        best = tune_scan(self.store, self.ps, self.pairs, self.orient_mask, self.tm, self.stream,
+                         sample_bases, wg_options, reps, variants, tolerance)
         self.tuned = best
         self.graph = None
         return best
