@@ -31,6 +31,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup-s", type=float, default=0.5,
+                    help="untimed warm-up lasts at least --warmup steps and at least this long (the GPU's clocks "
+                         "settle under sustained load)")
     ap.add_argument("--config", type=int, default=2, help="workload (2 = genome scale)")
     ap.add_argument("--n-seqs", type=int, default=None, help="shrink the workload (testing)")
     ap.add_argument("--len-scale", type=float, default=1.0, help="shrink the workload (testing)")
@@ -51,7 +54,8 @@ def parse():
     ap.add_argument("--budget-mb", type=int, default=16384, help="serve: device memory budget per batch")
     ap.add_argument("--no-extras", action="store_true",
                     help="genome run only: skip the batched-vs-plain and serving sub-results")
-    ap.add_argument("--extra-requests", type=int, default=400, help="serving sub-result: requests per run")
+    ap.add_argument("--extra-requests", type=int, default=2000,
+                    help="serving sub-result: measured requests per run (warm-up: a tenth as many)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM counters)")
     return ap.parse_args()
@@ -342,9 +346,12 @@ def bench_batch(args, wl, store, sample):
     res = br.run()                                 # eager sizing + capture + one replay
     n_hits, n_amps, n_bytes = br.pipe.counts()
     log("batch: hits %d amplicons %d pass %d bytes %d" % (n_hits, n_amps, int(res["pass"].sum()), n_bytes))
-    for _ in range(args.warmup):
+    n_warm, t_w = 0, time.perf_counter()
+    while n_warm < args.warmup or time.perf_counter() - t_w < args.warmup_s:
         br.replay()
-    torch.cuda.synchronize()
+        n_warm += 1
+        torch.cuda.synchronize()
+    log("warm-up: %d steps in %.2f s" % (n_warm, time.perf_counter() - t_w))
     t_start = time.perf_counter()
     for _ in range(args.steps):
         br.replay()
@@ -391,7 +398,7 @@ def bench_batch(args, wl, store, sample):
                    "pairs": npairs, "bases": total, "hits": n_hits, "amplicons": n_amps,
                    "scan_kernel": "primer-set specialised (hipRTC)" if br.ps.jit else "generic",
                    "graph": True, "autotune": tuned.table if tuned else None,
-                   "wg_per_cu": tuned.wg_per_cu if tuned else 0, "variant": variant},
+                   "wg_per_cu": tuned.wg_per_cu if tuned else 0, "variant": variant, "warmup_steps_run": n_warm},
         "batched_vs_plain": {"batched_ms": round(ms_step, 3),
                              "plain_loop_ms": round(plain_ms, 3) if plain_ms else None,
                              "speedup": round(plain_ms / ms_step, 3) if plain_ms else None,
@@ -521,14 +528,15 @@ def extra_batch(args):
 
 
 def extra_serve(args):
-    """Continuous batching on the 19.9 Gb serving store (shortened runs)."""
+    """Continuous batching on the 19.9 Gb serving store: per arrival rate,
+    2000 measured requests after 200 warm-up ones by default."""
     import copy
 
     from paper_2511_00170_amd import synth
     wl = synth.gen_config(5)
     store = make_store(wl)
     a = copy.copy(args)
-    a.requests, a.warm_requests = args.extra_requests, max(1, args.extra_requests // 8)
+    a.requests, a.warm_requests = args.extra_requests, max(1, args.extra_requests // 10)
     o = bench_serve(a, wl, store)
     r = dict(o["serve"])
     r.update({"workload": o["config"]["workload"], "unit": "pair-Gbases/s",
@@ -634,7 +642,7 @@ def main():
         from paper_2511_00170_amd import batch
         tt = time.time()
         tuned = batch.tune_scan(store, ps, wl.pairs, wl.orient_mask, wl.tm, stream,
-                                sample_bases=float(total), reps=5, tolerance=0.01)
+                                sample_bases=float(total), reps=9, tolerance=0.01, variants=((2, 48), (1, 48)))
         log("scan tuned in %.1f s: variant %s, %d workgroups per CU (%.4f ms on the sample)"
             % (time.time() - tt, tuned.variant, tuned.wg_per_cu, tuned.ms))
     stages = tuple(args.stages.split(","))
@@ -644,9 +652,14 @@ def main():
         n_hits, n_amps, n_bytes = pipe.counts()
         log("hits %d amplicons %d pass %d bytes %d" % (n_hits, n_amps, int(pipe.passed[:n_amps].sum().item()),
                                                       n_bytes))
-        for _ in range(args.warmup):
-            pipe.launch(stream, stages)
+        n_warm, t_w = 0, time.perf_counter()
+        while n_warm < args.warmup or time.perf_counter() - t_w < args.warmup_s:
+            for _ in range(8):
+                pipe.launch(stream, stages)
+            n_warm += 8
+            stream.synchronize()
         torch.cuda.synchronize()
+        log("warm-up: %d steps in %.2f s" % (n_warm, time.perf_counter() - t_w))
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
         t_start = time.perf_counter()
         for i in range(args.steps):
@@ -662,11 +675,20 @@ def main():
     alg_bytes = BYTES_PER_BASE * total + 12.0 * n_hits
     achieved = alg_bytes / (scan_ms / 1e3) / 1e9
     prof = counters_from_profiles("scan_genome", scan_source_hash()) if ps.jit else None
+    if prof and prof.get("variant") != (list(ps.variant) if ps.variant else None):
+        prof = None      # counters of another tile / hit-buffer variant
     traffic = prof.get("hbm_bytes_per_launch") if prof else None
+    # the committed kernel trace of the same command: its timed dispatches'
+    # average, beside this run's event timing
+    trace_ms = prof.get("trace_timed_avg_us") / 1e3 if prof and prof.get("trace_timed_avg_us") else None
     stream_gbs = stream_read_probe()
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "ah_scan_jit" if ps.jit else "ah_scan_kernel", "kernel_ms": round(scan_ms, 4),
+            "kernel_ms_timing": "HIP events around each timed launch, on the launch stream",
+            "trace_kernel_ms": round(trace_ms, 4) if trace_ms else None,
+            "trace_frac": round(alg_bytes / (trace_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if trace_ms else None,
+            "trace_wg_per_cu": prof.get("trace_wg_per_cu") if trace_ms else None,
             "algorithmic_bytes_per_launch": int(alg_bytes),
             "measured_hbm_frac": round(traffic / (scan_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
             "stream_read_GB_s": stream_gbs, "frac_of_stream_read": round(achieved / stream_gbs, 4),
@@ -695,7 +717,8 @@ def main():
                    "scan_kernel": "primer-set specialised (hipRTC)" if ps.jit else "generic",
                    "scan_tile_bases": 4096 * (ps.variant[0] if ps.jit and ps.variant else 1),
                    "scan_hit_buffer": ps.variant[1] if ps.jit and ps.variant else 48,
-                   "scan_wg_per_cu": tuned.wg_per_cu if tuned else None},
+                   "scan_wg_per_cu": tuned.wg_per_cu if tuned else None,
+                   "warmup_steps_run": n_warm},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -68,7 +68,8 @@ class TuneResult:
 
 
 def tune_scan(store: ah.Store, ps: ah.PrimerSet, pairs, orient_mask: int, tm, stream, sample_bases: float = 1e9,
-              wg_options=None, reps: int = 3, variants=None, tolerance: float = 0.02) -> TuneResult:
+              wg_options=None, reps: int = 3, variants=None, tolerance: float = 0.02,
+              prewarm_s: float = 0.3) -> TuneResult:
     """Time the scan of a leading sample of the store (about sample_bases)
     under each kernel variant -- the specialised kernel at every (tile size =
     blocks per lane, LDS hit buffer) of `variants`, the generic kernel -- and
@@ -76,7 +77,11 @@ def tune_scan(store: ah.Store, ps: ah.PrimerSet, pairs, orient_mask: int, tm, st
     half).  Keep the first candidate (default variant first, larger grids
     first) within `tolerance` of the fastest, so timing noise does not flip
     the choice between runs, and select it in `ps`.  Every variant must give
-    the same hit set."""
+    the same hit set.  The GPU's clocks settle under sustained load (a scan
+    right after idle time runs up to ~20% slower than in steady state), so
+    the first candidate runs back to back for prewarm_s before any timing,
+    and each candidate's reps run back to back, each between its own pair of
+    events."""
     lens = store.lengths.astype(np.int64)
     m = int(np.searchsorted(np.cumsum(lens), sample_bases, side="left")) + 1
     m = max(1, min(m, store.n_seqs))
@@ -103,15 +108,19 @@ def tune_scan(store: ah.Store, ps: ah.PrimerSet, pairs, orient_mask: int, tm, st
                 if h <= probe.caps.hits:
                     break
                 probe._alloc(ah.Caps(int(h * 1.25) + 1024, 1, 1))
-            ts = []
-            for _ in range(reps):
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
+            if not cands and prewarm_s > 0:
+                t_w = time.perf_counter()
+                while time.perf_counter() - t_w < prewarm_s:
+                    for _ in range(8):
+                        probe.launch(stream, ("scan",))
+                    stream.synchronize()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            for e0, e1 in evs:
                 e0.record(stream)
                 probe.launch(stream, ("scan",))
                 e1.record(stream)
-                e1.synchronize()
-                ts.append(e0.elapsed_time(e1))
+            stream.synchronize()
+            ts = [e0.elapsed_time(e1) for e0, e1 in evs]
             h = probe.counts()[0]
             hits = ah.hits_canonical(probe.hits[:h].cpu().numpy().view(np.uint8).reshape(-1).view(ah.HIT_DTYPE))
             if ref is None:

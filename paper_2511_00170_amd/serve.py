@@ -28,7 +28,10 @@ tested without a GPU.
 """
 from __future__ import annotations
 
+import os
+import threading
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional, Sequence
 
@@ -268,6 +271,46 @@ def plan_batch(reqs: Sequence[Request], pool: Sequence[PairSpec], n_seqs: int,
                      np.array(slot_req, np.int64), np.array(slot_thr, np.float64))
 
 
+_COPY_LOCK = threading.Lock()
+_COPY_POOL: Optional[ThreadPoolExecutor] = None
+_COPY_CHUNK = 8 << 20
+
+
+def _copy_threads() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(8, n))
+
+
+def parallel_copy(src: np.ndarray) -> np.ndarray:
+    """A copy of a byte buffer, made by up to 8 host threads in 8 MB chunks.
+    A batch at saturation returns 100-200 MB of amplicon bytes; one thread's
+    copy of that out of the pinned staging buffer takes tens of
+    milliseconds, and numpy releases the GIL while it copies."""
+    global _COPY_POOL
+    src = np.asarray(src, np.uint8).reshape(-1)
+    dst = np.empty_like(src)
+    n = len(src)
+    parts = -(-n // _COPY_CHUNK)
+    if parts <= 1:
+        dst[:] = src
+        return dst
+    with _COPY_LOCK:
+        if _COPY_POOL is None:
+            _COPY_POOL = ThreadPoolExecutor(_copy_threads(), thread_name_prefix="ah-copy")
+        pool = _COPY_POOL
+
+    def one(i):
+        a, b = i * _COPY_CHUNK, min(n, (i + 1) * _COPY_CHUNK)
+        np.copyto(dst[a:b], src[a:b])
+
+    for f in [pool.submit(one, i) for i in range(parts)]:
+        f.result()
+    return dst
+
+
 def split_results(plan: BatchPlan, amps, tm, tm_site, passed, seq: bytes, seq_off: np.ndarray,
                   slot_pair_index: List[int]) -> Dict[int, RequestResult]:
     """Split a batch's amplicons (ordered by sequence, slot, site) by request."""
@@ -277,7 +320,7 @@ def split_results(plan: BatchPlan, amps, tm, tm_site, passed, seq: bytes, seq_of
     sb = np.frombuffer(seq, np.uint8) if isinstance(seq, (bytes, bytearray)) else np.asarray(seq, np.uint8)
     off = seq_off.astype(np.int64)
     lens_all = off[1:] - off[:-1]
-    buf = sb.copy()                                     # the batch's bytes, shared by its requests
+    buf = parallel_copy(sb)                             # the batch's bytes, shared by its requests
     order = np.argsort(req_of, kind="stable")          # amplicons grouped by request, order kept
     bounds = np.searchsorted(req_of[order], np.arange(len(plan.reqs) + 1))
     for r, rq in enumerate(plan.reqs):

@@ -119,6 +119,15 @@ def test_split_results_by_request():
     assert r8.amps["pair"].tolist() == [0] and r8.seq == b"GGGG" and r8.tm.tolist() == [53.0]
 
 
+@pytest.mark.parametrize("n", [0, 1, 5, (8 << 20) - 1, 8 << 20, (8 << 20) + 1, 3 * (8 << 20) + 12345])
+def test_parallel_copy_is_a_copy(n):
+    src = np.random.default_rng(n).integers(0, 256, n, dtype=np.uint8)
+    dst = serve.parallel_copy(src)
+    assert dst.dtype == np.uint8 and dst.shape == src.shape and np.array_equal(dst, src)
+    if n:
+        assert not np.shares_memory(dst, src)
+
+
 def test_request_cost_grows_with_subset_and_pairs():
     wl = synth.gen_config(5, n_seqs=50, len_scale=0.01)
     lens = wl.lengths.astype(np.int64)
