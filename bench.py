@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--plain-reps", type=int, default=1, help="timed repetitions of the plain per-pair loop (batch)")
     ap.add_argument("--no-tune", action="store_true", help="skip the scan autotuner (genome and batch lines)")
     ap.add_argument("--serve", action="store_true", help="serving workload (continuous batching, latency)")
+    ap.add_argument("--sweep-points", default=None,
+                    help="sweep only these points, e.g. 'degeneracy:6,mismatch:3' (default: all)")
     ap.add_argument("--sweep", action="store_true",
                     help="degeneracy and mismatch sweeps on the genome workload (prints their own line)")
     ap.add_argument("--requests", type=int, default=2000, help="serve: measured requests per run")
@@ -287,9 +289,14 @@ def bench_sweep(args, wl, store):
                        % (wl.n_seqs, total / 1e9, wl.pairs[0].fwd, wl.pairs[0].rev, wl.pairs[0].k,
                           wl.pairs[0].clamp)}
     stream = torch.cuda.Stream()
+    only = None
+    if args.sweep_points:
+        only = {(p.split(":")[0], int(p.split(":")[1])) for p in args.sweep_points.split(",")}
     for kind in ("degeneracy", "mismatch"):
         rows = []
         for x, pair in synth.sweep_pairs(wl.pairs[0], kind):
+            if only is not None and (kind, x) not in only:
+                continue
             tc = time.perf_counter()
             ps = ah.PrimerSet([pair], jit=True)
             t_compile = time.perf_counter() - tc

@@ -30,8 +30,9 @@ typedef __hip_internal::int64_t int64_t;
 #define AH_MAXL 32
 // Variants per primer the Tm kernel will enumerate.
 #define AH_MAX_VARIANTS (1u << 24)
-// Variants per primer tabulated in its record (one load per variant in the
-// Tm kernel instead of a walk over the degenerate positions).
+// Entries of each of the two half tables of a primer's variants (the Tm
+// kernel builds variant v from two loads instead of a walk over the
+// degenerate positions, for up to AH_VARTAB^2 variants).
 #define AH_VARTAB 64
 
 // One oriented pattern: pair q, kind (bit0 reverse primer, bit1 minus strand).
@@ -57,12 +58,20 @@ struct DPrimer {
     uint8_t deg_pos[AH_MAXL];
     uint8_t deg_n[AH_MAXL];
     uint8_t deg_base[AH_MAXL][4];
-    uint64_t var[AH_VARTAB];  // codes of variants 0..D-1 when D <= AH_VARTAB (else enumerated on the fly)
+    // Variant v = a * rb + b (b indexes the last degenerate positions, which
+    // vary fastest) has the codes hi[a] | lo[b]: lo holds the codes of those
+    // last positions, hi every other position.  rb = 0: no split with both
+    // halves within AH_VARTAB entries; variants are enumerated on the fly.
+    uint32_t rb;
+    uint32_t ra;
+    uint64_t lo[AH_VARTAB];
+    uint64_t hi[AH_VARTAB];
 };
 
 // Variant v of a degenerate primer as 2-bit codes (base j at bits 2j): v in
 // mixed radix over the degenerate positions, the last one varying fastest.
-// The host fills DPrimer::var with it, the Tm kernel calls it past the table.
+// The host fills the half tables with it; the Tm kernel calls it when the
+// primer has no split.
 __host__ __device__ inline uint64_t primer_variant(const DPrimer &P, uint64_t base, uint32_t v) {
     uint64_t V = base;
     for (int d = P.n_deg - 1; d >= 0; d--) {

@@ -115,8 +115,22 @@ static void make_primer(const int *m, int L, DPrimer *p) {
         if (D > AH_MAX_VARIANTS) D = (uint64_t)AH_MAX_VARIANTS + 1;
     }
     p->D = D > AH_MAX_VARIANTS ? 0u : (uint32_t)D;  // 0: too many variants for Tm
-    if (p->D && p->D <= AH_VARTAB)
-        for (uint32_t v = 0; v < p->D; v++) p->var[v] = primer_variant(*p, p->base, v);
+    if (!p->D) return;
+    // split the degenerate positions: the longest run of last positions with
+    // at most AH_VARTAB combinations (b), the rest (a)
+    uint32_t rb = 1;
+    int d0 = p->n_deg;
+    while (d0 > 0 && rb * p->deg_n[d0 - 1] <= AH_VARTAB) rb *= p->deg_n[--d0];
+    const uint32_t ra = p->D / rb;
+    if (ra > AH_VARTAB) return;
+    uint64_t lo_mask = 0;
+    for (int d = d0; d < p->n_deg; d++) lo_mask |= 3ull << (2 * p->deg_pos[d]);
+    for (uint32_t b = 0; b < rb; b++) p->lo[b] = primer_variant(*p, p->base, b) & lo_mask;
+    for (uint32_t a = 0; a < ra; a++) p->hi[a] = primer_variant(*p, p->base, a * rb) & ~lo_mask;
+    for (uint32_t v = 0; v < p->D; v++)
+        if ((p->hi[v / rb] | p->lo[v % rb]) != primer_variant(*p, p->base, v)) return;  // (cannot happen)
+    p->rb = rb;
+    p->ra = ra;
 }
 
 // Build the primer set's host tables; unless host_only, also its device tables.

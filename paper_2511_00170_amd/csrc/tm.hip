@@ -342,12 +342,19 @@ struct LdsTables {
     }
 };
 
+// Entries 256..271 of the staged stack table: (0, 0), read by a step outside
+// the helix (entry 256 + the variant's dinucleotide: the address needs no
+// select per variant).
+#define AH_ZERO_ENTRY 256
+#define AH_STACK_ENTRIES (256 + 16)
+
 __device__ void stage_tables(double2 *st, double2 *tt, int set) {
     const NNTable &S = g_stack[set];
     for (int i = threadIdx.x; i < 256; i += blockDim.x) {
         st[i] = tab_ok(S.ok, i) ? make_double2(S.dh[i], S.ds[i]) : make_double2(NAN, NAN);
         tt[i] = tab_ok(g_term.ok, i) ? make_double2(g_term.dh[i], g_term.ds[i]) : make_double2(NAN, NAN);
     }
+    if (threadIdx.x < AH_STACK_ENTRIES - 256) st[AH_ZERO_ENTRY + threadIdx.x] = make_double2(0.0, 0.0);
     __syncthreads();
 }
 
@@ -362,6 +369,26 @@ __device__ __forceinline__ int gc_count(uint64_t V, int L) {
     // codes 1 (C) and 2 (G) have differing bits
     const uint64_t lmask = L >= 32 ? ~0ull : ((1ull << (2 * L)) - 1);
     return __popcll((V ^ (V >> 1)) & 0x5555555555555555ull & lmask);
+}
+
+// The salt term and Tm = 1000 dH / (dS + R ln C) - 273.15 from the summed
+// dH and dS (salt method 5 adds to dS first; 1-4 add to Tm; 6 and 7 add to
+// 1/Tm).
+__device__ __forceinline__ double tm_of_sums(double dh, double ds, const PrimerEnds &P, const TmConst &k) {
+    const int L = P.L;
+    if (k.saltcorr == 5) ds += 0.368 * (double)(L - 1) * k.ln_mon;
+    double tm = (1000.0 * dh) / (ds + k.rlnc) - 273.15;
+    if (k.saltcorr >= 1 && k.saltcorr <= 4) tm += k.dtm;
+    if (k.saltcorr >= 6) {
+        const double fgc = (double)P.gc / (double)L;
+        double corr;
+        if (k.mg_model)
+            corr = (k.m7a + fgc * k.m7b + k.m7d / (2.0 * (L - 1))) * 1e-5;
+        else
+            corr = (4.29 * fgc - 3.95) * 1e-5 * k.ln_mon + 9.40e-6 * k.ln_mon * k.ln_mon;
+        tm = 1.0 / (1.0 / (tm + 273.15) + corr) - 273.15;
+    }
+    return tm;
 }
 
 // Steps after the dangling ends, on the helix of n facing pairs V / C (2-bit
@@ -414,20 +441,7 @@ __device__ bool helix_tm(uint64_t V, uint64_t C, int n, double dh, double ds, co
         dh += a;
         ds += b;
     }
-    const int L = P.L;
-    if (k.saltcorr == 5) ds += 0.368 * (double)(L - 1) * k.ln_mon;
-    double tm = (1000.0 * dh) / (ds + k.rlnc) - 273.15;
-    if (k.saltcorr >= 1 && k.saltcorr <= 4) tm += k.dtm;
-    if (k.saltcorr >= 6) {
-        const double fgc = (double)P.gc / (double)L;
-        double corr;
-        if (k.mg_model)
-            corr = (k.m7a + fgc * k.m7b + k.m7d / (2.0 * (L - 1))) * 1e-5;
-        else
-            corr = (4.29 * fgc - 3.95) * 1e-5 * k.ln_mon + 9.40e-6 * k.ln_mon * k.ln_mon;
-        tm = 1.0 / (1.0 / (tm + 273.15) + corr) - 273.15;
-    }
-    *out = tm;
+    *out = tm_of_sums(dh, ds, P, k);
     return true;
 }
 
@@ -442,6 +456,102 @@ __device__ __forceinline__ bool duplex_tm(uint64_t V, uint64_t C, int L, const T
 }
 
 // ---------------------------------------------------------------- sites
+// The initiation terms of the selected set, read once per kernel (uniform,
+// scalar registers).
+struct InitTerms {
+    double dh0, ds0, gc_dh, gc_ds, at0_dh, at0_ds, end_at_dh, end_at_ds, end_gc_dh, end_gc_ds;
+    __device__ explicit InitTerms(int set) {
+        const NNInit &I = g_init[set];
+        dh0 = I.init_dh, ds0 = I.init_ds;
+        gc_dh = I.one_gc_dh, gc_ds = I.one_gc_ds, at0_dh = I.all_at_dh, at0_ds = I.all_at_ds;
+        end_at_dh = I.at_dh, end_at_ds = I.at_ds, end_gc_dh = I.gc_dh, end_gc_ds = I.gc_ds;
+    }
+};
+
+// Byte offset in a staged table of the entry nn_index(V_j, V_j+1, C_j, C_j+1).
+__device__ __forceinline__ uint32_t stack_off(uint64_t V, uint64_t C, int j) {
+    return (((uint32_t)(V >> (2 * j)) & 15u) << 4) | (((uint32_t)(C >> (2 * j)) & 15u) << 8);
+}
+
+__device__ __forceinline__ double2 lds_at(const double2 *t, uint32_t off) {
+    return *(const double2 *)((const char *)t + off);
+}
+
+// Tm of variant V (L >= 3 bases) on the site whose partner strand, read
+// 3'->5' against it, is C: the additions of helix_tm over the whole duplex,
+// in the same order -- terminal mismatch at the left end, then the right
+// end; initiation; stacks j = lo .. hi - 1 from 5' to 3'; salt -- with the
+// stack loop unrolled over fixed positions, in groups of four up to the
+// wave's longest site (lw, wave-uniform).  A step outside the helix reads a
+// zero entry: the first and the last step when an end pair left the helix,
+// and steps j >= L - 2 of a shorter site in the wave (the partner part of
+// the address then points into the zero block).  Adding +0.0 leaves a sum
+// unchanged, since the sums start at +0.0 and a sum of two numbers is -0.0
+// only when both are.  An untabulated stack reads NaN, which carries to the
+// end, where the variant is dropped (helix_tm leaves its loop there instead).
+__device__ __forceinline__ bool site_variant_tm(uint64_t V, uint64_t C, int L, int lw, const double2 *st,
+                                                const double2 *tt, const InitTerms &I, const TmConst &k,
+                                                double *out) {
+    double dh = 0.0, ds = 0.0;
+    // left end, read from the partner strand: nn_index(C_1, C_0, V_1, V_0)
+    const uint32_t il = (uint32_t)(((C >> 2) & 3u) | ((C & 3u) << 2) | (((V >> 2) & 3u) << 4) | ((V & 3u) << 6));
+    const double2 tl = tt[il];
+    const bool left_out = tl.x == tl.x;
+    if (left_out) {
+        dh += tl.x;
+        ds += tl.y;
+    }
+    // right end: nn_index(V_L-2, V_L-1, C_L-2, C_L-1)
+    const uint32_t last = stack_off(V, C, L - 2);
+    const double2 tr = lds_at(tt, last);
+    const bool right_out = tr.x == tr.x;
+    if (right_out) {
+        dh += tr.x;
+        ds += tr.y;
+    }
+    const int gc = gc_count(V, L);
+    const int e0 = (int)(V & 3u), e1 = (int)((V >> (2 * (L - 1))) & 3u);
+    dh += I.dh0;
+    ds += I.ds0;
+    dh += gc ? I.gc_dh : I.at0_dh;
+    ds += gc ? I.gc_ds : I.at0_ds;
+    const bool at0 = e0 == 0 || e0 == 3, at1 = e1 == 0 || e1 == 3;
+    dh += at0 ? I.end_at_dh : I.end_gc_dh;
+    ds += at0 ? I.end_at_ds : I.end_gc_ds;
+    dh += at1 ? I.end_at_dh : I.end_gc_dh;
+    ds += at1 ? I.end_at_ds : I.end_gc_ds;
+    const uint32_t zero = 16u * AH_ZERO_ENTRY;
+    double2 e = lds_at(st, left_out ? zero : stack_off(V, C, 0));
+    dh += e.x;
+    ds += e.y;
+#pragma unroll
+    for (int g = 0; g < (AH_MAXL - 3 + 3) / 4; g++) {
+        if (1 + 4 * g >= lw - 2) break;  // uniform
+        double2 E[4];  // the group's four reads first, then its additions in order
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int j = 1 + 4 * g + t;
+            if (j < AH_MAXL - 2) {
+                const uint32_t cp = j < L - 2 ? (((uint32_t)(C >> (2 * j)) & 15u) << 8) : zero;
+                E[t] = lds_at(st, (((uint32_t)(V >> (2 * j)) & 15u) << 4) | cp);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            if (1 + 4 * g + t < AH_MAXL - 2) {
+                dh += E[t].x;
+                ds += E[t].y;
+            }
+        }
+    }
+    e = lds_at(st, right_out ? zero : last);
+    dh += e.x;
+    ds += e.y;
+    if (!(dh == dh)) return false;
+    *out = tm_of_sums(dh, ds, PrimerEnds{e0, e1, L, gc}, k);
+    return true;
+}
+
 __device__ __forceinline__ uint64_t spread_bits(uint32_t v) {
     uint64_t x = v;
     x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
@@ -498,13 +608,14 @@ __device__ __forceinline__ uint64_t primer_base_codes(const DPrimer &P) { return
 // Bounded to six waves per SIMD (80 VGPRs, two spilled): latency-bound, it
 // gains more from the sixth wave than the spills cost (seven: 72, eleven
 // spilled, slower).
-__global__ void __launch_bounds__(256, 6) ah_tm_site_kernel(ah_store st, const DPair *pairs, const uint32_t *amps,
+__global__ void __launch_bounds__(256, 4) ah_tm_site_kernel(ah_store st, const DPair *pairs, const uint32_t *amps,
                                                          const uint64_t *d_n, uint64_t cap, TmConst k,
                                                          uint32_t lps, double *tm_site, const double *pair_thr,
                                                          double *tm, uint8_t *pass) {
-    __shared__ double2 sst[256], stt[256];
+    __shared__ double2 sst[AH_STACK_ENTRIES], stt[256];
     stage_tables(sst, stt, k.table);
     const LdsTables nn{sst, stt};
+    const InitTerms init(k.table);
     const uint64_t n = *d_n < cap ? *d_n : cap;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t per_wave = 64u / lps, sub = lane / lps, vl = lane % lps;
@@ -531,14 +642,36 @@ __global__ void __launch_bounds__(256, 6) ah_tm_site_kernel(ah_store st, const D
         const uint64_t lm = L == 32 ? ~0ull : ((1ull << (2 * L)) - 1);
         const uint64_t Cc = side == 0 ? (G ^ (0xFFFFFFFFFFFFFFFFull & lm)) : reverse_codes(G, L);
         double best = -INFINITY;
+        int lw = live && !has_n && P.D ? L : 0;
+        for (int d = 32; d >= 1; d >>= 1) {
+            const int o = __shfl_xor(lw, d, 64);
+            lw = o > lw ? o : lw;
+        }
+        lw = __builtin_amdgcn_readfirstlane(lw);
         if (live && !has_n && P.D) {
-            const uint64_t base = primer_base_codes(P);
-            const bool tab = P.D <= AH_VARTAB;
-            for (uint32_t v = vl; v < P.D; v += lps) {
-                double t;
-                const uint64_t V = tab ? P.var[v] : primer_variant(P, base, v);
-                if (duplex_tm(V, Cc, L, nn, k, &t))
-                    best = t > best ? t : best;
+            if (P.rb && L >= 3) {
+                // variant v = a * rb + b: both halves advance by lps per step
+                // (the loop bound lw: the wave's longest such site)
+                const uint32_t rb = P.rb, ia = lps / rb, ib = lps - ia * rb;
+                uint32_t a = vl / rb, b = vl - (vl / rb) * rb;
+                for (uint32_t v = vl; v < P.D; v += lps) {
+                    double t;
+                    if (site_variant_tm(P.hi[a] | P.lo[b], Cc, L, lw, sst, stt, init, k, &t))
+                        best = t > best ? t : best;
+                    a += ia;
+                    b += ib;
+                    if (b >= rb) {
+                        b -= rb;
+                        a += 1;
+                    }
+                }
+            } else {
+                const uint64_t base = primer_base_codes(P);
+                for (uint32_t v = vl; v < P.D; v += lps) {
+                    double t;
+                    if (duplex_tm(primer_variant(P, base, v), Cc, L, nn, k, &t))
+                        best = t > best ? t : best;
+                }
             }
         }
         for (uint32_t d = lps >> 1; d >= 1; d >>= 1) {  // within the site's lanes

@@ -313,26 +313,36 @@ def parallel_copy(src: np.ndarray) -> np.ndarray:
 
 def split_results(plan: BatchPlan, amps, tm, tm_site, passed, seq: bytes, seq_off: np.ndarray,
                   slot_pair_index: List[int]) -> Dict[int, RequestResult]:
-    """Split a batch's amplicons (ordered by sequence, slot, site) by request."""
+    """Split a batch's amplicons (ordered by sequence, slot, site) by request.
+    The batch's arrays are permuted once into request order (a stable radix
+    sort on the 8-bit request index keeps each request's own order); every
+    request's result holds slices of them and its byte ranges of one shared
+    copy of the batch's amplicon bytes."""
     out = {}
-    req_of = plan.slot_req[amps["pair"].astype(np.int64)] if len(amps) else np.zeros(0, np.int64)
+    n_req = len(plan.reqs)
+    assert n_req <= 256
+    req_of = (plan.slot_req[amps["pair"].astype(np.int64)] if len(amps) else np.zeros(0, np.int64)).astype(np.uint8)
     spi = np.asarray(slot_pair_index, np.uint16)
     sb = np.frombuffer(seq, np.uint8) if isinstance(seq, (bytes, bytearray)) else np.asarray(seq, np.uint8)
     off = seq_off.astype(np.int64)
-    lens_all = off[1:] - off[:-1]
     buf = parallel_copy(sb)                             # the batch's bytes, shared by its requests
     order = np.argsort(req_of, kind="stable")          # amplicons grouped by request, order kept
-    bounds = np.searchsorted(req_of[order], np.arange(len(plan.reqs) + 1))
+    bounds = np.zeros(n_req + 1, np.int64)
+    bounds[1:] = np.cumsum(np.bincount(req_of, minlength=n_req)[:n_req])
+    a_all = amps[order]
+    if len(a_all):
+        a_all["pair"] = spi[a_all["pair"].astype(np.int64)]
+    tms = np.ascontiguousarray(tm_site, np.float64).reshape(-1, 2)
+    tm_all, pas_all = tm[order], passed[order]
+    tms_all = tms.view(np.complex128).reshape(-1)[order].view(np.float64).reshape(-1, 2)   # row gather
+    start_all = off[:-1][order]
+    len_all = off[1:][order] - start_all
     for r, rq in enumerate(plan.reqs):
-        idx = order[bounds[r]:bounds[r + 1]]
-        a = amps[idx].copy()
-        if len(a):
-            a["pair"] = spi[a["pair"].astype(np.int64)]
-        lens = lens_all[idx]
-        so = np.zeros(len(idx) + 1, np.uint64)
-        so[1:] = np.cumsum(lens)
-        out[rq.rid] = RequestResult(rq.rid, a, tm[idx].copy(), tm_site[idx].copy(), passed[idx].copy(),
-                                    (buf, off[idx]), so)
+        lo, hi = int(bounds[r]), int(bounds[r + 1])
+        so = np.zeros(hi - lo + 1, np.uint64)
+        np.cumsum(len_all[lo:hi], out=so[1:])
+        out[rq.rid] = RequestResult(rq.rid, a_all[lo:hi], tm_all[lo:hi], tms_all[lo:hi], pas_all[lo:hi],
+                                    (buf, start_all[lo:hi]), so)
     return out
 
 
