@@ -11,6 +11,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -43,7 +44,11 @@ struct GenericFilter {
     static constexpr int kW = AH_WMAX;
     static constexpr bool kHoistGuard = false;  // codes are read at run time
     static constexpr bool kSkipEmpty = true;
-    __device__ __forceinline__ void filter(uint32_t g, const AhBase &, const uint32_t (&Sh)[AH_WMAX][AH_HW],
+    static constexpr int kHalves = 1;
+    static constexpr int kGroupStep = 1;
+    __device__ __forceinline__ void block(const AhBase &, int) {}
+    __device__ __forceinline__ void guard() {}
+    __device__ __forceinline__ void filter(uint32_t g, int, const AhBase &, const uint32_t (&Sh)[AH_WMAX][AH_HW],
                                            const uint32_t (&Sl)[AH_WMAX][AH_HW], uint32_t (&C)[4 * AH_HW]) const {
         uint32_t fc[4][2], W = 0;
 #pragma unroll
@@ -199,7 +204,10 @@ struct AhJitSet {
 // patterns of a strand, so their shifted planes are shared), round-robin.
 // The group size s (0 = clamp only) minimises an estimate of vector
 // instructions per 4096-base tile: tests and shifts against candidates
-// verified (about 2.25 instructions each, measured).
+// verified (about 2.25 instructions each, measured).  In a set of many pairs
+// the shifted planes of each strand are formed once per block for all of
+// them (offsets within [-kSharedReach, kSharedReach + AH_WMAX)), so a
+// position costs its two tests only.
 struct FiltPos {
     int d;           // offset from the clamp site
     unsigned code;   // IUPAC set (bit b = base b)
@@ -218,7 +226,9 @@ static unsigned pat_code(const DPat &P, int j) {
 
 static double set_frac(unsigned m) { return __builtin_popcount(m) / 4.0; }
 
-static FiltPlan plan_filter(const DPat &P) {
+#define AH_SHARED_REACH 12
+
+static FiltPlan plan_filter(const DPat &P, bool shared) {
     FiltPlan best;
     const int L = (int)(P.meta & 0xFFu), k = (int)((P.meta >> 8) & 0xFFu), W = (int)((P.meta >> 16) & 0xFFu);
     const int shift = (int)(P.meta >> 24);
@@ -250,6 +260,7 @@ static FiltPlan plan_filter(const DPat &P) {
             for (int t = 0; t < sz; t++) {
                 const FiltPos &fp = near[g + t * (k + 1)];
                 if (fp.d <= -32 || fp.d >= 32) ok = false;
+                if (shared && (fp.d < -AH_SHARED_REACH || fp.d >= AH_SHARED_REACH + AH_WMAX)) ok = false;
                 plan.groups[g].push_back(fp);
                 pg *= set_frac(fp.code);
             }
@@ -258,8 +269,10 @@ static FiltPlan plan_filter(const DPat &P) {
         if (!ok) break;
         if (p_any > 1.0) p_any = 1.0;
         // tests: 2 words per position; shifts: 4 funnel shifts per position,
-        // shared by the two patterns of a strand; one OR per group and word
-        const double cost = 2.0 * W + 2.0 * (k + 1) + 4.0 * need + kTile * p_clamp * p_any * kVerify + 6.0;
+        // shared by the two patterns of a strand (by every pattern of the
+        // strand when shared); one OR per group and word
+        const double per_pos = shared ? 2.0 : 4.0;
+        const double cost = 2.0 * W + 2.0 * (k + 1) + per_pos * need + kTile * p_clamp * p_any * kVerify + 6.0;
         if (cost < best_cost) {
             best_cost = cost;
             best = plan;
@@ -268,10 +281,25 @@ static FiltPlan plan_filter(const DPat &P) {
     return best;
 }
 
-static std::string set_test_chain(std::string acc, const std::vector<FiltPos> &pos, int word) {
-    for (const FiltPos &fp : pos)
-        acc = "ah_and_at<" + std::to_string(fp.code) + "u, " + std::to_string(fp.d) + ", " + std::to_string(word) +
-              ">(" + acc + ", B)";
+// Set tests of one pigeonhole group, word `word`: from the filter's own
+// shifted planes (offsets 0..kW-1), the shared planes of the pass (`offs`,
+// when not null), or shifts of the base words.
+static std::string set_test_chain(std::string acc, const std::vector<FiltPos> &pos, int word, int kW,
+                                  const std::vector<int> *offs) {
+    const std::string Ws = std::to_string(word);
+    for (const FiltPos &fp : pos) {
+        const std::string M = std::to_string(fp.code) + "u";
+        if (fp.d >= 0 && fp.d < kW) {
+            const std::string I = std::to_string(fp.d);
+            acc = "ah_and_set<" + M + ">(" + acc + ", Sh[" + I + "][" + Ws + "], Sl[" + I + "][" + Ws + "])";
+        } else if (offs) {
+            const int i = (int)(std::find(offs->begin(), offs->end(), fp.d) - offs->begin());
+            const std::string I = std::to_string(i);
+            acc = "ah_and_set<" + M + ">(" + acc + ", Ph[" + I + "][" + Ws + "], Pl[" + I + "][" + Ws + "])";
+        } else {
+            acc = "ah_and_at<" + M + ", " + std::to_string(fp.d) + ", " + Ws + ">(" + acc + ", B)";
+        }
+    }
     return acc;
 }
 
@@ -280,52 +308,107 @@ static std::string set_test_chain(std::string acc, const std::vector<FiltPos> &p
 static std::string jit_source(const ah_primer_set_ *ps, uint32_t bpl, uint32_t hcap) {
     std::string s;
     const int nw = AH_HW;  // words per plane of the block the filter sees
+    const int kW = ps->max_W > 0 ? ps->max_W : 1;
+    // many pairs: each strand's shifted planes formed once per block
+    const bool shared = ps->n_pairs > 1;
     std::vector<FiltPlan> plans(ps->n_pats);
     bool any_groups = false;
+    std::vector<int> offs[2];  // shared offsets of the plus (x = 0, 1) and minus (x = 2, 3) patterns
     for (uint32_t X = 0; X < ps->n_pats; X++) {
-        plans[X] = plan_filter(ps->h_pats[X]);
+        plans[X] = plan_filter(ps->h_pats[X], shared);
         any_groups = any_groups || plans[X].n_groups > 0;
+        for (int q = 0; q < plans[X].n_groups; q++)
+            for (const FiltPos &fp : plans[X].groups[q]) {
+                std::vector<int> &o = offs[(X & 3u) >> 1];
+                if ((fp.d < 0 || fp.d >= kW) && std::find(o.begin(), o.end(), fp.d) == o.end()) o.push_back(fp.d);
+            }
     }
+    const bool halves = shared && any_groups;
+    const size_t n_sh = std::max(offs[0].size(), offs[1].size());
     s += "#define AH_BPL " + std::to_string(bpl) + "\n";
     s += "#define AH_HCAP " + std::to_string(hcap) + "\n";
     s += "#include \"scan_core.h\"\n";
     s += std::string("#define AH_JIT_USES_BASE ") + (any_groups ? "true" : "false") + "\n";
     s += "struct JitFilter {\n";
     s += "  static constexpr bool kUsesBase = AH_JIT_USES_BASE;\n";
-    s += "  static constexpr int kW = " + std::to_string(ps->max_W > 0 ? ps->max_W : 1) + ";\n";
+    s += "  static constexpr int kW = " + std::to_string(kW) + ";\n";
     s += std::string("  static constexpr bool kHoistGuard = ") + (ps->n_pairs > 1 ? "true" : "false") + ";\n";
     s += std::string("  static constexpr bool kSkipEmpty = ") + (ps->n_pairs > 1 ? "true" : "false") + ";\n";
+    // with shared planes, four groups per filter call: one dispatch on the
+    // group index per four groups
+    const uint32_t gstep = halves ? 4u : 1u;
+    s += std::string("  static constexpr int kHalves = ") + (halves ? "2" : "1") + ";\n";
+    s += "  static constexpr int kGroupStep = " + std::to_string(gstep) + ";\n";
+    // the shared planes of the current pass: Ph/Pl[i][w] = word w of the
+    // plane shifted by the pass's i-th offset
+    s += "  static constexpr int kNP = " + std::to_string(halves && n_sh ? n_sh : 1) + ";\n";
+    s += "  uint32_t Ph[kNP][AH_HW], Pl[kNP][AH_HW];\n";
+    s += "  __device__ __forceinline__ void block(const AhBase &B, int half) {\n";
+    if (halves) {
+        for (int h = 0; h < 2; h++) {
+            s += std::string(h ? "    else {\n" : "    if (half == 0) {\n");
+            for (size_t i = 0; i < offs[h].size(); i++)
+                for (int w = 0; w < nw; w++) {
+                    const std::string tgt = "[" + std::to_string(i) + "][" + std::to_string(w) + "]";
+                    const std::string tp = "<" + std::to_string(offs[h][i]) + ", " + std::to_string(w) + ">";
+                    s += "      Ph" + tgt + " = ah_shw" + tp + "(B.h);\n";
+                    s += "      Pl" + tgt + " = ah_shw" + tp + "(B.l);\n";
+                }
+            s += "    }\n";
+        }
+    }
+    s += "  }\n";
+    s += "  __device__ __forceinline__ void guard() {\n";
+    if (halves && n_sh)
+        s += "#pragma unroll\n    for (int i = 0; i < kNP; i++)\n#pragma unroll\n"
+             "      for (int w = 0; w < AH_HW; w++) asm volatile(\"\" : \"+v\"(Ph[i][w]), \"+v\"(Pl[i][w]));\n";
+    s += "  }\n";
     s += "  __device__ uint32_t groups(const ScanArgs &) const { return " + std::to_string(ps->n_pairs) + "u; }\n";
-    s += "  __device__ __forceinline__ void filter(uint32_t g, const AhBase &B, const uint32_t (&Sh)[AH_WMAX][AH_HW], "
-         "const uint32_t (&Sl)[AH_WMAX][AH_HW], uint32_t (&C)[4 * AH_HW]) const {\n";
+    s += "  __device__ __forceinline__ void filter(uint32_t g, int half, const AhBase &B, "
+         "const uint32_t (&Sh)[AH_WMAX][AH_HW], const uint32_t (&Sl)[AH_WMAX][AH_HW], "
+         "uint32_t (&C)[kGroupStep * 4 / kHalves * AH_HW]) const {\n";
     s += "    switch (g) {\n";
-    for (uint32_t g = 0; g < ps->n_pairs; g++) {
-        s += "    case " + std::to_string(g) + "u: {\n";
-        for (int x = 0; x < 4; x++) {
-            const DPat &P = ps->h_pats[4 * g + x];
-            const uint32_t W = (P.meta >> 16) & 0xFFu;
-            const FiltPlan &plan = plans[4 * g + x];
-            for (int w = 0; w < nw; w++) {
-                const std::string Ws = std::to_string(w);
-                std::string c = "0xFFFFFFFFu";
-                for (uint32_t i = 0; i < W; i++) {
-                    const unsigned m = P.fcode[i];
-                    if (m == 15) continue;  // N matches every base
-                    const std::string I = std::to_string(i), M = std::to_string(m);
-                    c = "ah_and_set<" + M + "u>(" + c + ", Sh[" + I + "][" + Ws + "], Sl[" + I + "][" + Ws + "])";
+    for (uint32_t g0 = 0; g0 < ps->n_pairs; g0 += gstep) {
+        s += "    case " + std::to_string(g0) + "u: {\n";
+        for (int h = 0; h < (halves ? 2 : 1); h++) {
+            if (halves) s += std::string(h ? "      } else {\n" : "      if (half == 0) {\n");
+            const int x0 = halves ? 2 * h : 0, nx = halves ? 2 : 4;
+            for (uint32_t gi = 0; gi < gstep; gi++)
+            for (int xi = 0; xi < nx; xi++) {
+                const uint32_t g = g0 + gi;
+                const int slot = (int)(gi * nx + xi) * nw;  // first word of (group, pattern) in C
+                if (g >= ps->n_pairs) {
+                    for (int w = 0; w < nw; w++) s += "      C[" + std::to_string(slot + w) + "] = 0u;\n";
+                    continue;
                 }
-                if (plan.n_groups) {
-                    std::string any;
-                    for (int q = 0; q < plan.n_groups; q++)
-                        any += (q ? " | " : "") + set_test_chain("0xFFFFFFFFu", plan.groups[q], w);
-                    c = "(" + c + ") & (" + any + ")";
+                const int x = x0 + xi;
+                const DPat &P = ps->h_pats[4 * g + x];
+                const uint32_t W = (P.meta >> 16) & 0xFFu;
+                const FiltPlan &plan = plans[4 * g + x];
+                for (int w = 0; w < nw; w++) {
+                    const std::string Ws = std::to_string(w);
+                    std::string c = "0xFFFFFFFFu";
+                    for (uint32_t i = 0; i < W; i++) {
+                        const unsigned m = P.fcode[i];
+                        if (m == 15) continue;  // N matches every base
+                        const std::string I = std::to_string(i), M = std::to_string(m);
+                        c = "ah_and_set<" + M + "u>(" + c + ", Sh[" + I + "][" + Ws + "], Sl[" + I + "][" + Ws + "])";
+                    }
+                    if (plan.n_groups) {
+                        std::string any;
+                        for (int q = 0; q < plan.n_groups; q++)
+                            any += (q ? " | " : "") +
+                                   set_test_chain("0xFFFFFFFFu", plan.groups[q], w, kW, halves ? &offs[h] : nullptr);
+                        c = "(" + c + ") & (" + any + ")";
+                    }
+                    s += "      C[" + std::to_string(slot + w) + "] = " + c + ";\n";
                 }
-                s += "      C[" + std::to_string(nw * x + w) + "] = " + c + ";\n";
             }
         }
+        if (halves) s += "      }\n";
         s += "      break; }\n";
     }
-    s += "    default: for (int w = 0; w < 4 * AH_HW; w++) C[w] = 0u;\n";
+    s += "    default: for (int w = 0; w < kGroupStep * 4 / kHalves * AH_HW; w++) C[w] = 0u;\n";
     s += "    }\n  }\n};\n";
     const uint32_t n_lds = ps->n_pats < AH_LDS_PATS ? ps->n_pats : AH_LDS_PATS;
     s += "#define AH_JIT_LDS_PATS " + std::to_string(n_lds) + "u\n";
@@ -371,8 +454,10 @@ static ah_status jit_compile(const ah_primer_set_ *ps, const std::string &arch, 
                             kJitHeaderNames) != HIPRTC_SUCCESS)
         return AH_E_HIP;
     const std::string arch_opt = "--offload-arch=" + arch;
-    const char *opts[] = {arch_opt.c_str(), "-O3", "-std=c++17", "-ffp-contract=off"};
-    if (hiprtcCompileProgram(prog, 4, opts) != HIPRTC_SUCCESS) {
+    // no packed-FP32 instructions, as for the library itself
+    const char *opts[] = {arch_opt.c_str(), "-O3", "-std=c++17", "-ffp-contract=off",
+                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    if (hiprtcCompileProgram(prog, 8, opts) != HIPRTC_SUCCESS) {
         size_t n = 0;
         hiprtcGetProgramLogSize(prog, &n);
         std::vector<char> log(n + 1, 0);

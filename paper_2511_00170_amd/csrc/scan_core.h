@@ -452,47 +452,68 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
                 Sl[i][w] = ah_funnel(B.l[w + 2], B.l[w + 1], i);
             }
         }
-        for (uint32_t g = 0; g < groups; g++) {
-            if (g < 64 && !((cur.gm >> g) & 1ull)) continue;  // group not asked for on this sequence
-            // Mark the shifted planes as redefined in every iteration (an
-            // empty asm, no instruction): otherwise, with compile-time codes,
-            // the compiler hoists every group's set tests out of this loop as
-            // invariants and runs out of registers once there are many groups.
-            if (F::kHoistGuard) {
+        // kHalves = 2: the plus-strand patterns of every group (x = 0, 1),
+        // then the minus-strand ones (x = 2, 3), each pass with the filter's
+        // own shifted planes for that strand, shared by all groups
+        constexpr int kX = 4 / F::kHalves;  // patterns per group and pass
+        constexpr int kG = F::kGroupStep;   // groups per filter call
+        for (int half = 0; half < F::kHalves; half++) {
+            f.block(B, half);
+            for (uint32_t g0 = 0; g0 < groups; g0 += kG) {
+                // groups asked for on this sequence (all past the first 64)
+                const uint32_t req =
+                    g0 < 64 ? (uint32_t)(cur.gm >> g0) & ((1u << kG) - 1u) : (1u << kG) - 1u;
+                if (!req) continue;
+                // Mark the shifted planes as redefined in every iteration (an
+                // empty asm, no instruction): otherwise, with compile-time
+                // codes, the compiler hoists every group's set tests out of
+                // this loop as invariants and runs out of registers once there
+                // are many groups.
+                if (F::kHoistGuard) {
 #pragma unroll
-                for (int i = 0; i < F::kW; i++)
+                    for (int i = 0; i < F::kW; i++)
 #pragma unroll
-                    for (int w = 0; w < AH_HW; w++) asm volatile("" : "+v"(Sh[i][w]), "+v"(Sl[i][w]));
-                if (F::kUsesBase) {
+                        for (int w = 0; w < AH_HW; w++) asm volatile("" : "+v"(Sh[i][w]), "+v"(Sl[i][w]));
+                    if (F::kUsesBase) {
 #pragma unroll
-                    for (int w = 0; w < AH_HW + 2; w++) asm volatile("" : "+v"(B.h[w]), "+v"(B.l[w]));
+                        for (int w = 0; w < AH_HW + 2; w++) asm volatile("" : "+v"(B.h[w]), "+v"(B.l[w]));
+                    }
+                    f.guard();
                 }
-            }
-            uint32_t C[4 * AH_HW];  // C[AH_HW * x + w]: clamp sites of word w, pattern x
-            f.filter(g, B, Sh, Sl, C);
-            if (F::kSkipEmpty) {  // many groups: most have no candidate in a block
-                uint32_t any = 0;
+                // C[(kX * gi + xi) * AH_HW + w]: clamp sites of word w, group
+                // g0 + gi, pattern kX * half + xi
+                uint32_t C[kG * kX * AH_HW];
+                f.filter(g0, half, B, Sh, Sl, C);
+                if (F::kSkipEmpty) {  // many groups: most have no candidate in a block
+                    uint32_t any = 0;
 #pragma unroll
-                for (int j = 0; j < 4 * AH_HW; j++) any |= C[j];
-                if (__ballot(any != 0) == 0) continue;
-            }
-            // room for this group's entries (at most 4 x 64); a non-draining
-            // flush leaves fewer than 64
-            if (qn > AH_QCAP - 256) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, rctx, sQ, qn, sW, hb, false);
-#pragma unroll
-            for (int x = 0; x < 4; x++) {
-                uint32_t nzw = 0;
-#pragma unroll
-                for (int w = 0; w < AH_HW; w++) nzw |= C[AH_HW * x + w];
-                const bool nz = nzw != 0;
-                const uint64_t bal = __ballot(nz);
-                if (nz) {
-                    const uint32_t slot = qn + ah_mbcnt(bal);
-#pragma unroll
-                    for (int w = 0; w < AH_HW; w++) sQ[slot][w] = C[AH_HW * x + w];
-                    sQ[slot][AH_HW] = ((4 * g + (uint32_t)x) << 9) | ((uint32_t)blk << 8) | (ci << 6) | lane;
+                    for (int j = 0; j < kG * kX * AH_HW; j++) any |= C[j];
+                    if (__ballot(any != 0) == 0) continue;
                 }
-                qn = ah_uni(qn + (uint32_t)__popcll(bal));  // keeps the queue count in a scalar register
+#pragma unroll
+                for (int gi = 0; gi < kG; gi++) {
+                    if (!((req >> gi) & 1u)) continue;
+                    const uint32_t g = g0 + (uint32_t)gi;
+                    // room for this group's entries (at most kX x 64); a
+                    // non-draining flush leaves fewer than 64
+                    if (qn > AH_QCAP - 64 * kX) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, rctx, sQ, qn, sW, hb, false);
+#pragma unroll
+                    for (int xi = 0; xi < kX; xi++) {
+                        uint32_t nzw = 0;
+#pragma unroll
+                        for (int w = 0; w < AH_HW; w++) nzw |= C[(kX * gi + xi) * AH_HW + w];
+                        const bool nz = nzw != 0;
+                        const uint64_t bal = __ballot(nz);
+                        if (nz) {
+                            const uint32_t slot = qn + ah_mbcnt(bal);
+                            const uint32_t x = (uint32_t)(kX * half + xi);
+#pragma unroll
+                            for (int w = 0; w < AH_HW; w++) sQ[slot][w] = C[(kX * gi + xi) * AH_HW + w];
+                            sQ[slot][AH_HW] = ((4 * g + x) << 9) | ((uint32_t)blk << 8) | (ci << 6) | lane;
+                        }
+                        qn = ah_uni(qn + (uint32_t)__popcll(bal));  // keeps the queue count in a scalar register
+                    }
+                }
             }
         }
     }
@@ -501,11 +522,19 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
 
 // The kernel body.  Filter F provides
 //   f.groups(a)                         number of pattern groups (primer pairs),
-//   f.filter(g, B, Sh, Sl, C)           candidate words of group g in one block
-//                                       (C[AH_HW*x + w]: clamp sites 32w..32w+31
-//                                       of the block, pattern x); a
-//                                       candidate must pass a necessary condition
-//                                       of a hit; verification decides.
+//   f.block(B, half), f.guard()         per-block state of pass `half` (shifted
+//                                       planes shared by every group) and its
+//                                       hoist guard,
+//   f.filter(g0, half, B, Sh, Sl, C)    candidate words of groups g0.. in one block
+//                                       (C[AH_HW*xi + w]: clamp sites 32w..32w+31
+//                                       of the block, pattern 4/kHalves*half + xi);
+//                                       a candidate must pass a necessary
+//                                       condition of a hit; verification decides.
+//   F::kHalves                          passes per block: 1 (all four patterns of
+//                                       a group at once) or 2 (plus, then minus),
+//   F::kGroupStep                       groups per filter call (C holds kGroupStep
+//                                       groups' words, group after group; groups
+//                                       past the last give zero words),
 //   F::kUsesBase                        whether filter reads the base words B,
 //   F::kW                               shifted planes it reads (offsets 0 .. kW-1),
 //   F::kHoistGuard                      its codes are compile-time and there are
