@@ -419,7 +419,12 @@ def bench_batch(args, wl, store, sample):
                      "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tlane-ops/s",
                      "frac": valu["frac"] if valu else None,
                      "traffic": prof.get("hbm_bytes_per_launch") if prof else None, "kernel": kern,
-                     "kernel_ms": round(scan_ms, 4), "valu_insts_per_launch": valu["insts_per_launch"] if valu else None,
+                     "kernel_ms": round(scan_ms, 4),
+                     "trace_kernel_ms": round(prof["trace_timed_avg_us"] / 1e3, 4)
+                     if prof and prof.get("trace_timed_avg_us") else None,
+                     "valu_insts_per_launch": valu["insts_per_launch"] if valu else None,
+                     "valu_lane_ops_per_pair_base": round(valu["insts_per_launch"] * 64 / (npairs * total), 3)
+                     if valu else None,
                      "algorithmic_bytes_per_launch": int(alg_bytes), "hbm_achieved_GB_s": round(achieved, 1),
                      "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)},
         "cpu_baseline": cpu_baseline(wl, sample, ex, "pair-Gbases/s"),

@@ -414,8 +414,12 @@ static std::string jit_source(const ah_primer_set_ *ps, uint32_t bpl, uint32_t h
     s += "#define AH_JIT_LDS_PATS " + std::to_string(n_lds) + "u\n";
     s += std::string("#define AH_JIT_LDS_ONLY ") + (ps->n_pats <= AH_LDS_PATS ? "true" : "false") + "\n";
     // two-block tiles for a few pairs: bound the registers to six waves per
-    // SIMD (80 VGPRs, no spills), the count the LDS allows
-    const std::string bounds = (bpl == 2 && ps->n_pairs <= 4) ? "__launch_bounds__(256, 6)" : "__launch_bounds__(256)";
+    // SIMD (80 VGPRs, no spills), the count the LDS allows; with shared
+    // strand planes, to three (168 VGPRs), so that both tile sizes keep three
+    // workgroups per CU
+    const std::string bounds = (bpl == 2 && ps->n_pairs <= 4) ? "__launch_bounds__(256, 6)"
+                               : halves                       ? "__launch_bounds__(256, 3)"
+                                                              : "__launch_bounds__(256)";
     s += "extern \"C\" __global__ void " + bounds + " ah_scan_jit(ScanArgs a) {\n"
          "  __shared__ DPat sPat[AH_JIT_LDS_PATS];\n"
          "  __shared__ TileCtx sCtx[4][AH_NCTX];\n"
