@@ -305,7 +305,11 @@ def bench_sweep(args, wl, store):
                 pipe.run(stream)
                 n_hits, n_amps, n_bytes = pipe.counts()
                 n_pass = int(pipe.passed[:n_amps].sum().item())
-                pipe.launch(stream)
+                t_w = time.perf_counter()
+                while time.perf_counter() - t_w < args.warmup_s:  # clocks settle under load
+                    for _ in range(8):
+                        pipe.launch(stream)
+                    stream.synchronize()
                 torch.cuda.synchronize()
                 ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
                       for _ in range(args.steps)]
