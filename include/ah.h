@@ -501,6 +501,54 @@ ah_status ah_fasta_format(const ah_fasta_names *names, uint32_t fb_len, uint32_t
                           const char *h_fprimer, const char *h_rprimer, char *h_out, uint64_t out_cap,
                           uint64_t *h_n_bytes);
 
+/* ------------------------------------------------------------------------
+ * FASTQ input and output with quality propagation (Discussion: FASTQ input
+ * with qualities carried to the amplicons, for amplicon sequencing data; the
+ * Python AHv1.1 reads FASTQ).  A record is four lines: "@" and a header whose
+ * first white-space-separated word is the identifier; the bases (bytes
+ * '!'..'~'; other than A/C/G/T in either case they read as N); a line
+ * starting with "+" (the rest of it ignored); the qualities, one byte in
+ * '!'..'~' per base.  Lines end in LF or CR LF; empty lines between records
+ * are skipped; anything else is AH_E_FORMAT, as are records of 2^32 or more
+ * bases (records wrapped over several lines are not read).
+ *
+ * ah_fastq_read parses the files on the host into a record table of the
+ * FASTA type (ah_fasta_info, ah_fasta_table, ah_fasta_names_of and
+ * ah_fasta_free apply; the store layout is ah_pack_layout's) that also keeps
+ * the bases and qualities.  ah_fastq_bases gives the bases back to back with
+ * [n_records + 1] offsets (host memory owned by the table, valid until
+ * ah_fasta_free) for ah_pack.  ah_fastq_qual_layout writes the qualities
+ * laid out like the store's bases: record r's base j at byte
+ * 64 * block0[r] + j of h_qual (cap >= 64 * n_blocks bytes, else
+ * AH_E_LIMIT; every other byte 0).  Errors: AH_E_ARG (also: a table not read
+ * from FASTQ), AH_E_IO, AH_E_FORMAT; *out is set only on success.
+ * ---------------------------------------------------------------------- */
+ah_status ah_fastq_read(const char *const *paths, uint32_t n_files, ah_fasta **out);
+ah_status ah_fastq_bases(const ah_fasta *f, const char **h_bases, const uint64_t **h_off);
+ah_status ah_fastq_qual_layout(const ah_fasta *f, uint8_t *h_qual, uint64_t cap);
+
+/* Quality bytes of the amplicons ah_extract wrote, from the same amplicons,
+ * pass flags, options and offsets (d_seq_off): for each written amplicon the
+ * qualities of its bases in the order ah_extract wrote them -- forward, or
+ * reversed for RF, whose bases are reverse-complemented -- at d_out +
+ * d_seq_off[i].  d_qual: the device copy of ah_fastq_qual_layout's array
+ * (qual_len >= 64 * st->n_blocks bytes).  Bytes at or past out_cap are not
+ * written.  Asynchronous on stream; allocates nothing; AH_E_ARG for missing
+ * arrays or a short d_qual. */
+ah_status ah_extract_qual(const ah_store *st, const uint8_t *d_qual, uint64_t qual_len, ah_primer_set ps,
+                          const ah_amp *d_amps, const uint64_t *d_n_amps, uint64_t amp_cap, const uint8_t *d_pass,
+                          const ah_extract_opts *o, const uint64_t *d_seq_off, uint8_t *d_out, uint64_t out_cap,
+                          void *stream);
+
+/* FASTQ output: the records of ah_fasta_format with "@" in place of ">" and,
+ * after the bases, a "+" line and the amplicon's qualities (h_qual at the
+ * offsets of h_seq).  Same arguments and errors as ah_fasta_format. */
+ah_status ah_fastq_format(const ah_fasta_names *names, uint32_t fb_len, uint32_t rb_len, const ah_amp *h_amps,
+                          uint64_t n_amps, const double *h_tm, const uint8_t *h_pass, const char *h_seq,
+                          const uint64_t *h_seq_off, const char *h_qual, const char *h_fb, const char *h_rb,
+                          const uint8_t *h_bc_len, const char *h_fprimer, const char *h_rprimer, char *h_out,
+                          uint64_t out_cap, uint64_t *h_n_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -96,6 +96,11 @@ _sig("ah_fasta_names_of", I32, VP, C.POINTER(ah_fasta_names))
 _sig("ah_fasta_free", None, VP)
 _sig("ah_fasta_format", I32, C.POINTER(ah_fasta_names), U32, U32, VP, U64, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP,
      U64, C.POINTER(U64))
+_sig("ah_fastq_read", I32, C.POINTER(C.c_char_p), U32, C.POINTER(VP))
+_sig("ah_fastq_bases", I32, VP, C.POINTER(VP), C.POINTER(VP))
+_sig("ah_fastq_qual_layout", I32, VP, VP, U64)
+_sig("ah_fastq_format", I32, C.POINTER(ah_fasta_names), U32, U32, VP, U64, VP, VP, VP, VP, VP, VP, VP, VP, VP, VP,
+     VP, U64, C.POINTER(U64))
 _sig("ah_primers_compile", I32, C.POINTER(ah_pair_spec), U32, C.POINTER(VP))
 _sig("ah_primers_free", None, VP)
 _sig("ah_primers_compile_into", I32, C.POINTER(ah_pair_spec), U32, VP, U64, VP, C.POINTER(VP))
@@ -118,6 +123,8 @@ _sig("ah_tm_duplex", I32, VP, VP, VP, VP, VP, U32, U32, C.POINTER(ah_tm_params),
 _sig("ah_extract_ws_size", I32, U64, C.POINTER(U64))
 _sig("ah_extract", I32, C.POINTER(ah_store), VP, VP, VP, U64, VP, C.POINTER(ah_extract_opts), VP, U64, VP, VP, VP,
      VP, VP, VP, VP, VP, U64, VP)
+_sig("ah_extract_qual", I32, C.POINTER(ah_store), VP, U64, VP, VP, VP, U64, VP, C.POINTER(ah_extract_opts), VP, VP,
+     U64, VP)
 
 EXPORTED = ["ah_status_str", "ah_version", "ah_pack_layout", "ah_pack_begin", "ah_pack", "ah_pack_finish",
             "ah_unpack", "ah_primers_compile", "ah_primers_compile_into", "ah_primers_table_bytes", "ah_primers_free", "ah_primers_count", "ah_primers_jit", "ah_primers_jit_check", "ah_primers_jit_variant", "ah_primers_use_jit",
@@ -125,6 +132,7 @@ EXPORTED = ["ah_status_str", "ah_version", "ah_pack_layout", "ah_pack_begin", "a
             "ah_scan_primers", "ah_scan_primers_static", "ah_scan_primers_masked", "ah_route_hits", "ah_pair_ws_size", "ah_pair_amplicons", "ah_tm_nn", "ah_tm_duplex",
             "ah_extract_ws_size", "ah_extract", "ah_pack_pieces", "ah_fasta_ws_size", "ah_fasta_ingest",
             "ah_fasta_info", "ah_fasta_table", "ah_fasta_names_of", "ah_fasta_free", "ah_fasta_format",
+            "ah_fastq_read", "ah_fastq_bases", "ah_fastq_qual_layout", "ah_extract_qual", "ah_fastq_format",
             "ah_read_probe"]
 
 HIT_DTYPE = np.dtype([("seq", "<u4"), ("pos", "<u4"), ("pair", "<u2"), ("kind", "u1"), ("mm", "u1")])
@@ -298,6 +306,22 @@ class Store:
         st.fasta = tab
         return st
 
+    @classmethod
+    def from_fastq(cls, paths: Sequence[str], nmask_cap: int = 1 << 16):
+        """Read FASTQ files into a new store (ah_fastq_read, then ah_pack):
+        the record table is ``store.fasta`` and the qualities, laid out like
+        the bases (record r's base j at byte 64 * block0[r] + j), are the
+        device array ``store.qual``."""
+        tab, bases, off, qual = read_fastq(paths)
+        st = cls(tab.lengths.astype(np.uint64), nmask_cap=nmask_cap)
+        if st.n_blocks != tab.n_blocks or not np.array_equal(st.seq_block0_host, tab.block0):
+            raise AhError(AH_E_ARG, "ah_fastq_read: record layout differs from ah_pack_layout")
+        if tab.n_records:
+            st.pack_chunks([(0, bases if len(bases) else np.zeros(1, np.uint8), off)])
+        st.qual = torch.from_numpy(qual).to(st.blocks.device)
+        st.fasta = tab
+        return st
+
     def unpack(self, seq: int, start: int = 0, n: Optional[int] = None) -> bytes:
         n = int(self.lengths[seq]) - start if n is None else n
         out = torch.zeros(max(n, 1), dtype=torch.uint8, device=self.blocks.device)
@@ -349,7 +373,7 @@ class FastaTable:
         return [arr[i] for i in range(self.names.n_files)]
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:  # (module globals are gone at interpreter exit)
             _lib.ah_fasta_free(self._h)
             self._h = None
 
@@ -410,6 +434,55 @@ def format_fasta(names, res: dict, fb_len: int, rb_len: int, tm_filter: bool = T
     check(_lib.ah_fasta_format(*args, None, 0, C.byref(need)), "ah_fasta_format")
     out = C.create_string_buffer(max(int(need.value), 1))
     check(_lib.ah_fasta_format(*args, out, int(need.value), C.byref(need)), "ah_fasta_format")
+    return out.raw[:int(need.value)]
+
+
+def read_fastq(paths: Sequence[str]):
+    """Parse FASTQ files on the host (ah_fastq_read; no GPU): the record table,
+    the bases back to back with their offsets, and the qualities laid out
+    like the store's bases (64 * n_blocks bytes)."""
+    paths = [os.fspath(p) for p in paths]
+    arr = (C.c_char_p * max(1, len(paths)))(*[os.fsencode(p) for p in paths])
+    h = VP()
+    check(_lib.ah_fastq_read(arr, len(paths), C.byref(h)), "ah_fastq_read")
+    tab = FastaTable(h)
+    bp, op = VP(), VP()
+    check(_lib.ah_fastq_bases(h, C.byref(bp), C.byref(op)), "ah_fastq_bases")
+    off = np.ctypeslib.as_array(C.cast(op, C.POINTER(U64)), (tab.n_records + 1,)).copy()
+    total = int(off[-1])
+    bases = np.ctypeslib.as_array(C.cast(bp, C.POINTER(C.c_uint8)), (total,)).copy() if total else \
+        np.zeros(0, np.uint8)
+    qual = np.empty(max(64 * tab.n_blocks, 1), np.uint8)
+    check(_lib.ah_fastq_qual_layout(h, qual.ctypes.data_as(VP), qual.size), "ah_fastq_qual_layout")
+    return tab, bases, off, qual
+
+
+def format_fastq(names, res: dict, fb_len: int, rb_len: int, tm_filter: bool = True) -> bytes:
+    """FASTQ text of a run over a FASTQ store (``Pipeline.results()`` with
+    ``qual``): the records of format_fasta with "@" headers, then "+" and the
+    amplicon's qualities."""
+    amps = np.ascontiguousarray(res["amps"])
+    n = len(amps)
+    tm = np.ascontiguousarray(res["tm"], np.float64)
+    pas = np.ascontiguousarray(res["pass"], np.uint8) if tm_filter else None
+    seq_buf = np.frombuffer(res["seq"], np.uint8) if len(res["seq"]) else np.zeros(1, np.uint8)
+    qual_buf = np.frombuffer(res["qual"], np.uint8) if len(res["qual"]) else np.zeros(1, np.uint8)
+    so = np.ascontiguousarray(res["seq_off"], np.uint64)
+    fb = np.ascontiguousarray(res["fb"], np.uint8) if fb_len else np.zeros(1, np.uint8)
+    rb = np.ascontiguousarray(res["rb"], np.uint8) if rb_len else np.zeros(1, np.uint8)
+    bc = np.ascontiguousarray(res["bc_len"], np.uint8)
+    fp = np.ascontiguousarray(res["fprimer"], np.uint8)
+    rp = np.ascontiguousarray(res["rprimer"], np.uint8)
+
+    def ptr(a):
+        return a.ctypes.data_as(VP)
+    args = (C.byref(names.names), fb_len, rb_len, ptr(amps) if n else None, n, ptr(tm) if n else None,
+            ptr(pas) if pas is not None and n else None, ptr(seq_buf), ptr(so), ptr(qual_buf), ptr(fb), ptr(rb),
+            ptr(bc) if n else None, ptr(fp) if n else None, ptr(rp) if n else None)
+    need = U64(0)
+    check(_lib.ah_fastq_format(*args, None, 0, C.byref(need)), "ah_fastq_format")
+    out = C.create_string_buffer(max(int(need.value), 1))
+    check(_lib.ah_fastq_format(*args, out, int(need.value), C.byref(need)), "ah_fastq_format")
     return out.raw[:int(need.value)]
 
 
@@ -600,6 +673,13 @@ def extract(store, ps, amps, n_amps, amp_cap, passed, opts: ah_extract_opts, seq
                           ws.numel() * ws.element_size(), _stream(stream)), "ah_extract")
 
 
+def extract_qual(store, ps, amps, n_amps, amp_cap, passed, opts: ah_extract_opts, seq_off, out, out_cap,
+                 stream=None):
+    check(_lib.ah_extract_qual(C.byref(store.c), _p(store.qual), store.qual.numel(), ps.h, _p(amps), _p(n_amps),
+                               amp_cap, _p(passed), C.byref(opts), _p(seq_off), _p(out), out_cap, _stream(stream)),
+          "ah_extract_qual")
+
+
 def tm_duplex(seqs: Sequence[str], cseqs: Sequence[str], tm, shifts: Optional[Sequence[int]] = None) -> np.ndarray:
     """Tm of explicit duplexes on the GPU (seq 5'->3', cseq its partner 3'->5',
     cseq[j] facing seq[j - shift]; lengths may differ)."""
@@ -680,6 +760,8 @@ class Pipeline:
             self.bc_len = torch.empty((caps.amps, 2), dtype=torch.uint8, device=d)
             self.fpr = torch.empty((caps.amps, 32), dtype=torch.uint8, device=d)
             self.rpr = torch.empty((caps.amps, 32), dtype=torch.uint8, device=d)
+            if getattr(self.store, "qual", None) is not None:  # FASTQ input: qualities beside the bases
+                self.qual = torch.empty(max(caps.seq_bytes, 1), dtype=torch.uint8, device=d)
 
     def launch(self, stream=None, stages=("scan", "pair", "tm", "extract")):
         c = self.counters
@@ -696,6 +778,10 @@ class Pipeline:
             extract(self.store, self.ps, self.amps, n_amps, self.caps.amps,
                     self.passed if self.tm_spec.filter else None, self.opts, self.seq, self.caps.seq_bytes,
                     self.seq_off, self.fb, self.rb, self.bc_len, self.fpr, self.rpr, n_bytes, self.ws, stream)
+            if getattr(self.store, "qual", None) is not None:
+                extract_qual(self.store, self.ps, self.amps, n_amps, self.caps.amps,
+                             self.passed if self.tm_spec.filter else None, self.opts, self.seq_off, self.qual,
+                             self.caps.seq_bytes, stream)
 
     def counts(self):
         torch.cuda.synchronize()
@@ -733,6 +819,8 @@ class Pipeline:
             out["bc_len"] = self.bc_len[:a].cpu().numpy()
             out["fprimer"] = self.fpr[:a].cpu().numpy()
             out["rprimer"] = self.rpr[:a].cpu().numpy()
+            if getattr(self.store, "qual", None) is not None:
+                out["qual"] = self.qual[:b].cpu().numpy().tobytes()
         return out
 
 

@@ -1,17 +1,20 @@
-"""Command line: FASTA genomes in, AHv2-format amplicon FASTA out.
+"""Command line: FASTA genomes in, AHv2-format amplicon FASTA out (or FASTQ
+reads in, amplicon FASTQ with their qualities out).
 
     python -m paper_2511_00170_amd.cli --input g1.fa g2.fa --forward F --reverse R \\
         --mismatches 3 --clamp 5 --min-length 200 --max-length 2000 \\
         [--include-offtarget] [--trim-primers] [--fb-len N] [--rb-len N] \\
-        [--tm-threshold 45] [--output amplicons.fa]
+        [--tm-threshold 45] [--input-fq] [--output amplicons.fa]
 
 The flags follow the tool's own (Supplementary, "Amplicon calling and
 orientation" and "Primer trimming and barcode extraction"): FR and RF
 amplicons by default, FF/RR too with --include-offtarget; --trim-primers
 removes the primer sites from the written sequence; --fb-len/--rb-len cut
-barcodes.  Every sequence and primer pair runs through the GPU path
-(ah_fasta_ingest, scan, pair, Tm, extract); the headers are written by
-ah_fasta_format.
+barcodes; --input-fq reads FASTQ and writes each amplicon with the
+qualities of its bases.  Every sequence and primer pair runs through the GPU
+path (ah_fasta_ingest or ah_fastq_read, scan, pair, Tm, extract, and
+ah_extract_qual for FASTQ); the records are written by ah_fasta_format or
+ah_fastq_format.
 """
 from __future__ import annotations
 
@@ -46,7 +49,9 @@ def parse_args(argv=None):
     ap.add_argument("--dnac1-nM", type=float, default=250.0, help="primer strand concentration")
     ap.add_argument("--dnac2-nM", type=float, default=0.0, help="template strand concentration")
     ap.add_argument("--saltcorr", type=int, default=5, help="salt correction method 0-7 (Tm_NN's numbering)")
-    ap.add_argument("--output", default="-", help="output FASTA ('-' = standard output)")
+    ap.add_argument("--input-fq", action="store_true",
+                    help="the inputs are FASTQ; write FASTQ with each amplicon's qualities")
+    ap.add_argument("--output", default="-", help="output FASTA or FASTQ ('-' = standard output)")
     ap.add_argument("--chunk-mb", type=int, default=64, help="staging chunk for FASTA ingest, MiB")
     ap.add_argument("--quiet", action="store_true")
     a = ap.parse_args(argv)
@@ -75,11 +80,15 @@ def main(argv=None) -> int:
                       filter=a.tm_threshold is not None)
     ex = synth.ExtractSpec(trim=a.trim_primers, fb_len=a.fb_len, rb_len=a.rb_len)
     orient = 0b1111 if a.include_offtarget else 0b0011
-    store = ah.Store.from_fasta(a.input, chunk_bytes=a.chunk_mb << 20)
+    if a.input_fq:
+        store = ah.Store.from_fastq(a.input)
+    else:
+        store = ah.Store.from_fasta(a.input, chunk_bytes=a.chunk_mb << 20)
     t1 = time.perf_counter()
     res = ah.Pipeline(store, ah.PrimerSet([pair], jit=True), orient, tm, ex).run().results()
     t2 = time.perf_counter()
-    text = ah.format_fasta(store.fasta, res, ex.fb_len, ex.rb_len, tm_filter=tm.filter)
+    fmt = ah.format_fastq if a.input_fq else ah.format_fasta
+    text = fmt(store.fasta, res, ex.fb_len, ex.rb_len, tm_filter=tm.filter)
     if a.output == "-":
         sys.stdout.buffer.write(text)
         sys.stdout.buffer.flush()
@@ -88,7 +97,7 @@ def main(argv=None) -> int:
             fh.write(text)
     t3 = time.perf_counter()
     if not a.quiet:
-        n_out = text.count(b"\n>") + (1 if text else 0)
+        n_out = res["pass"].astype(bool).sum() if tm.filter else len(res["amps"])
         print("%d files, %d sequences, %.3f Gbases; %d amplicons, %d written; ingest %.2f s, path %.2f s, "
               "write %.2f s" % (len(a.input), store.n_seqs, store.total_bases / 1e9, len(res["amps"]), n_out,
                                 t1 - t0, t2 - t1, t3 - t2), file=sys.stderr)

@@ -354,3 +354,48 @@ extern "C" ah_status ah_extract(const ah_store *st, ah_primer_set ps, ah_amp *d_
     }
     return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
 }
+
+// ---------------------------------------------------------------- qualities
+// Quality bytes of each written amplicon (FASTQ input): the qualities of the
+// bases ah_extract wrote for it, in the same order -- forward, or reversed
+// for RF, whose bases are reverse-complemented (a quality has no
+// complement) -- at the same offsets.  One wave per amplicon, consecutive
+// lanes on consecutive bytes.
+__global__ void __launch_bounds__(256) ah_extract_qual_kernel(const ah_store st, const uint8_t *qual,
+                                                              const uint32_t *amps, const uint64_t *d_n, uint64_t cap,
+                                                              const DPair *pairs, const uint8_t *pass, uint32_t trim,
+                                                              const uint64_t *seq_off, uint8_t *out,
+                                                              uint64_t out_cap) {
+    const uint64_t n = *d_n < cap ? *d_n : cap;
+    const uint32_t lane = ah_lane();
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t i = blockIdx.x * (uint64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); i < n; i += nw) {
+        if (pass && !pass[i]) continue;
+        const AmpGeom g = amp_geom(amps, i, pairs);
+        uint64_t a0, a1;
+        amp_span(g, trim, &a0, &a1);
+        const bool rc = g.orient == 1;
+        const uint8_t *q = qual + 64 * st.d_seq_block0[g.seq];
+        const uint64_t dst = seq_off[i], len = a1 - a0;
+        for (uint64_t j = lane; j < len; j += 64) {
+            if (dst + j >= out_cap) break;
+            out[dst + j] = q[rc ? a1 - 1 - j : a0 + j];
+        }
+    }
+}
+
+extern "C" ah_status ah_extract_qual(const ah_store *st, const uint8_t *d_qual, uint64_t qual_len, ah_primer_set ps,
+                                     const ah_amp *d_amps, const uint64_t *d_n_amps, uint64_t amp_cap,
+                                     const uint8_t *d_pass, const ah_extract_opts *o, const uint64_t *d_seq_off,
+                                     uint8_t *d_out, uint64_t out_cap, void *stream) {
+    if (!st || !ps || !o || !d_n_amps || (amp_cap && (!d_amps || !d_seq_off))) return AH_E_ARG;
+    if (!d_qual || qual_len < 64 * st->n_blocks || (out_cap && !d_out)) return AH_E_ARG;
+    if (!amp_cap) return AH_OK;
+    uint64_t wgs = (amp_cap + 3) / 4;  // one wave per amplicon, at most the resident grid
+    const uint64_t resident = ah_resident_wgs(ah_extract_qual_kernel, 256);
+    if (wgs > resident) wgs = resident;
+    hipLaunchKernelGGL(ah_extract_qual_kernel, dim3((unsigned)wgs), dim3(256), 0, ah_stream(stream), *st, d_qual,
+                       (const uint32_t *)d_amps, d_n_amps, amp_cap, (const DPair *)ps->d_pairs, d_pass, o->trim,
+                       d_seq_off, d_out, out_cap);
+    return hipGetLastError() == hipSuccess ? AH_OK : AH_E_HIP;
+}

@@ -32,18 +32,7 @@
 #include "ah.h"
 #include "ah_internal.h"
 
-struct ah_fasta {
-    std::vector<std::string> files;   // source names (path without directories)
-    std::vector<const char *> file_ptrs;
-    std::vector<uint32_t> len;
-    std::vector<uint64_t> block0;
-    std::vector<uint32_t> file;
-    std::vector<uint64_t> id_off;
-    std::string ids;                  // NUL-terminated identifiers, back to back
-    uint64_t n_bases = 0;
-    uint64_t n_blocks = 0;
-    uint32_t max_len = 0;
-};
+#include "fasta_table.h"
 
 namespace {
 
@@ -585,11 +574,13 @@ uint64_t strnlen32(const char *p) {
 
 }  // namespace
 
-extern "C" ah_status ah_fasta_format(const ah_fasta_names *nm, uint32_t fb_len, uint32_t rb_len, const ah_amp *h_amps,
-                                     uint64_t n_amps, const double *h_tm, const uint8_t *h_pass, const char *h_seq,
-                                     const uint64_t *h_seq_off, const char *h_fb, const char *h_rb,
-                                     const uint8_t *h_bc_len, const char *h_fprimer, const char *h_rprimer,
-                                     char *h_out, uint64_t out_cap, uint64_t *h_n_bytes) {
+// Records in FASTA (">" header, bases) or, with h_qual, FASTQ ("@" header,
+// bases, "+", qualities).
+static ah_status format_records(const ah_fasta_names *nm, uint32_t fb_len, uint32_t rb_len, const ah_amp *h_amps,
+                                uint64_t n_amps, const double *h_tm, const uint8_t *h_pass, const char *h_seq,
+                                const uint64_t *h_seq_off, const char *h_qual, const char *h_fb, const char *h_rb,
+                                const uint8_t *h_bc_len, const char *h_fprimer, const char *h_rprimer, char *h_out,
+                                uint64_t out_cap, uint64_t *h_n_bytes, bool fastq) {
     if (!nm || !h_n_bytes || (out_cap && !h_out)) return AH_E_ARG;
     if (n_amps && (!h_amps || !h_tm || !h_seq_off || !h_bc_len || !h_fprimer || !h_rprimer)) return AH_E_ARG;
     if (n_amps && (!nm->ids || !nm->id_off || !nm->seq_file || !nm->files)) return AH_E_ARG;
@@ -600,7 +591,7 @@ extern "C" ah_status ah_fasta_format(const ah_fasta_names *nm, uint32_t fb_len, 
         if (a.seq >= nm->n_seqs || nm->seq_file[a.seq] >= nm->n_files || a.orient > 3) return AH_E_ARG;
         if (h_seq_off[i + 1] < h_seq_off[i] || h_bc_len[2 * i] > fb_len || h_bc_len[2 * i + 1] > rb_len)
             return AH_E_ARG;
-        if (h_seq_off[i + 1] > h_seq_off[i] && !h_seq) return AH_E_ARG;
+        if (h_seq_off[i + 1] > h_seq_off[i] && (!h_seq || (fastq && !h_qual))) return AH_E_ARG;
     }
     static const char *kOrient[4] = {"FR", "RF", "FF", "RR"};
     Out o{h_out, out_cap};
@@ -608,7 +599,7 @@ extern "C" ah_status ah_fasta_format(const ah_fasta_names *nm, uint32_t fb_len, 
     for (uint64_t i = 0; i < n_amps; i++) {
         if (h_pass && !h_pass[i]) continue;
         const ah_amp &a = h_amps[i];
-        o.put(">");
+        o.put(fastq ? "@" : ">");
         o.put(nm->ids + nm->id_off[a.seq]);
         o.put(".source=");
         o.put(nm->files[nm->seq_file[a.seq]]);
@@ -638,7 +629,30 @@ extern "C" ah_status ah_fasta_format(const ah_fasta_names *nm, uint32_t fb_len, 
         o.put("\n");
         o.put(h_seq + h_seq_off[i], h_seq_off[i + 1] - h_seq_off[i]);
         o.put("\n");
+        if (fastq) {
+            o.put("+\n");
+            o.put(h_qual + h_seq_off[i], h_seq_off[i + 1] - h_seq_off[i]);
+            o.put("\n");
+        }
     }
     *h_n_bytes = o.pos;
     return AH_OK;
+}
+
+extern "C" ah_status ah_fasta_format(const ah_fasta_names *nm, uint32_t fb_len, uint32_t rb_len, const ah_amp *h_amps,
+                                     uint64_t n_amps, const double *h_tm, const uint8_t *h_pass, const char *h_seq,
+                                     const uint64_t *h_seq_off, const char *h_fb, const char *h_rb,
+                                     const uint8_t *h_bc_len, const char *h_fprimer, const char *h_rprimer,
+                                     char *h_out, uint64_t out_cap, uint64_t *h_n_bytes) {
+    return format_records(nm, fb_len, rb_len, h_amps, n_amps, h_tm, h_pass, h_seq, h_seq_off, nullptr, h_fb, h_rb,
+                          h_bc_len, h_fprimer, h_rprimer, h_out, out_cap, h_n_bytes, false);
+}
+
+extern "C" ah_status ah_fastq_format(const ah_fasta_names *nm, uint32_t fb_len, uint32_t rb_len, const ah_amp *h_amps,
+                                     uint64_t n_amps, const double *h_tm, const uint8_t *h_pass, const char *h_seq,
+                                     const uint64_t *h_seq_off, const char *h_qual, const char *h_fb,
+                                     const char *h_rb, const uint8_t *h_bc_len, const char *h_fprimer,
+                                     const char *h_rprimer, char *h_out, uint64_t out_cap, uint64_t *h_n_bytes) {
+    return format_records(nm, fb_len, rb_len, h_amps, n_amps, h_tm, h_pass, h_seq, h_seq_off, h_qual, h_fb, h_rb,
+                          h_bc_len, h_fprimer, h_rprimer, h_out, out_cap, h_n_bytes, true);
 }
