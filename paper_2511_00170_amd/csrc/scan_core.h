@@ -99,7 +99,10 @@ struct TileCtx {
     int32_t room;    // bases from the tile start to the sequence end (capped at 2^20)
     uint32_t pos0;   // sequence position of the tile's first base
     uint32_t has_n;
-    uint32_t pad;
+    // past the sequence's first 32 bases, room for the longest window after
+    // the tile's last base, no N: every window of the tile lies inside its
+    // sequence and is N-free
+    uint32_t plain;
 };
 
 #ifndef AH_QCAP
@@ -113,7 +116,7 @@ struct TileCtx {
 #ifndef AH_HCAP
 #define AH_HCAP 48                        // hits buffered per wave (LDS) before one atomic reserves their room
 #endif
-#define AH_TW (2 * AH_TILE_BLOCKS + 2)    // words per plane of a tile (+ one word each side)
+#define AH_TW (2 * AH_TILE_BLOCKS + 2)    // {h, l} ring words of a tile (+ one word each side)
 #define AH_QW (AH_HW + 1)                 // queue entry: one block's candidate words + tag
 // N-bitmap words covering the tile's blocks and one block on each side
 #define AH_NBW ((AH_TILE_BLOCKS + 2 + 31) / 32 + 1)
@@ -261,17 +264,59 @@ __device__ __forceinline__ void ah_pattern_record(const ScanArgs &a, const DPat 
     }
 }
 
-// Verify queued entries [e0, e1) (at most 64: one per lane).  Entry =
-// {candidate words 0..AH_HW-1 (bit q of word w: clamp site 32w+q of one
-// block of the lane), X << 9 | block << 8 | ctx << 6 | lane}; windows are
-// read from the tile words kept in LDS (sW[ctx][plane][word]).
+// Test one candidate window (start pl, tile-relative) against its pattern
+// record and buffer it as a hit: hW/lW = the window's plane words, nW = its
+// N positions.
+__device__ __forceinline__ void ah_window_hit(const ScanArgs &a, const HitBuf &hb, const TileCtx &c, const uint4 &p0,
+                                              const uint4 &p1, uint32_t k, int32_t pl, uint32_t hW, uint32_t lW,
+                                              uint32_t nW) {
+    const uint32_t lo = (lW & p0.y) | (~lW & p0.x);  // C : A
+    const uint32_t hi = (lW & p0.w) | (~lW & p0.z);  // T : G
+    const uint32_t matched = ((hW & hi) | (~hW & lo)) & ~nW & p1.y;
+    const uint32_t nmm = __popc(p1.y & ~matched);
+    if ((matched & p1.x) == p1.x && nmm <= k) {
+        const uint32_t pos = (uint32_t)((int64_t)c.pos0 + pl), w2 = p1.w | (nmm << 24);
+        const uint32_t slot = atomicAdd(hb.n, 1u);  // LDS
+        if (slot < AH_HCAP) {
+            // through an LDS-qualified pointer: a generic one becomes
+            // a FLAT store, which makes every later wait a full drain
+            ah_lds_u32 *r = (ah_lds_u32 *)&hb.rec[slot][0];
+            r[0] = c.seq;
+            r[1] = pos;
+            r[2] = w2;
+        } else {  // buffer full: straight to the hit array
+            const uint64_t h = atomicAdd((unsigned long long *)a.n_hits, 1ull);
+            if (h < a.hit_cap) {
+                uint32_t *r = a.hits + 3 * h;
+                r[0] = c.seq;
+                r[1] = pos;
+                r[2] = w2;
+            }
+        }
+    }
+}
+
+// Verify queued entries [e0, e1) (at most 64).  Entry = {candidate words
+// 0..AH_HW-1 (bit q of word w: clamp site 32w+q of one block of the lane),
+// X << 9 | block << 8 | ctx << 6 | lane}; windows are read from the tile
+// words kept in LDS (sW[ctx][word] = {h, l}).  A round of at most 32 (16)
+// entries gives each entry 2 (4) lanes, each taking a contiguous share of
+// its candidate bits: the round lasts as long as its busiest lane's bit
+// walk, and most entries hold one or two bits.
 template <bool kLdsOnly>
 __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
                                 const TileCtx &rctx, const uint32_t (*sQ)[AH_QW], uint32_t e0, uint32_t e1,
-                                const uint32_t (*sW)[2][AH_TW], const HitBuf &hb) {
-    const uint32_t e = e0 + ah_lane();
+                                const uint2 (*sW)[AH_TW], const HitBuf &hb) {
+    const uint32_t n = e1 - e0;  // wave-uniform
+    const uint32_t lg = n <= 16u ? 2u : (n <= 32u ? 1u : 0u);
+    const uint32_t lane = ah_lane();
+    const uint32_t e = e0 + (lane >> lg);
     if (e >= e1) return;
     uint64_t mm64 = ((uint64_t)sQ[e][1] << 32) | sQ[e][0];
+    if (lg) {
+        const uint32_t part = 64u >> lg, sub = lane & ((1u << lg) - 1u);
+        mm64 &= (~0ull >> (64u - part)) << (part * sub);
+    }
     const uint32_t tag = sQ[e][AH_HW];
     const uint32_t X = tag >> 9, blk = (tag >> 8) & 1u, ci = (tag >> 6) & 3u, ln = tag & 63u;
     // with one tile in the ring its context is wave-uniform (scalar registers)
@@ -279,11 +324,26 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
     uint4 p0, p1;
     ah_pattern_record<kLdsOnly>(a, sPat, n_lds, X, p0, p1);
     const uint32_t L = p1.z & 0xFFu, k = (p1.z >> 8) & 0xFFu, shift = p1.z >> 24;
-    const uint32_t *Wh = sW[ci][0], *Wl = sW[ci][1];
+    const uint2 *W = sW[ci];
+    // window start of bit 0 (tile-relative; shift <= 31, so >= -31)
+    const int32_t lane0 = (int32_t)(64 * (AH_BPL * ln + blk)) - (int32_t)shift;
+    // a plain tile (wave-uniform with one tile in the ring): the walk needs
+    // no bounds or N tests
+    if (AH_NCTX == 1 && c.plain) {
+        const uint32_t r0 = (uint32_t)(lane0 + 32);  // ring position of bit 0's window
+        while (mm64) {
+            const uint32_t bit = (uint32_t)__ffsll((unsigned long long)mm64) - 1;
+            mm64 &= mm64 - 1;
+            const uint32_t idx = r0 + bit;
+            const uint2 u = W[idx >> 5], v = W[(idx >> 5) + 1];
+            ah_window_hit(a, hb, c, p0, p1, k, (int32_t)idx - 32, ah_funnel(v.x, u.x, idx & 31u),
+                          ah_funnel(v.y, u.y, idx & 31u), 0u);
+        }
+        return;
+    }
     // window starts (tile-relative) allowed by the sequence bounds
     const int32_t lo_ok = c.lo;
     const int32_t hi_ok = c.room - (int32_t)L;
-    const int32_t lane0 = (int32_t)(64 * (AH_BPL * ln + blk)) - (int32_t)shift;
     while (mm64) {
         const uint32_t bit = (uint32_t)__ffsll((unsigned long long)mm64) - 1;
         mm64 &= mm64 - 1;
@@ -291,8 +351,7 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
         if (pl < lo_ok || pl > hi_ok) continue;
         const uint32_t idx = (uint32_t)(pl + 32);
         const uint32_t w = idx >> 5, off = idx & 31u;
-        const uint32_t hW = ah_funnel(Wh[w + 1], Wh[w], off);
-        const uint32_t lW = ah_funnel(Wl[w + 1], Wl[w], off);
+        const uint2 u = W[w], v = W[w + 1];
         uint32_t nW = 0;
         if (c.has_n) {
             const uint64_t gp = c.gbase + (uint64_t)(int64_t)pl;
@@ -302,30 +361,7 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
             if (bb != ba && o) nm |= ah_block_nmask(a.st, bb) << (64 - o);
             nW = (uint32_t)nm;
         }
-        const uint32_t lo = (lW & p0.y) | (~lW & p0.x);  // C : A
-        const uint32_t hi = (lW & p0.w) | (~lW & p0.z);  // T : G
-        const uint32_t matched = ((hW & hi) | (~hW & lo)) & ~nW & p1.y;
-        const uint32_t nmm = __popc(p1.y & ~matched);
-        if ((matched & p1.x) == p1.x && nmm <= k) {
-            const uint32_t pos = (uint32_t)((int64_t)c.pos0 + pl), w2 = p1.w | (nmm << 24);
-            const uint32_t slot = atomicAdd(hb.n, 1u);  // LDS
-            if (slot < AH_HCAP) {
-                // through an LDS-qualified pointer: a generic one becomes
-                // a FLAT store, which makes every later wait a full drain
-                ah_lds_u32 *r = (ah_lds_u32 *)&hb.rec[slot][0];
-                r[0] = c.seq;
-                r[1] = pos;
-                r[2] = w2;
-            } else {  // buffer full: straight to the hit array
-                const uint64_t h = atomicAdd((unsigned long long *)a.n_hits, 1ull);
-                if (h < a.hit_cap) {
-                    uint32_t *r = a.hits + 3 * h;
-                    r[0] = c.seq;
-                    r[1] = pos;
-                    r[2] = w2;
-                }
-            }
-        }
+        ah_window_hit(a, hb, c, p0, p1, k, pl, ah_funnel(v.x, u.x, off), ah_funnel(v.y, u.y, off), nW);
     }
 }
 
@@ -334,7 +370,7 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
 template <bool kLdsOnly>
 __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
                                          const TileCtx &rctx,
-                                         uint32_t (*sQ)[AH_QW], uint32_t &qn, const uint32_t (*sW)[2][AH_TW],
+                                         uint32_t (*sQ)[AH_QW], uint32_t &qn, const uint2 (*sW)[AH_TW],
                                          const HitBuf &hb, bool drain) {
     ah_wave_sync();
     uint32_t e0 = 0;
@@ -367,7 +403,7 @@ __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, ui
 // and verify full rounds of queued candidates.
 template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds, TileCtx *sCtx,
-                                        TileCtx &rctx, uint32_t (*sQ)[AH_QW], uint32_t (*sW)[2][AH_TW],
+                                        TileCtx &rctx, uint32_t (*sQ)[AH_QW], uint2 (*sW)[AH_TW],
                                         const HitBuf &hb, const TileLoad &L, const SeqCursor &cur, uint32_t groups,
                                         uint32_t &qn, uint32_t &nctx) {
     const uint32_t lane = ah_lane();
@@ -385,18 +421,16 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
     const uint32_t rest = cur.len - c.pos0;
     c.room = (int32_t)(rest < (1u << 20) ? rest : (1u << 20));
     c.has_n = tile_has_n(L);
-    c.pad = 0;
+    c.plain = c.lo == -32 && c.room >= 64 * AH_TILE_BLOCKS + 32 && !c.has_n;
     if (AH_NCTX == 1) rctx = c;
     else if (lane == 0) sCtx[ci] = c;
     // the tile's words for deferred verification: [0] the 32 positions
     // before the tile, then every lane's blocks in order, then the 32 after
-    uint32_t *Wh = sW[ci][0], *Wl = sW[ci][1];
+    uint2 *W = sW[ci];
 #pragma unroll
     for (int b = 0; b < AH_BPL; b++) {
-        Wh[1 + AH_NW * lane + 2 * b] = L.blk[b].x;
-        Wl[1 + AH_NW * lane + 2 * b] = L.blk[b].y;
-        Wh[2 + AH_NW * lane + 2 * b] = L.blk[b].z;
-        Wl[2 + AH_NW * lane + 2 * b] = L.blk[b].w;
+        W[1 + AH_NW * lane + 2 * b] = make_uint2(L.blk[b].x, L.blk[b].y);
+        W[2 + AH_NW * lane + 2 * b] = make_uint2(L.blk[b].z, L.blk[b].w);
     }
     // the lane after's first words (lane 63: the block after the tile)
     uint32_t nxh = ah_from_next_lane(L.blk[0].x), nxl = ah_from_next_lane(L.blk[0].y);
@@ -404,14 +438,8 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
         nxh = L.hal.x;
         nxl = L.hal.y;
     }
-    if (lane == 0) {
-        Wh[0] = L.hal.z;
-        Wl[0] = L.hal.w;
-    }
-    if (lane == 63) {
-        Wh[AH_TW - 1] = nxh;
-        Wl[AH_TW - 1] = nxl;
-    }
+    if (lane == 0) W[0] = make_uint2(L.hal.z, L.hal.w);
+    if (lane == 63) W[AH_TW - 1] = make_uint2(nxh, nxl);
 #pragma unroll
     for (int blk = 0; blk < AH_BPL; blk++) {
         // the block's words and their neighbours
@@ -544,14 +572,14 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
 template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds,
                                              TileCtx (*sCtx_all)[AH_NCTX], uint32_t (*sQ_all)[AH_QCAP][AH_QW],
-                                             uint32_t (*sW_all)[AH_NCTX][2][AH_TW],
+                                             uint2 (*sW_all)[AH_NCTX][AH_TW],
                                              uint32_t (*sH_all)[AH_HCAP][3], uint32_t *sHn_all) {
     // the wave index is uniform across the wave; saying so keeps the tile
     // walk, the cursor and the queue bookkeeping in scalar registers
     const uint32_t wv = ah_uni(threadIdx.x >> 6);
     TileCtx *sCtx = sCtx_all[wv];
     uint32_t(*sQ)[AH_QW] = sQ_all[wv];
-    uint32_t(*sW)[2][AH_TW] = sW_all[wv];
+    uint2(*sW)[AH_TW] = sW_all[wv];
     const HitBuf hb{sH_all[wv], sHn_all + wv};
     if (ah_lane() == 0) *hb.n = 0u;
     ah_wave_sync();
