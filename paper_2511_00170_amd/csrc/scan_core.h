@@ -246,6 +246,14 @@ __device__ __forceinline__ void ah_hits_out(const ScanArgs &a, const HitBuf &hb)
     }
 }
 
+// Block i of the lane's loaded blocks by selection, not by indexing: where the
+// block loop stays rolled (many pattern groups make its body too large to
+// unroll), an indexed register array would be kept in scratch memory.
+static_assert(AH_BPL == 1 || AH_BPL == 2, "one or two blocks per lane");
+__device__ __forceinline__ uint4 ah_blk_at(const TileLoad &L, int i) {
+    return (AH_BPL == 1 || i == 0) ? L.blk[0] : L.blk[AH_BPL - 1];
+}
+
 // Any N in the tile's blocks or its halo blocks (wave-uniform, conservative).
 __device__ __forceinline__ bool tile_has_n(const TileLoad &L) { return __ballot(L.nbw != 0) != 0; }
 
@@ -444,20 +452,23 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
     for (int blk = 0; blk < AH_BPL; blk++) {
         // the block's words and their neighbours
         AhBase B;
-        B.h[1] = L.blk[blk].x;
-        B.l[1] = L.blk[blk].y;
-        B.h[2] = L.blk[blk].z;
-        B.l[2] = L.blk[blk].w;
-        B.h[3] = blk + 1 < AH_BPL ? L.blk[blk + 1 < AH_BPL ? blk + 1 : 0].x : nxh;
-        B.l[3] = blk + 1 < AH_BPL ? L.blk[blk + 1 < AH_BPL ? blk + 1 : 0].y : nxl;
+        const uint4 cb = ah_blk_at(L, blk);
+        B.h[1] = cb.x;
+        B.l[1] = cb.y;
+        B.h[2] = cb.z;
+        B.l[2] = cb.w;
+        const uint4 nb = ah_blk_at(L, blk + 1 < AH_BPL ? blk + 1 : 0);
+        B.h[3] = blk + 1 < AH_BPL ? nb.x : nxh;
+        B.l[3] = blk + 1 < AH_BPL ? nb.y : nxl;
         B.h[0] = B.l[0] = 0u;
         if (F::kUsesBase) {
             // the 32 positions before (lane 0's first block: the block before
             // the tile; at a sequence start they are another sequence's or
             // padding, which only windows that verification rejects can see)
             if (blk > 0) {
-                B.h[0] = L.blk[blk > 0 ? blk - 1 : 0].z;
-                B.l[0] = L.blk[blk > 0 ? blk - 1 : 0].w;
+                const uint4 pb = ah_blk_at(L, blk > 0 ? blk - 1 : 0);
+                B.h[0] = pb.z;
+                B.l[0] = pb.w;
             } else {
                 B.h[0] = ah_from_prev_lane(L.blk[AH_BPL - 1].z);
                 B.l[0] = ah_from_prev_lane(L.blk[AH_BPL - 1].w);
