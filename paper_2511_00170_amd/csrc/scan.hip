@@ -132,50 +132,37 @@ __device__ __forceinline__ uint64_t tiles_of(const ah_store &st, const uint32_t 
     return (nblk + tile_blocks - 1) / tile_blocks;
 }
 
-// Exclusive prefix of get(0..n-1) into out[0..n] (out[n] = total) by one
-// workgroup, one contiguous chunk per thread.  A chunk of at most 8 values is
-// held in registers and all its loads are issued before the first is used,
-// so it costs one round of memory latency instead of two per value.
-template <class Get>
-__device__ __forceinline__ void ah_chunk_excl_scan(uint64_t n, uint64_t *out, uint64_t *lds, Get get) {
-    const uint64_t per = (n + blockDim.x - 1) / blockDim.x;  // wave-uniform
-    const uint64_t i0 = threadIdx.x * per, i1 = i0 + per < n ? i0 + per : n;
-    uint64_t tot;
-    if (per <= 8) {
-        uint64_t v[8];
-#pragma unroll
-        for (int j = 0; j < 8; j++) v[j] = i0 + j < i1 ? get(i0 + j) : 0;
-        uint64_t loc = 0;
-#pragma unroll
-        for (int j = 0; j < 8; j++) loc += v[j];
-        uint64_t o = ah_block_excl_sum<uint64_t>(loc, lds, tot);
-#pragma unroll
-        for (int j = 0; j < 8; j++) {
-            if (i0 + j < i1) out[i0 + j] = o;
-            o += v[j];
-        }
-    } else {
-        uint64_t loc = 0;
-        for (uint64_t i = i0; i < i1; i++) loc += get(i);
-        uint64_t o = ah_block_excl_sum<uint64_t>(loc, lds, tot);
-        for (uint64_t i = i0; i < i1; i++) {
-            out[i] = o;
-            o += get(i);
-        }
-    }
-    if (threadIdx.x == 0) out[n] = tot;
-}
-
 __global__ void __launch_bounds__(1024) ah_tile_pref_kernel(ah_store st, const uint32_t *list, uint32_t n,
                                                             uint32_t tile_blocks, uint64_t *pref, uint64_t *n_hits) {
     __shared__ uint64_t lds[16];
     if (threadIdx.x == 0) *n_hits = 0;
-    ah_chunk_excl_scan(n, pref, lds, [&](uint64_t i) { return tiles_of(st, list, i, tile_blocks); });
+    const uint64_t per = ((uint64_t)n + blockDim.x - 1) / blockDim.x;
+    const uint64_t i0 = threadIdx.x * per, i1 = i0 + per < n ? i0 + per : n;
+    uint64_t loc = 0;
+    for (uint64_t i = i0; i < i1; i++) loc += tiles_of(st, list, i, tile_blocks);
+    uint64_t tot;
+    uint64_t o = ah_block_excl_sum<uint64_t>(loc, lds, tot);
+    for (uint64_t i = i0; i < i1; i++) {
+        pref[i] = o;
+        o += tiles_of(st, list, i, tile_blocks);
+    }
+    if (threadIdx.x == 0) pref[n] = tot;
 }
 
 __global__ void __launch_bounds__(1024) ah_scan_small_u64_kernel(const uint64_t *in, uint64_t *out, uint64_t n) {
     __shared__ uint64_t lds[16];
-    ah_chunk_excl_scan(n, out, lds, [&](uint64_t i) { return in[i]; });
+    const uint64_t per = (n + blockDim.x - 1) / blockDim.x;  // one contiguous chunk per thread
+    const uint64_t i0 = threadIdx.x * per, i1 = i0 + per < n ? i0 + per : n;
+    uint64_t loc = 0;
+    for (uint64_t i = i0; i < i1; i++) loc += in[i];
+    uint64_t tot;
+    uint64_t o = ah_block_excl_sum<uint64_t>(loc, lds, tot);
+    for (uint64_t i = i0; i < i1; i++) {
+        const uint64_t v = in[i];
+        out[i] = o;
+        o += v;
+    }
+    if (threadIdx.x == 0) out[n] = tot;
 }
 
 void ah_scan_small_u64(const uint64_t *d_in, uint64_t *d_out, uint64_t n, hipStream_t s) {
