@@ -106,7 +106,7 @@ struct TileCtx {
 };
 
 #ifndef AH_QCAP
-#define AH_QCAP 320                       // queue entries per wave: < 64 left over + 4 x 64 of one group
+#define AH_QCAP 320                       // queue entries per wave: < 64 left over + 4 x 64 of one group (+ one spare)
 #endif
 #ifndef AH_NCTX
 // tiles whose candidates may wait in the queue (<= 4); a two-block tile
@@ -543,13 +543,13 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
                         for (int w = 0; w < AH_HW; w++) nzw |= C[(kX * gi + xi) * AH_HW + w];
                         const bool nz = nzw != 0;
                         const uint64_t bal = __ballot(nz);
-                        if (nz) {
-                            const uint32_t slot = qn + ah_mbcnt(bal);
-                            const uint32_t x = (uint32_t)(kX * half + xi);
+                        // every lane writes, without a branch; lanes without
+                        // candidates all to the one spare entry past the queue
+                        const uint32_t slot = nz ? qn + ah_mbcnt(bal) : (uint32_t)AH_QCAP;
+                        const uint32_t x = (uint32_t)(kX * half + xi);
 #pragma unroll
-                            for (int w = 0; w < AH_HW; w++) sQ[slot][w] = C[(kX * gi + xi) * AH_HW + w];
-                            sQ[slot][AH_HW] = ((4 * g + x) << 9) | ((uint32_t)blk << 8) | (ci << 6) | lane;
-                        }
+                        for (int w = 0; w < AH_HW; w++) sQ[slot][w] = C[(kX * gi + xi) * AH_HW + w];
+                        sQ[slot][AH_HW] = ((4 * g + x) << 9) | ((uint32_t)blk << 8) | (ci << 6) | lane;
                         qn = ah_uni(qn + (uint32_t)__popcll(bal));  // keeps the queue count in a scalar register
                     }
                 }
@@ -582,7 +582,7 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
 // n_lds: pattern records staged in sPat; kLdsOnly: n_lds covers every record.
 template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds,
-                                             TileCtx (*sCtx_all)[AH_NCTX], uint32_t (*sQ_all)[AH_QCAP][AH_QW],
+                                             TileCtx (*sCtx_all)[AH_NCTX], uint32_t (*sQ_all)[AH_QCAP + 1][AH_QW],
                                              uint2 (*sW_all)[AH_NCTX][AH_TW],
                                              uint32_t (*sH_all)[AH_HCAP][3], uint32_t *sHn_all) {
     // the wave index is uniform across the wave; saying so keeps the tile
