@@ -128,13 +128,17 @@ __device__ __forceinline__ uint64_t ah_uni64(uint64_t x) {
 }
 
 // Sequence cursor over the tile list of one wave (wave-uniform values).
+// Tiles are counted from a first tile t0 in 32 bits (the walk covers at most
+// 2^31 tiles from it), so the per-tile walk needs no 64-bit compares.
 struct SeqCursor {
     uint32_t i;        // list index
     uint32_t seq;
     uint32_t len;
     uint32_t nblk;
     uint64_t blk0;
-    uint64_t tp0, tp1; // tile_pref[i], tile_pref[i + 1]
+    uint64_t t0;       // the walk's first tile
+    uint32_t d;        // tile_pref[i] - t0 (mod 2^32): tile r is the sequence's tile r - d
+    uint32_t r1;       // tile_pref[i + 1] - t0, capped at 2^32 - 1: the first tile past the sequence
     uint64_t gm;       // groups scanned on this sequence (bit g)
 
     __device__ void load(const ScanArgs &a) {
@@ -146,10 +150,13 @@ struct SeqCursor {
         len = in_store ? ah_uni(a.st.d_seq_len[seq]) : 0u;
         nblk = (len + 63u) / 64u;
         blk0 = in_store ? ah_uni64(a.st.d_seq_block0[seq]) : 0ull;
-        tp0 = ah_uni64(a.tile_pref[i]);
-        tp1 = ah_uni64(a.tile_pref[i + 1]);
+        const uint64_t tp0 = ah_uni64(a.tile_pref[i]), tp1 = ah_uni64(a.tile_pref[i + 1]);
+        d = (uint32_t)(tp0 - t0);
+        r1 = tp1 - t0 < 0xFFFFFFFFull ? (uint32_t)(tp1 - t0) : 0xFFFFFFFFu;  // tp1 > t0 once loaded
     }
+    // the sequence holding tile t, which becomes the walk's first
     __device__ void init(const ScanArgs &a, uint64_t t) {
+        t0 = t;
         uint32_t lo = 0, hi = a.n_list;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
@@ -159,8 +166,9 @@ struct SeqCursor {
         i = lo;
         load(a);
     }
-    __device__ void advance(const ScanArgs &a, uint64_t t) {
-        while (t >= tp1) {
+    // move to the sequence holding tile r (r >= the current one's first)
+    __device__ void advance(const ScanArgs &a, uint32_t r) {
+        while (r >= r1) {
             i++;
             load(a);
         }
@@ -179,9 +187,9 @@ struct TileLoad {
     uint64_t gb0;    // store block of the tile's first block (uniform)
 };
 
-__device__ __forceinline__ void tile_issue(const ScanArgs &a, const SeqCursor &c, uint64_t t, TileLoad &L) {
+__device__ __forceinline__ void tile_issue(const ScanArgs &a, const SeqCursor &c, uint32_t r, TileLoad &L) {
     const uint32_t lane = ah_lane();
-    L.rel0 = (uint32_t)(t - c.tp0) * AH_TILE_BLOCKS;
+    L.rel0 = (r - c.d) * AH_TILE_BLOCKS;
     const uint32_t left = c.nblk - L.rel0;
     L.nb = left < AH_TILE_BLOCKS ? left : AH_TILE_BLOCKS;
     L.gb0 = c.blk0 + L.rel0;
@@ -601,35 +609,40 @@ __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat
     const uint32_t wg = (nwg % 8 == 0) ? (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8 : blockIdx.x;
     const uint64_t nw = (uint64_t)nwg * 4, gw = (uint64_t)wg * 4 + wv;
     const uint64_t per = (total + nw - 1) / nw;
-    uint64_t t = gw * per;
-    const uint64_t tend = t + per < total ? t + per : total;
-    if (t >= tend) return;
+    const uint64_t t0 = gw * per;
+    if (t0 >= total) return;
+    const uint64_t tend = t0 + per < total ? t0 + per : total;
 
     const uint32_t groups = f.groups(a);
     uint32_t qn = 0, nctx = 0;
     TileCtx rctx{};  // the ring tile's context when the ring holds one tile
+    // The wave's tiles in segments of at most 2^31 (one segment in practice),
+    // each walked with 32-bit tile counts.
+    for (uint64_t s0 = t0; s0 < tend; s0 += (1ull << 31)) {
+    const uint32_t nt = (uint32_t)(tend - s0 < (1ull << 31) ? tend - s0 : (1ull << 31));
     SeqCursor cur;
-    cur.init(a, t);
+    cur.init(a, s0);
     // Two load sets used in turn: the next tile's loads go to the set not being
     // processed, so no register copy (which would wait for them) is needed.
     // The last tile reloads itself, so the loads are unconditional.
     TileLoad A, B;
-    tile_issue(a, cur, t, A);
-    for (;;) {
-        uint64_t tn = t + 1 < tend ? t + 1 : t;
+    tile_issue(a, cur, 0u, A);
+    for (uint32_t r = 0;;) {
+        uint32_t rn = r + 1 < nt ? r + 1 : r;
         SeqCursor nc = cur;
-        nc.advance(a, tn);
-        tile_issue(a, nc, tn, B);
+        nc.advance(a, rn);
+        tile_issue(a, nc, rn, B);
         ah_tile<kLdsOnly>(a, f, sPat, n_lds, sCtx, rctx, sQ, sW, hb, A, cur, groups, qn, nctx);
         cur = nc;
-        if (++t >= tend) break;
-        tn = t + 1 < tend ? t + 1 : t;
+        if (++r >= nt) break;
+        rn = r + 1 < nt ? r + 1 : r;
         nc = cur;
-        nc.advance(a, tn);
-        tile_issue(a, nc, tn, A);
+        nc.advance(a, rn);
+        tile_issue(a, nc, rn, A);
         ah_tile<kLdsOnly>(a, f, sPat, n_lds, sCtx, rctx, sQ, sW, hb, B, cur, groups, qn, nctx);
         cur = nc;
-        if (++t >= tend) break;
+        if (++r >= nt) break;
+    }
     }
     if (qn) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, rctx, sQ, qn, sW, hb, true);
     ah_hits_out(a, hb);
