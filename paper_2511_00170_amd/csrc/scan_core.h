@@ -551,13 +551,19 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
                         for (int w = 0; w < AH_HW; w++) nzw |= C[(kX * gi + xi) * AH_HW + w];
                         const bool nz = nzw != 0;
                         const uint64_t bal = __ballot(nz);
-                        // every lane writes, without a branch; lanes without
-                        // candidates all to the one spare entry past the queue
-                        const uint32_t slot = nz ? qn + ah_mbcnt(bal) : (uint32_t)AH_QCAP;
+                        // With all four patterns in one pass every lane writes,
+                        // without a branch, lanes without candidates all to the
+                        // one spare entry past the queue (fewer scalar
+                        // instructions, 2% faster); in the many-pair kernel only
+                        // the lanes with candidates write (the same time with 15%
+                        // fewer VALU instructions).
                         const uint32_t x = (uint32_t)(kX * half + xi);
+                        if (F::kHalves == 1 || nz) {
+                            const uint32_t slot = nz ? qn + ah_mbcnt(bal) : (uint32_t)AH_QCAP;
 #pragma unroll
-                        for (int w = 0; w < AH_HW; w++) sQ[slot][w] = C[(kX * gi + xi) * AH_HW + w];
-                        sQ[slot][AH_HW] = ((4 * g + x) << 9) | ((uint32_t)blk << 8) | (ci << 6) | lane;
+                            for (int w = 0; w < AH_HW; w++) sQ[slot][w] = C[(kX * gi + xi) * AH_HW + w];
+                            sQ[slot][AH_HW] = ((4 * g + x) << 9) | ((uint32_t)blk << 8) | (ci << 6) | lane;
+                        }
                         qn = ah_uni(qn + (uint32_t)__popcll(bal));  // keeps the queue count in a scalar register
                     }
                 }
