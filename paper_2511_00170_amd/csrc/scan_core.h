@@ -223,6 +223,12 @@ __device__ __forceinline__ void tile_issue(const ScanArgs &a, const SeqCursor &c
 
 typedef __attribute__((address_space(3))) uint32_t ah_lds_u32;
 
+// Queue entry `slot` through an LDS-qualified pointer: its address is formed
+// in 32 bits (through the generic array type it is a 64-bit multiply-add).
+__device__ __forceinline__ ah_lds_u32 *ah_qe(const uint32_t (*sQ)[AH_QW], uint32_t slot) {
+    return (ah_lds_u32 *)&sQ[0][0] + __umul24(slot, (uint32_t)AH_QW);
+}
+
 // A wave's hit buffer in LDS: records and the count of hits accepted since
 // the last write-out (those past AH_HCAP went to global memory directly).
 struct HitBuf {
@@ -328,12 +334,13 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
     const uint32_t lane = ah_lane();
     const uint32_t e = e0 + (lane >> lg);
     if (e >= e1) return;
-    uint64_t mm64 = ((uint64_t)sQ[e][1] << 32) | sQ[e][0];
+    const ah_lds_u32 *qe = ah_qe(sQ, e);
+    uint64_t mm64 = ((uint64_t)qe[1] << 32) | qe[0];
     if (lg) {
         const uint32_t part = 64u >> lg, sub = lane & ((1u << lg) - 1u);
         mm64 &= (~0ull >> (64u - part)) << (part * sub);
     }
-    const uint32_t tag = sQ[e][AH_HW];
+    const uint32_t tag = qe[AH_HW];
     const uint32_t X = tag >> 9, blk = (tag >> 8) & 1u, ci = (tag >> 6) & 3u, ln = tag & 63u;
     // with one tile in the ring its context is wave-uniform (scalar registers)
     const TileCtx c = AH_NCTX == 1 ? rctx : sCtx[ci];
@@ -400,12 +407,12 @@ __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, ui
         uint32_t v[AH_QW];
         if (lane < rest) {
 #pragma unroll
-            for (int j = 0; j < AH_QW; j++) v[j] = sQ[e0 + lane][j];
+            for (int j = 0; j < AH_QW; j++) v[j] = ah_qe(sQ, e0 + lane)[j];
         }
         ah_wave_sync();
         if (lane < rest) {
 #pragma unroll
-            for (int j = 0; j < AH_QW; j++) sQ[lane][j] = v[j];
+            for (int j = 0; j < AH_QW; j++) ah_qe(sQ, lane)[j] = v[j];
         }
         qn = ah_uni(rest);
     }
@@ -560,9 +567,10 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
                         const uint32_t x = (uint32_t)(kX * half + xi);
                         if (F::kHalves == 1 || nz) {
                             const uint32_t slot = nz ? qn + ah_mbcnt(bal) : (uint32_t)AH_QCAP;
+                            ah_lds_u32 *qe = ah_qe(sQ, slot);
 #pragma unroll
-                            for (int w = 0; w < AH_HW; w++) sQ[slot][w] = C[(kX * gi + xi) * AH_HW + w];
-                            sQ[slot][AH_HW] = ((4 * g + x) << 9) | ((uint32_t)blk << 8) | (ci << 6) | lane;
+                            for (int w = 0; w < AH_HW; w++) qe[w] = C[(kX * gi + xi) * AH_HW + w];
+                            qe[AH_HW] = ((4 * g + x) << 9) | ((uint32_t)blk << 8) | (ci << 6) | lane;
                         }
                         qn = ah_uni(qn + (uint32_t)__popcll(bal));  // keeps the queue count in a scalar register
                     }
