@@ -116,7 +116,7 @@ struct TileCtx {
 #ifndef AH_HCAP
 #define AH_HCAP 48                        // hits buffered per wave (LDS) before one atomic reserves their room
 #endif
-#define AH_TW (2 * AH_TILE_BLOCKS + 2)    // {h, l} ring words of a tile (+ one word each side)
+#define AH_TW (2 * AH_TILE_BLOCKS + 2)    // {h, l} ring words of a tile (+ one word each side; one spare follows)
 #define AH_QW (AH_HW + 1)                 // queue entry: one block's candidate words + tag
 // N-bitmap words covering the tile's blocks and one block on each side
 #define AH_NBW ((AH_TILE_BLOCKS + 2 + 31) / 32 + 1)
@@ -213,7 +213,7 @@ __device__ __forceinline__ void tile_issue(const ScanArgs &a, const SeqCursor &c
     // gb0+AH_TILE_BLOCKS.  A nonzero word means the tile may touch an N -- a
     // superset, which only costs exact per-block lookups in verification.
     const uint64_t q = L.gb0 >> 5;
-    const uint64_t wb = (q > 1 ? q : 1) - 1;
+    const uint64_t wb = q - (q != 0 ? 1u : 0u);  // max(q, 1) - 1, with scalar compares
     const uint64_t nw = (a.st.n_blocks + 31) >> 5;
     const uint32_t room = (uint32_t)(nw - 1 - wb);  // words after wb
     uint32_t wi = lane < AH_NBW - 1 ? lane : AH_NBW - 1;
@@ -328,7 +328,7 @@ __device__ __forceinline__ void ah_window_hit(const ScanArgs &a, const HitBuf &h
 template <bool kLdsOnly>
 __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
                                 const TileCtx &rctx, const uint32_t (*sQ)[AH_QW], uint32_t e0, uint32_t e1,
-                                const uint2 (*sW)[AH_TW], const HitBuf &hb) {
+                                const uint2 (*sW)[AH_TW + 1], const HitBuf &hb) {
     const uint32_t n = e1 - e0;  // wave-uniform
     const uint32_t lg = n <= 16u ? 2u : (n <= 32u ? 1u : 0u);
     const uint32_t lane = ah_lane();
@@ -393,7 +393,7 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
 template <bool kLdsOnly>
 __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
                                          const TileCtx &rctx,
-                                         uint32_t (*sQ)[AH_QW], uint32_t &qn, const uint2 (*sW)[AH_TW],
+                                         uint32_t (*sQ)[AH_QW], uint32_t &qn, const uint2 (*sW)[AH_TW + 1],
                                          const HitBuf &hb, bool drain) {
     ah_wave_sync();
     uint32_t e0 = 0;
@@ -417,8 +417,6 @@ __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, ui
         qn = ah_uni(rest);
     }
     ah_wave_sync();
-    // half full: write out, so the next flush's hits fit
-    if (ah_uni(*hb.n) >= AH_HCAP / 2) ah_hits_out(a, hb);
 }
 
 // One tile, its blocks already loaded into L: record its context and words
@@ -426,7 +424,7 @@ __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, ui
 // and verify full rounds of queued candidates.
 template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds, TileCtx *sCtx,
-                                        TileCtx &rctx, uint32_t (*sQ)[AH_QW], uint2 (*sW)[AH_TW],
+                                        TileCtx &rctx, uint32_t (*sQ)[AH_QW], uint2 (*sW)[AH_TW + 1],
                                         const HitBuf &hb, const TileLoad &L, const SeqCursor &cur, uint32_t groups,
                                         uint32_t &qn, uint32_t &nctx) {
     const uint32_t lane = ah_lane();
@@ -434,6 +432,8 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
         ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, rctx, sQ, qn, sW, hb, true);
         nctx = 0;
     }
+    // buffered hits so far, read here and tested after the filter
+    const uint32_t hits_buffered = ah_lds<uint32_t>(hb.n);
     const uint32_t ci = nctx;
     nctx = ah_uni(nctx + 1);
     TileCtx c;  // wave-uniform
@@ -461,8 +461,10 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
         nxh = L.hal.x;
         nxl = L.hal.y;
     }
-    if (lane == 0) W[0] = make_uint2(L.hal.z, L.hal.w);
-    if (lane == 63) W[AH_TW - 1] = make_uint2(nxh, nxl);
+    // the halo words without a branch: lane 0 the word before the tile, lane
+    // 63 the word after it, every other lane the spare word past the ring
+    W[lane == 0 ? 0 : (lane == 63 ? AH_TW - 1 : AH_TW)] =
+        lane == 0 ? make_uint2(L.hal.z, L.hal.w) : make_uint2(nxh, nxl);
 #pragma unroll
     for (int blk = 0; blk < AH_BPL; blk++) {
         // the block's words and their neighbours
@@ -579,6 +581,7 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
         }
     }
     if (qn >= 64) ah_flush<kLdsOnly>(a, sPat, n_lds, sCtx, rctx, sQ, qn, sW, hb, false);
+    if (ah_uni(hits_buffered) >= AH_HCAP / 2) ah_hits_out(a, hb);
 }
 
 // The kernel body.  Filter F provides
@@ -605,14 +608,14 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
 template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds,
                                              TileCtx (*sCtx_all)[AH_NCTX], uint32_t (*sQ_all)[AH_QCAP + 1][AH_QW],
-                                             uint2 (*sW_all)[AH_NCTX][AH_TW],
+                                             uint2 (*sW_all)[AH_NCTX][AH_TW + 1],
                                              uint32_t (*sH_all)[AH_HCAP][3], uint32_t *sHn_all) {
     // the wave index is uniform across the wave; saying so keeps the tile
     // walk, the cursor and the queue bookkeeping in scalar registers
     const uint32_t wv = ah_uni(threadIdx.x >> 6);
     TileCtx *sCtx = sCtx_all[wv];
     uint32_t(*sQ)[AH_QW] = sQ_all[wv];
-    uint2(*sW)[AH_TW] = sW_all[wv];
+    uint2(*sW)[AH_TW + 1] = sW_all[wv];
     const HitBuf hb{sH_all[wv], sHn_all + wv};
     if (ah_lane() == 0) *hb.n = 0u;
     ah_wave_sync();
