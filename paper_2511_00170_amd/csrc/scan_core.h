@@ -567,9 +567,17 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
                         // the lanes with candidates write (the same time with 15%
                         // fewer VALU instructions).
                         const uint32_t x = (uint32_t)(kX * half + xi);
+                        // (the lane count is taken outside the select: it is a
+                        // cross-lane operation, which a select would turn into a
+                        // masked branch)
+                        const uint32_t m = F::kHalves == 1 ? ah_mbcnt(bal) : 0u;
                         if (F::kHalves == 1 || nz) {
-                            const uint32_t slot = nz ? qn + ah_mbcnt(bal) : (uint32_t)AH_QCAP;
-                            ah_lds_u32 *qe = ah_qe(sQ, slot);
+                            // entry qn + (lane count): the wave-uniform start
+                            // plus one 24-bit multiply-add per lane
+                            ah_lds_u32 *qe = F::kHalves == 1
+                                                 ? (nz ? ah_qe(sQ, qn) + __umul24(m, (uint32_t)AH_QW)
+                                                       : ah_qe(sQ, AH_QCAP))
+                                                 : ah_qe(sQ, qn) + __umul24(ah_mbcnt(bal), (uint32_t)AH_QW);
 #pragma unroll
                             for (int w = 0; w < AH_HW; w++) qe[w] = C[(kX * gi + xi) * AH_HW + w];
                             qe[AH_HW] = ((4 * g + x) << 9) | ((uint32_t)blk << 8) | (ci << 6) | lane;
