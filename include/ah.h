@@ -171,7 +171,7 @@ ah_status ah_primers_jit(ah_primer_set ps);
  * per wave (2..256), compiling it on first use (variants stay cached with
  * the set).  Every variant finds the same hits; registers, LDS and hence
  * occupancy and speed differ -- the batch autotuner times them.
- * ah_primers_jit selects (1, 48) unless a variant is already selected.
+ * ah_primers_jit selects (2, 48) unless a variant is already selected.
  * Errors: AH_E_ARG (null set, values out of range), AH_E_HIP. */
 ah_status ah_primers_jit_variant(ah_primer_set ps, uint32_t blocks_per_lane, uint32_t hit_buffer);
 

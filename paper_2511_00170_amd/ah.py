@@ -561,8 +561,8 @@ def table_bytes(n_pairs: int) -> int:
     return int(_lib.ah_primers_table_bytes(n_pairs))
 
 
-JIT_DEFAULT_VARIANT = (1, 48)
-JIT_VARIANTS = ((1, 48), (1, 16), (2, 48), (2, 16))   # (blocks per lane, LDS hit buffer per wave)
+JIT_DEFAULT_VARIANT = (2, 48)
+JIT_VARIANTS = ((2, 48), (2, 16), (1, 48), (1, 16))   # (blocks per lane, LDS hit buffer per wave), default first
 
 
 def read_probe(buf: torch.Tensor, out: torch.Tensor, stream=None) -> None:

@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(256) ah_scan_kernel(ScanArgs a) {
     __shared__ DPat sPat[AH_LDS_PATS];
     __shared__ TileCtx sCtx[4][AH_NCTX];
     __shared__ uint32_t sQ[4][AH_QCAP + 1][AH_QW];
-    __shared__ uint2 sW[4][AH_NCTX][AH_TW + 1];
+    __shared__ uint2 sW[4][AH_NCTX][AH_TW];
     __shared__ uint32_t sH[4][AH_HCAP][3];
     __shared__ uint32_t sHn[4];
     ah_stage_patterns(a, sPat, AH_LDS_PATS);
@@ -191,7 +191,7 @@ struct AhJitSet {
     AhJit *active = nullptr;
 };
 
-#define AH_JIT_DEFAULT_BPL 1u
+#define AH_JIT_DEFAULT_BPL 2u
 #define AH_JIT_DEFAULT_HCAP 48u
 
 // ---------------------------------------------------------------- filter plan
@@ -424,7 +424,7 @@ static std::string jit_source(const ah_primer_set_ *ps, uint32_t bpl, uint32_t h
          "  __shared__ DPat sPat[AH_JIT_LDS_PATS];\n"
          "  __shared__ TileCtx sCtx[4][AH_NCTX];\n"
          "  __shared__ uint32_t sQ[4][AH_QCAP + 1][AH_QW];\n"
-         "  __shared__ uint2 sW[4][AH_NCTX][AH_TW + 1];\n"
+         "  __shared__ uint2 sW[4][AH_NCTX][AH_TW];\n"
          "  __shared__ uint32_t sH[4][AH_HCAP][3];\n"
          "  __shared__ uint32_t sHn[4];\n"
          "  ah_stage_patterns(a, sPat, AH_JIT_LDS_PATS);\n"

@@ -106,7 +106,7 @@ struct TileCtx {
 };
 
 #ifndef AH_QCAP
-#define AH_QCAP 320                       // queue entries per wave: < 64 left over + 4 x 64 of one group (+ one spare)
+#define AH_QCAP 319                       // queue entries per wave: < 64 left over + 4 x 64 of one group (one spare follows)
 #endif
 #ifndef AH_NCTX
 // tiles whose candidates may wait in the queue (<= 4); a two-block tile
@@ -116,7 +116,7 @@ struct TileCtx {
 #ifndef AH_HCAP
 #define AH_HCAP 48                        // hits buffered per wave (LDS) before one atomic reserves their room
 #endif
-#define AH_TW (2 * AH_TILE_BLOCKS + 2)    // {h, l} ring words of a tile (+ one word each side; one spare follows)
+#define AH_TW (2 * AH_TILE_BLOCKS + 2)    // {h, l} ring words of a tile (+ one word each side)
 #define AH_QW (AH_HW + 1)                 // queue entry: one block's candidate words + tag
 // N-bitmap words covering the tile's blocks and one block on each side
 #define AH_NBW ((AH_TILE_BLOCKS + 2 + 31) / 32 + 1)
@@ -328,7 +328,7 @@ __device__ __forceinline__ void ah_window_hit(const ScanArgs &a, const HitBuf &h
 template <bool kLdsOnly>
 __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
                                 const TileCtx &rctx, const uint32_t (*sQ)[AH_QW], uint32_t e0, uint32_t e1,
-                                const uint2 (*sW)[AH_TW + 1], const HitBuf &hb) {
+                                const uint2 (*sW)[AH_TW], const HitBuf &hb) {
     const uint32_t n = e1 - e0;  // wave-uniform
     const uint32_t lg = n <= 16u ? 2u : (n <= 32u ? 1u : 0u);
     const uint32_t lane = ah_lane();
@@ -393,7 +393,7 @@ __device__ void ah_verify_round(const ScanArgs &a, const DPat *sPat, uint32_t n_
 template <bool kLdsOnly>
 __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, uint32_t n_lds, const TileCtx *sCtx,
                                          const TileCtx &rctx,
-                                         uint32_t (*sQ)[AH_QW], uint32_t &qn, const uint2 (*sW)[AH_TW + 1],
+                                         uint32_t (*sQ)[AH_QW], uint32_t &qn, const uint2 (*sW)[AH_TW],
                                          const HitBuf &hb, bool drain) {
     ah_wave_sync();
     uint32_t e0 = 0;
@@ -424,7 +424,7 @@ __device__ __forceinline__ void ah_flush(const ScanArgs &a, const DPat *sPat, ui
 // and verify full rounds of queued candidates.
 template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds, TileCtx *sCtx,
-                                        TileCtx &rctx, uint32_t (*sQ)[AH_QW], uint2 (*sW)[AH_TW + 1],
+                                        TileCtx &rctx, uint32_t (*sQ)[AH_QW], uint2 (*sW)[AH_TW],
                                         const HitBuf &hb, const TileLoad &L, const SeqCursor &cur, uint32_t groups,
                                         uint32_t &qn, uint32_t &nctx) {
     const uint32_t lane = ah_lane();
@@ -450,11 +450,6 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
     // the tile's words for deferred verification: [0] the 32 positions
     // before the tile, then every lane's blocks in order, then the 32 after
     uint2 *W = sW[ci];
-#pragma unroll
-    for (int b = 0; b < AH_BPL; b++) {
-        W[1 + AH_NW * lane + 2 * b] = make_uint2(L.blk[b].x, L.blk[b].y);
-        W[2 + AH_NW * lane + 2 * b] = make_uint2(L.blk[b].z, L.blk[b].w);
-    }
     // the lane after's first words (lane 63: the block after the tile)
     uint32_t nxh = ah_from_next_lane(L.blk[0].x), nxl = ah_from_next_lane(L.blk[0].y);
     if (lane == 63) {
@@ -462,9 +457,16 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
         nxl = L.hal.y;
     }
     // the halo words without a branch: lane 0 the word before the tile, lane
-    // 63 the word after it, every other lane the spare word past the ring
-    W[lane == 0 ? 0 : (lane == 63 ? AH_TW - 1 : AH_TW)] =
+    // 63 the word after it; every other lane writes its own first word,
+    // which its block writes below then overwrite (one wave's LDS writes
+    // land in order)
+    W[lane == 0 ? 0 : (lane == 63 ? AH_TW - 1 : 1 + AH_NW * lane)] =
         lane == 0 ? make_uint2(L.hal.z, L.hal.w) : make_uint2(nxh, nxl);
+#pragma unroll
+    for (int b = 0; b < AH_BPL; b++) {
+        W[1 + AH_NW * lane + 2 * b] = make_uint2(L.blk[b].x, L.blk[b].y);
+        W[2 + AH_NW * lane + 2 * b] = make_uint2(L.blk[b].z, L.blk[b].w);
+    }
 #pragma unroll
     for (int blk = 0; blk < AH_BPL; blk++) {
         // the block's words and their neighbours
@@ -616,14 +618,14 @@ __device__ __forceinline__ void ah_tile(const ScanArgs &a, F &f, const DPat *sPa
 template <bool kLdsOnly, class F>
 __device__ __forceinline__ void ah_scan_body(const ScanArgs &a, F &f, const DPat *sPat, uint32_t n_lds,
                                              TileCtx (*sCtx_all)[AH_NCTX], uint32_t (*sQ_all)[AH_QCAP + 1][AH_QW],
-                                             uint2 (*sW_all)[AH_NCTX][AH_TW + 1],
+                                             uint2 (*sW_all)[AH_NCTX][AH_TW],
                                              uint32_t (*sH_all)[AH_HCAP][3], uint32_t *sHn_all) {
     // the wave index is uniform across the wave; saying so keeps the tile
     // walk, the cursor and the queue bookkeeping in scalar registers
     const uint32_t wv = ah_uni(threadIdx.x >> 6);
     TileCtx *sCtx = sCtx_all[wv];
     uint32_t(*sQ)[AH_QW] = sQ_all[wv];
-    uint2(*sW)[AH_TW + 1] = sW_all[wv];
+    uint2(*sW)[AH_TW] = sW_all[wv];
     const HitBuf hb{sH_all[wv], sHn_all + wv};
     if (ah_lane() == 0) *hb.n = 0u;
     ah_wave_sync();

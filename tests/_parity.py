@@ -72,8 +72,8 @@ def compare_extract(r, e):
 
 # scan kernels: the generic one and the specialised one in every variant
 # (blocks per lane, LDS hit buffer) the autotuner may pick
-KERNELS = {"generic": (False, None), "jit": (True, None), "jit-1x16": (True, (1, 16)),
-           "jit-2x48": (True, (2, 48)), "jit-2x16": (True, (2, 16))}
+KERNELS = {"generic": (False, None), "jit": (True, None), "jit-1x48": (True, (1, 48)), "jit-1x16": (True, (1, 16)),
+           "jit-2x16": (True, (2, 16))}
 
 
 def full_parity(store, ascii_buf, off, pairs, orient_mask, tm, ex=None, n_threads=None, jit=False, variant=None):
