@@ -204,7 +204,8 @@ struct AhJitSet {
 // patterns of a strand, so their shifted planes are shared), round-robin.
 // The group size s (0 = clamp only) minimises an estimate of vector
 // instructions per 4096-base tile: tests and shifts against candidates
-// verified (about 2.25 instructions each, measured).  In a set of many pairs
+// verified (3.5 instructions each, fitted on a 64-pair set: 2.25, 3.5, 5 and 8
+// gave 37.6, 37.3, 37.6 and 37.7 ms per scan).  In a set of many pairs
 // the shifted planes of each strand are formed once per block for all of
 // them (offsets within [-kSharedReach, kSharedReach + AH_WMAX)), so a
 // position costs its two tests only.
@@ -246,7 +247,7 @@ static FiltPlan plan_filter(const DPat &P, bool shared) {
         for (int j = L - 1; j >= 0; j--)
             if (!((P.clampmask >> j) & 1u) && pat_code(P, j) != 15u) near.push_back({j - shift, pat_code(P, j)});
     }
-    const double kVerify = 2.25, kTile = 4096.0;
+    const double kVerify = 3.5, kTile = 4096.0;
     double best_cost = 2.0 * W + kTile * p_clamp * kVerify + 6.0;
     for (int sz = 1; sz <= 4; sz++) {
         const int need = sz * (k + 1);
