@@ -109,8 +109,9 @@ struct TileCtx {
 #define AH_QCAP 319                       // queue entries per wave: < 64 left over + 4 x 64 of one group (one spare follows)
 #endif
 #ifndef AH_NCTX
-// tiles whose candidates may wait in the queue (<= 4); a two-block tile
-// holds enough candidates for full verification rounds on its own
+// tiles whose candidates may wait in the queue (<= 4); with two-block tiles
+// one (its context then stays in scalar registers; a second tile's ring
+// words and context would cost a workgroup per CU)
 #define AH_NCTX (AH_BPL == 1 ? 2 : 1)
 #endif
 #ifndef AH_HCAP
