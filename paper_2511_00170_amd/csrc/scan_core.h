@@ -203,10 +203,10 @@ __device__ __forceinline__ void tile_issue(const ScanArgs &a, const SeqCursor &c
 #pragma unroll
     for (int b = 0; b < AH_BPL; b++) {
         uint32_t own = AH_BPL * lane + b;
-        own = own < L.nb ? own : L.nb - 1;
+        own = min(own, L.nb - 1);  // one v_min: L.nb >= 1
         L.blk[b] = ah_ldg<uint4>(base + 16u * (own + 1));
     }
-    uint32_t o_hal = (AH_BPL * lane < L.nb ? AH_BPL * lane : L.nb - 1) + 1;
+    uint32_t o_hal = min((uint32_t)(AH_BPL * lane), L.nb - 1) + 1;
     if (lane == 0 && L.rel0 != 0) o_hal = 0;
     if (lane == 63 && L.rel0 + AH_TILE_BLOCKS < c.nblk) o_hal = AH_TILE_BLOCKS + 1;
     L.hal = ah_ldg<uint4>(base + 16u * o_hal);
